@@ -1,0 +1,166 @@
+"""Throughput benchmark of the D2Q9 two-phase LBE step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 4096 x 4096 periodic droplet (radius 1024, density ratio 100,
+beta = 0.1, kappa = 0.02, tau = 0.8), well-balanced scheme, populations in
+FP64 (the headline line) and in the shifted FP32 form (reported beside it).
+A step is one launch of the fused step kernel over the whole lattice; the
+populations stay in HBM for the whole timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BYTES_PER_UPDATE = {"fp64": 144, "fp32s": 72}   # 9 populations read + written
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ["lbm_kernels.hip", "lbm_kernels.h"]:
+        with open(os.path.join(ROOT, "paper_2012_11075_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, "step_droplet_4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    e = d.get(precision)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):
+    import torch
+    from paper_2012_11075_amd import lbm, tune
+    s = lbm.Solver.for_problem(prob, precision=precision)
+    s.set_tile(*tune.bench_tile(prob.nx, prob.ny, precision))
+    s.init(prob.rho(), scheme=scheme)
+    s.step(warmup, scheme)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps, scheme)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ob = s.observe(fields=(), raise_nonfinite=False)
+    tile = s.get_tile()
+    kps = s.lib.lbm_kernels_per_step(s.ctx)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    nodes = prob.nx * prob.ny
+    ms_step = ms / steps
+    mlups = nodes * steps / (ms / 1e3) / 1e6
+    bpu = BYTES_PER_UPDATE[precision]
+    per_launch = bpu * nodes
+    achieved = per_launch / (ms_step / kps / 1e3) / 1e9
+    traffic = measured_traffic(precision)
+    return {
+        "mlups": mlups,
+        "ms_per_step": ms_step,
+        "wall_s": wall,
+        "tile": list(tile),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_update": bpu},
+        "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
+    }
+
+
+def cpu_baseline(prob, budget_s=15.0):
+    """The FP64 oracle on the same lattice for a bounded number of steps."""
+    import oracle
+    oracle.build()
+    ph = prob.physics
+    p = oracle.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    f = oracle.init("well_balanced", p, prob.rho())
+    t0 = time.perf_counter()
+    f = oracle.step("well_balanced", p, f, 1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(30, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    f = oracle.step("well_balanced", p, f, k)
+    dt = time.perf_counter() - t0
+    nodes = prob.nx * prob.ny
+    return {"value": round(nodes * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": "%dx%d %s lattice, %d WB steps after one warm-up step, FP64, %d threads"
+                      % (prob.nx, prob.ny, prob.name, k, oracle.get_threads())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the step on a single device "
+              "(multi-GPU decomposition is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    from paper_2012_11075_amd import inputs as I
+    prob = I.DROPLET_4096
+    r64 = time_gpu(prob, "fp64", args.steps, args.warmup)
+    out = {
+        "metric": "MLUPS (million lattice-node updates per second), FP64 well-balanced step",
+        "value": round(r64["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "droplet_4096: 4096x4096 periodic D2Q9 lattice, droplet R=1024, "
+                               "rho_l=1, rho_v=0.01, beta=0.1, kappa=0.02, tau=0.8, "
+                               "well-balanced scheme",
+                   "nx": prob.nx, "ny": prob.ny, "scheme": "well_balanced",
+                   "tile": r64["tile"], "kernels_per_step": 1},
+        "roofline": r64["roofline"],
+        "state_after": r64["state_after"],
+    }
+    if not args.no_fp32:
+        r32 = time_gpu(prob, "fp32s", args.steps, args.warmup)
+        out["fp32_shifted"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
+                               "ms_per_step": round(r32["ms_per_step"], 5),
+                               "tile": r32["tile"], "roofline": r32["roofline"],
+                               "state_after": r32["state_after"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

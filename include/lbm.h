@@ -1,0 +1,157 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 two-phase lattice Boltzmann step.
+ *
+ * The operation is one time step of the lattice Boltzmann equation for a
+ * liquid-vapour fluid driven by a chemical potential, in the two forms of
+ * Z. Guo, "Well-balanced lattice Boltzmann equation for two-phase flows",
+ * arXiv:2012.11075:
+ *
+ *   LBM_STANDARD       Sec. II: Eq. (2) with the equilibrium of Eq. (3), the
+ *                      forcing term of Eq. (5) and the potential-form force
+ *                      F = grad(cs2 rho) - rho grad(mu) (Eq. 6);
+ *   LBM_WELL_BALANCED  Sec. III: Eq. (2) with the equilibrium of Eq. (24),
+ *                      the force F = -rho grad(mu) of Eq. (25) and the
+ *                      forcing term of Eq. (26).
+ *
+ * Both use rho and the half-force velocity of Eq. (4), the chemical potential
+ * mu = mu0(rho) - kappa lap(rho) with the double-well mu0 of Eqs. (36)-(37),
+ * isotropic central differences for grad and lap (Sec. II, the ICS of
+ * Eq. 19 and its 9-point Laplacian companion), BGK collision with relaxation
+ * time tau, and streaming f_i(x + c_i, t + 1) = f*_i(x, t) on a lattice that
+ * is periodic in x and y.  Lattice units: dx = dt = c = 1, cs2 = 1/3.
+ * Velocities are numbered as in the paper: c0 = (0,0), c1 = (1,0),
+ * c2 = (0,1), c3 = (-1,0), c4 = (0,-1), c5 = (1,1), c6 = (-1,1),
+ * c7 = (-1,-1), c8 = (1,-1).
+ *
+ * Memory and ownership
+ *   - The caller owns every host array and the device workspace.  The library
+ *     allocates no device memory; it owns only its host-side context structs
+ *     (and HIP graph objects), which the destroy calls free.
+ *   - Host field arrays are dense, row-major double[ny][nx] (element (x, y)
+ *     at index y*nx + x).  Population arrays are double[9][ny][nx].
+ *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *     void*; NULL is the default stream).  lbm_step and lbm_batch_run are
+ *     asynchronous; calls that return host data synchronise that stream.
+ *   - A context (or batch) is not thread-safe; distinct ones are independent.
+ *     Two contexts must not share workspace memory.
+ *
+ * Errors: every call returns an lbm_status; lbm_last_error() gives a message
+ * for the last failing call on that context (or, for a NULL context, on the
+ * calling thread).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* bad argument (sizes, tau <= 1/2, NULL, non-finite) */
+  LBM_ENOSPACE = -2,    /* workspace or arena too small */
+  LBM_EHIP = -3,        /* a HIP runtime call failed */
+  LBM_ENONFINITE = -4,  /* observe found NaN/Inf or rho <= 0 (state kept) */
+  LBM_ESTATE = -5,      /* call out of order (e.g. step before init) */
+  LBM_EBUSY = -6        /* no free batch slot */
+} lbm_status;
+
+typedef enum { LBM_STANDARD = 0, LBM_WELL_BALANCED = 1 } lbm_scheme;
+
+/* LBM_FP64: populations stored and updated in double precision.
+ * LBM_FP32_SHIFTED: populations stored as float g_i = f_i - s_i and updated
+ * in single precision, with s_i = feq_i(rho_ref, u = 0) of the scheme in use
+ * (rho_ref for i = 0 and 0 otherwise under WB; w_i rho_ref under the
+ * standard scheme); mass, kinetic energy and max|u| are accumulated in
+ * double precision. */
+typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
+
+typedef struct {
+  int32_t nx, ny;   /* lattice size, each >= 1 */
+  double tau;       /* BGK relaxation time (Eq. 2), > 1/2 */
+  double beta;      /* double-well height (Eq. 36), >= 0 */
+  double kappa;     /* gradient coefficient in mu = mu0 - kappa lap rho, >= 0 */
+  double rho_l;     /* saturation liquid density (Eq. 36) */
+  double rho_v;     /* saturation vapour density (Eq. 36) */
+  double rho0;      /* constant rho0 of the WB equilibrium (Eq. 24); the paper uses 0 */
+  double rho_ref;   /* reference density of the FP32 shift; ignored for FP64 */
+  int32_t precision;   /* lbm_precision */
+  int32_t shift_all;   /* FP32 only: 1 = shift every scheme by w_i rho_ref */
+} lbm_params;
+
+typedef struct {
+  int64_t step;           /* steps taken since lbm_init / lbm_set_populations */
+  double max_u;           /* max over nodes of |u| (Eq. 4 velocity) */
+  double mass;            /* sum over nodes of rho */
+  double kinetic_energy;  /* (1/2) sum rho |u|^2, the E(t) of Sec. IV.A */
+  int32_t nonfinite;      /* 1 if any rho or u is NaN/Inf, or rho <= 0 */
+} lbm_observation;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+/* ---------------------------------------------------------- single instance */
+
+/* Bytes of device workspace a context with these parameters needs (two
+ * population copies, a field staging area and reduction partials).  Returns
+ * 0 if the parameters are invalid. */
+size_t lbm_workspace_bytes(const lbm_params* params);
+
+/* Create a context over a caller-owned device workspace of `bytes` bytes
+ * (256-byte aligned).  `hip_stream` is the hipStream_t all work goes to.
+ * On success *out owns host state only; the workspace must outlive it. */
+lbm_status lbm_create(const lbm_params* params, void* dev_workspace, size_t bytes,
+                      void* hip_stream, lbm_ctx** out);
+
+/* Set f(0) = feq(rho, u) of `scheme` (Eq. 3 or Eq. 24) from host fields.
+ * ux and uy may both be NULL (u = 0).  Rejects non-finite values and
+ * rho <= 0 with LBM_EINVAL.  Resets the step counter.  Synchronous. */
+lbm_status lbm_init(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                    lbm_scheme scheme);
+
+/* Advance n >= 0 time steps of Eq. (2) with `scheme`, asynchronously on the
+ * context stream.  Changing the scheme keeps the populations (for FP32 only
+ * the storage shift is converted, an exact constant offset). */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n, lbm_scheme scheme);
+
+/* Fields of the current state, with the same device code the step uses:
+ * rho (Eq. 4), u (Eq. 4, half-force), mu (mu0 - kappa lap rho).  Any of the
+ * four host arrays may be NULL; `obs` may be NULL.  Synchronous.  Returns
+ * LBM_ENONFINITE (after filling the outputs) if the state holds NaN/Inf or a
+ * non-positive density. */
+lbm_status lbm_observe(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* mu,
+                       lbm_observation* obs);
+
+/* Copy the populations f_i (unshifted, double) to / from host
+ * double[9][ny][nx].  Used for checkpoints and tests.  Synchronous.
+ * lbm_set_populations makes the context initialised with `scheme` and sets
+ * the step counter to `step`. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
+lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme, int64_t step);
+
+/* Tile shape of the step kernel: block width in threads (a multiple of 64,
+ * 128..1024; the block computes width-4 output columns) and rows per block.
+ * Any valid shape gives bit-identical populations.  0 keeps the current
+ * value.  lbm_get_tile reports the shape in use. */
+lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t block_width, int32_t rows);
+lbm_status lbm_get_tile(const lbm_ctx* ctx, int32_t* block_width, int32_t* rows);
+
+/* Steps per captured HIP graph for lbm_step (0 or 1 = plain launches). */
+lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int32_t steps);
+
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+const char* lbm_status_string(lbm_status s);
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Number of kernel launches one lbm_step(ctx, 1, .) performs (for profiling). */
+int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,487 @@
+// lbm_api.cpp -- host side of the C ABI declared in include/lbm.h.
+//
+// Validation, workspace layout, the ping-pong state, the FP32 storage shift,
+// HIP-graph replay of step sequences and the fixed-order final reduction of
+// the observe pass.  All device work is in lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_kernels.h"
+
+using lbmk::Q;
+
+namespace {
+
+constexpr double W[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+constexpr size_t ALIGN = 256;
+constexpr int MIN_ROWS = 4;
+constexpr int MIN_BLOCK = 128;
+
+thread_local std::string g_thread_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// Layout of a context's workspace.
+struct Layout {
+  lbmk::Geometry g;
+  size_t elem;
+  size_t state_bytes;   // one population copy
+  size_t staging_bytes; // 4 dense double fields
+  size_t partial_count; // blocks of the smallest tiling
+  size_t off_a, off_b, off_staging, off_partials, total;
+};
+
+bool valid_params(const lbm_params* p, std::string* why) {
+  if (!p) return *why = "params is NULL", false;
+  if (p->nx < 1 || p->ny < 1) return *why = "nx and ny must be >= 1", false;
+  if ((long long)p->nx * p->ny > (1LL << 31)) return *why = "lattice larger than 2^31 nodes", false;
+  if (!is_finite(p->tau) || p->tau <= 0.5) return *why = "tau must be finite and > 1/2", false;
+  if (!is_finite(p->beta) || p->beta < 0) return *why = "beta must be finite and >= 0", false;
+  if (!is_finite(p->kappa) || p->kappa < 0) return *why = "kappa must be finite and >= 0", false;
+  if (!is_finite(p->rho_l) || !is_finite(p->rho_v) || !is_finite(p->rho0) || !is_finite(p->rho_ref))
+    return *why = "densities must be finite", false;
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED)
+    return *why = "unknown precision", false;
+  return true;
+}
+
+Layout make_layout(const lbm_params& p) {
+  Layout L{};
+  L.elem = p.precision == LBM_FP64 ? 8 : 4;
+  L.g.nx = p.nx;
+  L.g.ny = p.ny;
+  L.g.pitch = (int)align_up((size_t)p.nx, 32);
+  L.g.plane = (long long)align_up((size_t)L.g.pitch * p.ny, ALIGN / L.elem);
+  L.state_bytes = align_up((size_t)Q * L.g.plane * L.elem, ALIGN);
+  L.staging_bytes = align_up((size_t)4 * p.nx * p.ny * sizeof(double), ALIGN);
+  const size_t strips = (p.nx + (MIN_BLOCK - 4) - 1) / (MIN_BLOCK - 4);
+  const size_t chunks = (p.ny + MIN_ROWS - 1) / MIN_ROWS;
+  L.partial_count = strips * chunks;
+  L.off_a = 0;
+  L.off_b = L.off_a + L.state_bytes;
+  L.off_staging = L.off_b + L.state_bytes;
+  L.off_partials = L.off_staging + L.staging_bytes;
+  L.total = L.off_partials + align_up(L.partial_count * 4 * sizeof(double), ALIGN);
+  return L;
+}
+
+// Storage shift s_i of a scheme (zero for FP64).
+void shift_of(const lbm_params& p, int scheme, double* s) {
+  for (int i = 0; i < Q; ++i) s[i] = 0.0;
+  if (p.precision == LBM_FP64) return;
+  if (scheme == LBM_WELL_BALANCED && !p.shift_all) {
+    s[0] = p.rho_ref;
+  } else {
+    for (int i = 0; i < Q; ++i) s[i] = W[i] * p.rho_ref;
+  }
+}
+
+// Equilibrium at rest feq_i(rho, 0) of a scheme (Eq. 3 / Eq. 24).
+void feq_rest(const lbm_params& p, int scheme, double rho, double* f) {
+  for (int i = 0; i < Q; ++i) {
+    if (scheme == LBM_STANDARD)
+      f[i] = W[i] * rho;
+    else
+      f[i] = (i == 0) ? rho - (1.0 - W[0]) * p.rho0 : W[i] * p.rho0;
+  }
+}
+
+lbmk::Physics make_physics(const lbm_params& p, int scheme) {
+  lbmk::Physics ph{};
+  ph.omega = 1.0 / p.tau;
+  ph.fpre = 1.0 - 0.5 / p.tau;
+  ph.beta = p.beta;
+  ph.kappa = p.kappa;
+  ph.rho_l = p.rho_l;
+  ph.rho_v = p.rho_v;
+  ph.rho_ref = p.precision == LBM_FP64 ? 0.0 : p.rho_ref;
+  double s[Q], fr[Q];
+  shift_of(p, scheme, s);
+  feq_rest(p, scheme, ph.rho_ref, fr);
+  for (int i = 0; i < Q; ++i) ph.geq_c[i] = fr[i] - s[i];
+  return ph;
+}
+
+lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows) {
+  lbmk::Tiling t{};
+  t.block = block;
+  t.rows = std::max(MIN_ROWS, std::min(rows, g.ny));
+  t.strips = (g.nx + (block - 4) - 1) / (block - 4);
+  t.chunks = (g.ny + t.rows - 1) / t.rows;
+  return t;
+}
+
+// Default tile: 256-wide strips; rows chosen so that the grid holds a few
+// blocks per compute unit of a 256-CU device and chunks stay tall (the y-halo
+// costs 4 rows per chunk).
+lbmk::Tiling default_tiling(const lbmk::Geometry& g) {
+  const int block = 256;
+  const int strips = (g.nx + (block - 4) - 1) / (block - 4);
+  const long long target = 2048;
+  long long rows = ((long long)g.ny * strips + target - 1) / target;
+  rows = std::max<long long>(16, std::min<long long>(rows, 128));
+  return make_tiling(g, block, (int)rows);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params prm{};
+  Layout L{};
+  lbmk::Tiling tl{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;           // 0: state in buffer A, 1: in buffer B
+  bool initialised = false;
+  int scheme = LBM_WELL_BALANCED;  // scheme the storage shift currently follows
+  int64_t step = 0;
+  int graph_steps = 0;
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [scheme][cur]
+  std::string err;
+
+  void* buf(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
+  void* state() const { return buf(cur); }
+  double* staging() const { return (double*)(ws + L.off_staging); }
+  double* partials() const { return (double*)(ws + L.off_partials); }
+  int storage() const { return prm.precision == LBM_FP64 ? lbmk::FP64 : lbmk::FP32; }
+  long long nodes() const { return (long long)prm.nx * prm.ny; }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_thread_error = msg;
+  return s;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+  return fail(c, LBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                    \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+void drop_graphs(lbm_ctx* c) {
+  for (auto& row : c->graph)
+    for (auto& g : row)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+// Enqueue n plain step launches.
+lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
+  const lbmk::Physics ph = make_physics(c->prm, scheme);
+  for (int64_t k = 0; k < n; ++k) {
+    HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
+                                c->buf(1 - c->cur), s));
+    c->cur = 1 - c->cur;
+  }
+  return LBM_OK;
+}
+
+// Graph of graph_steps launches starting from the current buffer (even count:
+// the buffer parity is the same after a replay).
+lbm_status get_graph(lbm_ctx* c, int scheme, hipGraphExec_t* out) {
+  hipGraphExec_t& slot = c->graph[scheme][c->cur];
+  if (!slot) {
+    hipStream_t cs;
+    HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return hip_fail(c, e, "hipStreamBeginCapture");
+    }
+    const int cur0 = c->cur;
+    lbm_status st = launch_steps(c, c->graph_steps, scheme, cs);
+    c->cur = cur0;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st != LBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&slot, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      slot = nullptr;
+      return hip_fail(c, e, "hipGraphInstantiate");
+    }
+  }
+  *out = slot;
+  return LBM_OK;
+}
+
+lbm_status convert_shift(lbm_ctx* c, int to_scheme) {
+  if (c->prm.precision == LBM_FP64 || to_scheme == c->scheme) {
+    c->scheme = to_scheme;
+    return LBM_OK;
+  }
+  double so[Q], sn[Q], d[Q];
+  shift_of(c->prm, c->scheme, so);
+  shift_of(c->prm, to_scheme, sn);
+  bool same = true;
+  for (int i = 0; i < Q; ++i) {
+    d[i] = so[i] - sn[i];
+    same = same && d[i] == 0.0;
+  }
+  if (!same) HIPCHK(c, lbmk::launch_reshift(c->storage(), c->L.g, d, c->state(), c->stream));
+  c->scheme = to_scheme;
+  return LBM_OK;
+}
+
+bool valid_scheme(int s) { return s == LBM_STANDARD || s == LBM_WELL_BALANCED; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) return 0;
+  return make_layout(*p).total;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* ws, size_t bytes, void* stream, lbm_ctx** out) {
+  std::string why;
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_params(p, &why)) return fail(nullptr, LBM_EINVAL, why);
+  if (!ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+  if ((uintptr_t)ws % ALIGN) return fail(nullptr, LBM_EINVAL, "workspace not 256-byte aligned");
+  Layout L = make_layout(*p);
+  if (bytes < L.total)
+    return fail(nullptr, LBM_ENOSPACE,
+                "workspace too small: need " + std::to_string(L.total) + " bytes");
+  lbm_ctx* c = new lbm_ctx();
+  c->prm = *p;
+  c->L = L;
+  c->ws = (char*)ws;
+  c->stream = (hipStream_t)stream;
+  c->tl = default_tiling(L.g);
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                    lbm_scheme scheme) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!rho) return fail(c, LBM_EINVAL, "rho is NULL");
+  if ((ux == nullptr) != (uy == nullptr)) return fail(c, LBM_EINVAL, "give both ux and uy or neither");
+  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  const long long n = c->nodes();
+  for (long long k = 0; k < n; ++k) {
+    if (!is_finite(rho[k]) || !(rho[k] > 0.0))
+      return fail(c, LBM_EINVAL, "rho must be finite and > 0 (node " + std::to_string(k) + ")");
+    if (ux && (!is_finite(ux[k]) || !is_finite(uy[k])))
+      return fail(c, LBM_EINVAL, "u must be finite (node " + std::to_string(k) + ")");
+  }
+  double* st = c->staging();
+  const size_t fb = (size_t)n * sizeof(double);
+  HIPCHK(c, hipMemcpyAsync(st, rho, fb, hipMemcpyHostToDevice, c->stream));
+  if (ux) {
+    HIPCHK(c, hipMemcpyAsync(st + n, ux, fb, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(st + 2 * n, uy, fb, hipMemcpyHostToDevice, c->stream));
+  }
+  c->cur = 0;
+  c->scheme = scheme;
+  const lbmk::Physics ph = make_physics(c->prm, scheme);
+  HIPCHK(c, lbmk::launch_init(c->storage(), scheme, c->L.g, ph, st, ux ? st + n : nullptr,
+                              ux ? st + 2 * n : nullptr, c->state(), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = 0;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_step before lbm_init");
+  lbm_status st = convert_shift(c, scheme);
+  if (st != LBM_OK) return st;
+  int64_t left = n;
+  if (c->graph_steps >= 2) {
+    while (left >= c->graph_steps) {
+      hipGraphExec_t ge;
+      st = get_graph(c, scheme, &ge);
+      if (st != LBM_OK) return st;
+      HIPCHK(c, hipGraphLaunch(ge, c->stream));
+      left -= c->graph_steps;
+    }
+  }
+  st = launch_steps(c, left, scheme, c->stream);
+  if (st != LBM_OK) return st;
+  c->step += n;
+  return LBM_OK;
+}
+
+lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* mu,
+                       lbm_observation* obs) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_observe before lbm_init");
+  const long long n = c->nodes();
+  double* st = c->staging();
+  lbmk::ObserveOut o{rho ? st : nullptr, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
+                     mu ? st + 3 * n : nullptr, c->partials()};
+  const lbmk::Physics ph = make_physics(c->prm, c->scheme);
+  HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,
+                                 c->stream));
+  const size_t fb = (size_t)n * sizeof(double);
+  if (rho) HIPCHK(c, hipMemcpyAsync(rho, st, fb, hipMemcpyDeviceToHost, c->stream));
+  if (ux) HIPCHK(c, hipMemcpyAsync(ux, st + n, fb, hipMemcpyDeviceToHost, c->stream));
+  if (uy) HIPCHK(c, hipMemcpyAsync(uy, st + 2 * n, fb, hipMemcpyDeviceToHost, c->stream));
+  if (mu) HIPCHK(c, hipMemcpyAsync(mu, st + 3 * n, fb, hipMemcpyDeviceToHost, c->stream));
+  const int nb = c->tl.blocks();
+  std::vector<double> part((size_t)nb * 4);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->partials(), part.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // fixed-order finish: tiles in order, compensated sums
+  double umax = 0.0, bad = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0;
+  auto neumaier = [](double& s, double& comp, double v) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v))
+      comp += (s - t) + v;
+    else
+      comp += (v - t) + s;
+    s = t;
+  };
+  for (int b = 0; b < nb; ++b) {
+    umax = std::max(umax, part[4 * b]);
+    neumaier(ms, mc, part[4 * b + 1]);
+    neumaier(es, ec, part[4 * b + 2]);
+    bad = std::max(bad, part[4 * b + 3]);
+    if (!is_finite(part[4 * b + 1]) || !is_finite(part[4 * b + 2])) bad = 1.0;
+  }
+  if (obs) {
+    obs->step = c->step;
+    obs->max_u = umax;
+    obs->mass = ms + mc;
+    obs->kinetic_energy = es + ec;
+    obs->nonfinite = bad != 0.0;
+  }
+  if (bad != 0.0) return fail(c, LBM_ENONFINITE, "state holds NaN/Inf or rho <= 0");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+  if (!c->initialised) return fail(c, LBM_ESTATE, "no state yet");
+  const long long n = c->nodes();
+  double s[Q];
+  shift_of(c->prm, c->scheme, s);
+  for (int q0 = 0; q0 < Q; q0 += 4) {
+    const int m = std::min(4, Q - q0);
+    HIPCHK(c, lbmk::launch_unpack(c->storage(), c->L.g, s, c->state(), q0, m, c->staging(),
+                                  c->stream));
+    HIPCHK(c, hipMemcpyAsync(f + (size_t)q0 * n, c->staging(), (size_t)m * n * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, int64_t step) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  const long long n = c->nodes();
+  for (long long k = 0; k < (long long)Q * n; ++k)
+    if (!is_finite(f[k])) return fail(c, LBM_EINVAL, "populations must be finite");
+  double s[Q];
+  shift_of(c->prm, scheme, s);
+  c->cur = 0;
+  for (int q0 = 0; q0 < Q; q0 += 4) {
+    const int m = std::min(4, Q - q0);
+    HIPCHK(c, hipMemcpyAsync(c->staging(), f + (size_t)q0 * n, (size_t)m * n * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, lbmk::launch_pack(c->storage(), c->L.g, s, c->staging(), q0, m, c->state(),
+                                c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  c->scheme = scheme;
+  c->step = step;
+  c->initialised = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (block == 0) block = c->tl.block;
+  if (rows == 0) rows = c->tl.rows;
+  if (!lbmk::block_width_supported(block))
+    return fail(c, LBM_EINVAL, "unsupported block width " + std::to_string(block));
+  if (rows < MIN_ROWS) return fail(c, LBM_EINVAL, "rows must be >= 4");
+  lbmk::Tiling t = make_tiling(c->L.g, block, rows);
+  if ((size_t)t.blocks() > c->L.partial_count)
+    return fail(c, LBM_EINVAL, "tiling exceeds the reduction area");
+  drop_graphs(c);
+  c->tl = t;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_tile(const lbm_ctx* c, int32_t* block, int32_t* rows) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (block) *block = c->tl.block;
+  if (rows) *rows = c->tl.rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx* c, int32_t steps) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (steps < 0 || steps > 4096) return fail(c, LBM_EINVAL, "graph steps must be in [0, 4096]");
+  if (steps >= 2 && (steps & 1)) return fail(c, LBM_EINVAL, "graph steps must be even");
+  drop_graphs(c);
+  c->graph_steps = steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  drop_graphs(c);
+  delete c;
+  return LBM_OK;
+}
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOSPACE: return "workspace too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ENONFINITE: return "non-finite state";
+    case LBM_ESTATE: return "call out of order";
+    case LBM_EBUSY: return "no free slot";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+  return c ? c->err.c_str() : g_thread_error.c_str();
+}
+
+int32_t lbm_kernels_per_step(const lbm_ctx*) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// lbm_kernels.h -- internal interface between the host library (lbm_api.cpp)
+// and the gfx950 kernels (lbm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmk {
+
+constexpr int Q = 9;
+
+// Geometry of one lattice's population storage: 9 planes of `pitch * ny`
+// elements (x fastest), each plane starting `plane` elements after the last.
+struct Geometry {
+  int nx, ny, pitch;
+  long long plane;  // elements between consecutive planes
+};
+
+// Physical and storage constants of one lattice, in the step's arithmetic.
+struct Physics {
+  double omega;      // 1/tau
+  double fpre;       // 1 - 1/(2 tau)
+  double beta, kappa, rho_l, rho_v;
+  double rho_ref;    // storage shift reference (0 for FP64)
+  double geq_c[Q];   // feq_i(rho_ref, 0) - s_i: constant part of the shifted equilibrium
+};
+
+// Tiling of the marching step kernel.
+struct Tiling {
+  int block;   // threads per block (multiple of 64)
+  int rows;    // output rows per block
+  int strips;  // blocks across x: ceil(nx / (block - 4))
+  int chunks;  // blocks along y: ceil(ny / rows)
+  int blocks() const { return strips * chunks; }
+};
+
+// Outputs of an observe pass (all optional).
+struct ObserveOut {
+  double* rho;
+  double* ux;
+  double* uy;
+  double* mu;
+  double* partials;  // 4 doubles per block: max|u|, mass, E, nonfinite flag
+};
+
+enum Scheme { STANDARD = 0, WELL_BALANCED = 1 };
+enum Storage { FP64 = 0, FP32 = 1 };
+
+// One step: populations fin -> fout (ping-pong buffers).
+hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics& ph,
+                       const Tiling& t, const void* fin, void* fout, hipStream_t s);
+
+// Fields and per-block reduction partials of the state f.
+hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,
+                          const Tiling& t, const void* f, const ObserveOut& o, hipStream_t s);
+
+// f = feq(rho, u) - shift, from dense device fields (ux, uy may be null).
+hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics& ph,
+                       const double* rho, const double* ux, const double* uy, void* f,
+                       hipStream_t s);
+
+// Dense double planes [m][ny][nx] <-> storage planes q0 .. q0+m-1, removing
+// (to storage) or adding back (from storage) the per-plane shift s[9]
+// (a host array, or null for no shift).
+hipError_t launch_pack(int storage, const Geometry& g, const double* shift, const double* dense,
+                       int q0, int m, void* f, hipStream_t s);
+hipError_t launch_unpack(int storage, const Geometry& g, const double* shift, const void* f,
+                         int q0, int m, double* dense, hipStream_t s);
+
+// g_i += delta_i on every node (conversion of the FP32 storage shift).
+hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, void* f,
+                          hipStream_t s);
+
+// Largest block width the kernels are instantiated for, and a check.
+bool block_width_supported(int block);
+
+}  // namespace lbmk

@@ -1,0 +1,218 @@
+"""Python binding of liblbm.so (argument marshalling only).
+
+Every step of the computation runs in the HIP kernels behind the C ABI of
+include/lbm.h.  PyTorch provides the device workspace and the HIP stream.
+If the library has not been built, loading fails with an error: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "liblbm.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "lbm.h")
+
+STANDARD, WELL_BALANCED = 0, 1
+FP64, FP32_SHIFTED = 0, 1
+SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED}
+PRECISIONS = {"fp64": FP64, "fp32s": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOSPACE", -3: "LBM_EHIP",
+          -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EBUSY"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class NonFiniteState(LbmError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("rho_l", ctypes.c_double),
+                ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("shift_all", ctypes.c_int32)]
+
+
+class Observation(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("max_u", ctypes.c_double), ("mass", ctypes.c_double),
+                ("kinetic_energy", ctypes.c_double), ("nonfinite", ctypes.c_int32)]
+
+
+_lib = None
+_VP, _D = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+
+
+def header_functions() -> list:
+    """Names of the functions include/lbm.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def load():
+    """Load liblbm.so (after torch, so that both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblbm.so is not built (%s); run python -m paper_2012_11075_amd.build"
+                          % LIB_PATH)
+    import torch  # noqa: F401  (loads the HIP runtime liblbm.so links against)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, O = ctypes.POINTER(Params), ctypes.POINTER(Observation)
+    i32, i64, st = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    sig = {
+        "lbm_workspace_bytes": (ctypes.c_size_t, [P]),
+        "lbm_create": (st, [P, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+        "lbm_init": (st, [_VP, _D, _D, _D, st]),
+        "lbm_step": (st, [_VP, i64, st]),
+        "lbm_observe": (st, [_VP, _D, _D, _D, _D, O]),
+        "lbm_get_populations": (st, [_VP, _D]),
+        "lbm_set_populations": (st, [_VP, _D, st, i64]),
+        "lbm_set_tile": (st, [_VP, i32, i32]),
+        "lbm_get_tile": (st, [_VP, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "lbm_set_graph_steps": (st, [_VP, i32]),
+        "lbm_destroy": (st, [_VP]),
+        "lbm_status_string": (ctypes.c_char_p, [st]),
+        "lbm_last_error": (ctypes.c_char_p, [_VP]),
+        "lbm_kernels_per_step": (i32, [_VP]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _scheme(s) -> int:
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
+                rho_ref=None, shift_all=False) -> Params:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if rho_ref is None:
+        rho_ref = 0.5 * (rho_l + rho_v)
+    return Params(int(nx), int(ny), float(tau), float(beta), float(kappa), float(rho_l),
+                  float(rho_v), float(rho0), float(rho_ref), prec, int(bool(shift_all)))
+
+
+def stream_handle(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Solver:
+    """One periodic lattice on the current HIP device."""
+
+    def __init__(self, nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
+                 rho_ref=None, shift_all=False, stream=None):
+        import torch
+        self.lib = load()
+        self.params = make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0, precision,
+                                  rho_ref, shift_all)
+        self.nx, self.ny = int(nx), int(ny)
+        nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise LbmError(-1, "invalid parameters")
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        assert self.workspace.data_ptr() % 256 == 0
+        self.stream = stream
+        h = _VP()
+        self._check(self.lib.lbm_create(ctypes.byref(self.params), self.workspace.data_ptr(),
+                                        nbytes, stream_handle(stream), ctypes.byref(h)), None)
+        self.ctx = h
+
+    @classmethod
+    def for_problem(cls, problem, precision="fp64", **kw):
+        ph = problem.physics
+        return cls(problem.nx, problem.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                   precision=precision, **kw)
+
+    def _check(self, status, ctx=-1):
+        if status != 0:
+            c = self.ctx if ctx == -1 else ctx
+            msg = self.lib.lbm_last_error(c).decode()
+            if status == -4:
+                raise NonFiniteState(status, msg)
+            raise LbmError(status, msg)
+
+    def init(self, rho, ux=None, uy=None, scheme="well_balanced"):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        assert rho.shape == (self.ny, self.nx)
+        if ux is not None:
+            ux = np.ascontiguousarray(np.broadcast_to(ux, rho.shape), dtype=np.float64)
+            uy = np.ascontiguousarray(np.broadcast_to(uy, rho.shape), dtype=np.float64)
+        self._check(self.lib.lbm_init(self.ctx, _dptr(rho), _dptr(ux), _dptr(uy), _scheme(scheme)))
+        return self
+
+    def step(self, n=1, scheme="well_balanced"):
+        self._check(self.lib.lbm_step(self.ctx, int(n), _scheme(scheme)))
+        return self
+
+    def observe(self, fields=("rho", "ux", "uy", "mu"), raise_nonfinite=True) -> dict:
+        out = {k: np.empty((self.ny, self.nx)) for k in fields}
+        obs = Observation()
+        st = self.lib.lbm_observe(self.ctx, _dptr(out.get("rho")), _dptr(out.get("ux")),
+                                  _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(obs))
+        if st != -4 or raise_nonfinite:
+            self._check(st)
+        out.update(step=obs.step, max_u=obs.max_u, mass=obs.mass,
+                   kinetic_energy=obs.kinetic_energy, nonfinite=bool(obs.nonfinite))
+        return out
+
+    def get_populations(self) -> np.ndarray:
+        """Populations as (9, ny, nx) doubles (unshifted)."""
+        f = np.empty((9, self.ny, self.nx))
+        self._check(self.lib.lbm_get_populations(self.ctx, _dptr(f)))
+        return f
+
+    def set_populations(self, f: np.ndarray, scheme="well_balanced", step=0):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self._check(self.lib.lbm_set_populations(self.ctx, _dptr(f), _scheme(scheme), int(step)))
+        return self
+
+    def set_tile(self, block=0, rows=0):
+        self._check(self.lib.lbm_set_tile(self.ctx, int(block), int(rows)))
+        return self
+
+    def get_tile(self):
+        b, r = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.lbm_get_tile(self.ctx, ctypes.byref(b), ctypes.byref(r)))
+        return b.value, r.value
+
+    def set_graph_steps(self, k):
+        self._check(self.lib.lbm_set_graph_steps(self.ctx, int(k)))
+        return self
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

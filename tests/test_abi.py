@@ -1,0 +1,68 @@
+"""The C-ABI library loads on any host and exports what include/lbm.h
+declares; argument checks that touch no device memory behave as documented.
+No compute calls: these run without a GPU."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2012_11075_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_2012_11075_amd import build
+        build.build()
+    return lbm.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = lbm.header_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_workspace_bytes_rejects_bad_params(lib):
+    P = lbm.make_params
+    for bad in [P(0, 4, 1.0, 0.1, 0.02, 1, 0.1), P(4, -1, 1.0, 0.1, 0.02, 1, 0.1),
+                P(4, 4, 0.5, 0.1, 0.02, 1, 0.1), P(4, 4, float("nan"), 0.1, 0.02, 1, 0.1),
+                P(4, 4, 1.0, -0.1, 0.02, 1, 0.1), P(4, 4, 1.0, 0.1, -1.0, 1, 0.1),
+                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision=7)]:
+        assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_workspace_bytes_layout(lib):
+    # two population copies + 4 double fields of staging + reduction partials
+    for prec, elem in [("fp64", 8), ("fp32s", 4)]:
+        p = lbm.make_params(4096, 4096, 0.8, 0.1, 0.02, 1.0, 0.01, precision=prec)
+        n = lib.lbm_workspace_bytes(ctypes.byref(p))
+        assert n >= 2 * 9 * 4096 * 4096 * elem + 4 * 4096 * 4096 * 8
+        assert n < 1.01 * (2 * 9 * 4096 * 4096 * elem + 4 * 4096 * 4096 * 8)
+
+
+def test_create_argument_errors(lib):
+    p = lbm.make_params(8, 8, 1.0, 0.1, 0.02, 1.0, 0.1)
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(p), None, 1 << 20, None, ctypes.byref(h)) == -1
+    assert b"workspace" in lib.lbm_last_error(None)
+    assert lib.lbm_create(ctypes.byref(p), 0x1001, 1 << 20, None, ctypes.byref(h)) == -1
+    assert b"aligned" in lib.lbm_last_error(None)
+    assert lib.lbm_create(ctypes.byref(p), 0x100000, 16, None, ctypes.byref(h)) == -2
+    assert lib.lbm_create(None, 0x100000, 1 << 20, None, ctypes.byref(h)) == -1
+    assert lib.lbm_create(ctypes.byref(p), 0x100000, 1 << 20, None, None) == -1
+    assert not h.value
+
+
+def test_null_context_calls(lib):
+    assert lib.lbm_step(None, 1, 1) == -1
+    assert lib.lbm_observe(None, None, None, None, None, None) == -1
+    assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_status_string(-4) == b"non-finite state"
