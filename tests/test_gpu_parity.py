@@ -55,7 +55,7 @@ def compare(orc, L, prob, scheme, steps, tile=None):
     rho0 = prob.rho()
     fo = orc.step(scheme, p, orc.init(scheme, p, rho0), steps)
     ro, uxo, uyo, muo = orc.fields(scheme, p, fo)
-    assert np.isfinite(fo).all(), "oracle state not finite: pick fewer steps"
+    assert np.isfinite(fo).all() and ro.min() > 0, "oracle state diverged: pick fewer steps"
     s = run_gpu(L, prob, scheme, steps, tile=tile, rho=rho0)
     fg = to_oracle(s.get_populations())
     ob = s.observe()
@@ -70,15 +70,15 @@ def compare(orc, L, prob, scheme, steps, tile=None):
 
 CASES = [
     ("flat_200x4", "well_balanced", 1000),
-    ("flat_200x4", "standard", 50),
+    ("flat_200x4", "standard", 30),
     ("droplet_256", "well_balanced", 1000),
-    ("droplet_256", "standard", 50),
+    ("droplet_256", "standard", 30),
     ("paper_flat_21x101", "well_balanced", 1000),
     ("paper_flat_21x101", "standard", 1000),
     ("paper_droplet_100", "well_balanced", 1000),
     ("paper_droplet_100", "standard", 1000),
-    ("droplet_512_ratio100", "well_balanced", 50),
-    ("droplet_512_ratio100", "standard", 10),
+    ("droplet_512_ratio100", "well_balanced", 25),
+    ("droplet_512_ratio100", "standard", 8),
 ]
 
 
