@@ -132,12 +132,14 @@ lbm_status lbm_observe(lbm_ctx* ctx, double* rho, double* ux, double* uy, double
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme, int64_t step);
 
-/* Tile shape of the step kernel: block width in threads (a multiple of 64,
- * 128..1024; the block computes width-4 output columns) and rows per block.
- * Any valid shape gives bit-identical populations.  0 keeps the current
- * value.  lbm_get_tile reports the shape in use. */
-lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t block_width, int32_t rows);
-lbm_status lbm_get_tile(const lbm_ctx* ctx, int32_t* block_width, int32_t* rows);
+/* Tile shape of the step kernel: block width in threads (128, 192, 256, 320
+ * or 512; the block computes block_width output columns), output rows
+ * per block (>= 4) and prefetch depth (rows of populations each thread keeps
+ * in flight, 1..3).  Any valid shape gives bit-identical populations.  0
+ * keeps the current value.  lbm_get_tile reports the shape in use (any
+ * output pointer may be NULL). */
+lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t block_width, int32_t rows, int32_t depth);
+lbm_status lbm_get_tile(const lbm_ctx* ctx, int32_t* block_width, int32_t* rows, int32_t* depth);
 
 /* Steps per captured HIP graph for lbm_step (0 or 1 = plain launches). */
 lbm_status lbm_set_graph_steps(lbm_ctx* ctx, int32_t steps);

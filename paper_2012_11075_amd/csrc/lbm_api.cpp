@@ -64,7 +64,7 @@ Layout make_layout(const lbm_params& p) {
   L.g.plane = (long long)align_up((size_t)L.g.pitch * p.ny, ALIGN / L.elem);
   L.state_bytes = align_up((size_t)Q * L.g.plane * L.elem, ALIGN);
   L.staging_bytes = align_up((size_t)4 * p.nx * p.ny * sizeof(double), ALIGN);
-  const size_t strips = (p.nx + (MIN_BLOCK - 4) - 1) / (MIN_BLOCK - 4);
+  const size_t strips = (p.nx + MIN_BLOCK - 1) / MIN_BLOCK;
   const size_t chunks = (p.ny + MIN_ROWS - 1) / MIN_ROWS;
   L.partial_count = strips * chunks;
   L.off_a = 0;
@@ -112,11 +112,12 @@ lbmk::Physics make_physics(const lbm_params& p, int scheme) {
   return ph;
 }
 
-lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows) {
+lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows, int depth) {
   lbmk::Tiling t{};
   t.block = block;
+  t.depth = depth;
   t.rows = std::max(MIN_ROWS, std::min(rows, g.ny));
-  t.strips = (g.nx + (block - 4) - 1) / (block - 4);
+  t.strips = (g.nx + block - 1) / block;
   t.chunks = (g.ny + t.rows - 1) / t.rows;
   return t;
 }
@@ -126,11 +127,11 @@ lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows) {
 // costs 4 rows per chunk).
 lbmk::Tiling default_tiling(const lbmk::Geometry& g) {
   const int block = 256;
-  const int strips = (g.nx + (block - 4) - 1) / (block - 4);
+  const int strips = (g.nx + block - 1) / block;
   const long long target = 2048;
   long long rows = ((long long)g.ny * strips + target - 1) / target;
   rows = std::max<long long>(16, std::min<long long>(rows, 128));
-  return make_tiling(g, block, (int)rows);
+  return make_tiling(g, block, (int)rows, 2);
 }
 
 }  // namespace
@@ -427,14 +428,16 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, i
   return LBM_OK;
 }
 
-lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows) {
+lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (block == 0) block = c->tl.block;
   if (rows == 0) rows = c->tl.rows;
+  if (depth == 0) depth = c->tl.depth;
+  if (depth < 1 || depth > 3) return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3");
   if (!lbmk::block_width_supported(block))
     return fail(c, LBM_EINVAL, "unsupported block width " + std::to_string(block));
   if (rows < MIN_ROWS) return fail(c, LBM_EINVAL, "rows must be >= 4");
-  lbmk::Tiling t = make_tiling(c->L.g, block, rows);
+  lbmk::Tiling t = make_tiling(c->L.g, block, rows, depth);
   if ((size_t)t.blocks() > c->L.partial_count)
     return fail(c, LBM_EINVAL, "tiling exceeds the reduction area");
   drop_graphs(c);
@@ -442,10 +445,11 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows) {
   return LBM_OK;
 }
 
-lbm_status lbm_get_tile(const lbm_ctx* c, int32_t* block, int32_t* rows) {
+lbm_status lbm_get_tile(const lbm_ctx* c, int32_t* block, int32_t* rows, int32_t* depth) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (block) *block = c->tl.block;
   if (rows) *rows = c->tl.rows;
+  if (depth) *depth = c->tl.depth;
   return LBM_OK;
 }
 

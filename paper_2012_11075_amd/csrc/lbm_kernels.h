@@ -31,6 +31,7 @@ struct Tiling {
   int rows;    // output rows per block
   int strips;  // blocks across x: ceil(nx / (block - 4))
   int chunks;  // blocks along y: ceil(ny / rows)
+  int depth;   // rows of populations in flight per thread (1..3)
   int blocks() const { return strips * chunks; }
 };
 

@@ -13,15 +13,17 @@
 //                      f_i(x + c_i, t+1) = f*_i(x, t), periodic.
 //
 // Design (one HBM pass per step).  Populations live in 9 structure-of-arrays
-// planes, x fastest.  A block of BW threads owns a strip of BW-4 output
-// columns and marches down a chunk of rows.  Each thread loads the 9
-// populations of one column per row (coalesced along x), keeps the last three
-// rows in registers, and publishes rho of the row to a 5-row LDS ring; mu of
+// planes, x fastest.  A block of BW threads owns an aligned strip of BW
+// output columns and marches along a chunk of rows.  Each thread loads the 9
+// populations of one column per row (coalesced along x) one row ahead of use,
+// keeps the last three rows in registers, and publishes rho of the row to a 5-row LDS ring; mu of
 // the previous row goes to a 3-row LDS ring.  The 2-column x-halo of rho is
-// recomputed by the edge threads (neighbouring strips overlap by 4 columns),
+// recomputed from populations that 36 lanes of the first wave load (one each),
 // the 2-row y-halo by reading two extra rows at each end of the chunk, so no
-// block ever waits for another.  Collision and streaming are fused: the
-// post-collision populations are pushed to x + c_i of the other buffer.
+// block ever waits for another.  Collision and streaming are fused in pull
+// form: the buffers hold post-collision populations; a step reads f_i of node
+// x from x - c_i of one buffer (misaligned loads are cheap) and writes the
+// new post-collision values of x, aligned and non-temporal, to the other.
 // rho, mu and u of every node come from the same device code in the step and
 // in the observe pass.
 #include <hip/hip_runtime.h>
@@ -117,14 +119,19 @@ __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R 
   }
 }
 
-// Marching step / observe kernel.  T: storage and arithmetic type.
-template <typename T, int SCHEME, int BW, bool OBSERVE>
+// Marching step / observe kernel.  T: storage and arithmetic type; BW:
+// threads per block = output columns per block; D: rows of populations in
+// flight ahead of the row being summed.
+template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
 __global__ void __launch_bounds__(BW)
     march(Geometry g, Physics phys, Tiling tl, const T* __restrict__ fin, T* __restrict__ fout,
           ObserveOut obs) {
   using R = T;
-  __shared__ R rs[5][BW];  // rho ring: rows y-2 .. y+2 of the output row y
-  __shared__ R ms[3][BW];  // mu ring: rows y-1 .. y+1
+  // LDS column j of the rho ring holds lattice column x0 - 2 + j, column m of
+  // the mu ring lattice column x0 - 1 + m (periodic).
+  __shared__ R rs[5][BW + 4];  // rho: rows y-2 .. y+2 of the output row y
+  __shared__ R ms[3][BW + 2];  // mu: rows y-1 .. y+1
+  __shared__ R fl[2][Q][BW];   // populations of rows y and y+1, each thread its own column
   const PhysR<R> p = to_r<R>(phys);
   const int t = threadIdx.x;
 
@@ -137,93 +144,152 @@ __global__ void __launch_bounds__(BW)
   const int chunk = tile / tl.strips;
   const int strip = tile - chunk * tl.strips;
 
-  const int x0 = strip * (BW - 4);
-  int xc = (x0 - 2 + t) % g.nx;
-  if (xc < 0) xc += g.nx;
-  const bool outc = (t >= 2) && (t < BW - 2) && (x0 + t - 2 < g.nx);
-  const int x = x0 + t - 2;
+  // Strips are BW columns wide and start on a multiple of BW, so loads and
+  // stores of a row are aligned to whole cache lines.
+  const int x0 = strip * BW;
+  const int x = x0 + t;
+  const bool outc = x < g.nx;
+  const int xc = x % g.nx;
   const int y0 = chunk * tl.rows;
   const int H = min(tl.rows, g.ny - y0);
-  const int K = H + 4;  // row index k <-> lattice row y0 - 2 + k
-
-  auto row_of = [&](int k) {
-    int y = (y0 - 2 + k) % g.ny;
+  const int K = H + 4;
+  // Odd chunks march upward, so that vertically adjacent blocks read the two
+  // halo rows they share at about the same time (L2 hits instead of a second
+  // HBM fetch).  Row index k is lattice row y0 - 2 + k (down) or
+  // y0 + H + 1 - k (up); the stencils are symmetric in y, and the y
+  // gradients take the sign of the direction, so results are bit-identical.
+  const bool up = (chunk & 1) != 0;
+  auto wrapy = [&](int y) {
+    y %= g.ny;
     return y < 0 ? y + g.ny : y;
   };
+  auto row_of = [&](int k) { return wrapy(up ? y0 + H + 1 - k : y0 - 2 + k); };
+
+  // Pull streaming: the buffers hold post-collision populations, so f_i at
+  // (x, y) is read from (x - c_ix, y - c_iy) of the previous step.
+  const int xw = (xc == 0) ? g.nx - 1 : xc - 1;
+  const int xe = (xc + 1 == g.nx) ? 0 : xc + 1;
   auto load_row = [&](int k, R(&dst)[Q]) {
-    const long long off = (long long)row_of(k) * g.pitch + xc;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) dst[i] = fin[(long long)i * g.plane + off];
+    const int y = row_of(k);
+    const int yu = (y == 0) ? g.ny - 1 : y - 1;
+    const int yd = (y + 1 == g.ny) ? 0 : y + 1;
+    const long long P = g.plane;
+    const long long r0 = (long long)y * g.pitch, ru = (long long)yu * g.pitch,
+                    rd = (long long)yd * g.pitch;
+    dst[0] = fin[r0 + xc];
+    dst[1] = fin[P + r0 + xw];
+    dst[2] = fin[2 * P + ru + xc];
+    dst[3] = fin[3 * P + r0 + xe];
+    dst[4] = fin[4 * P + rd + xc];
+    dst[5] = fin[5 * P + ru + xw];
+    dst[6] = fin[6 * P + ru + xe];
+    dst[7] = fin[7 * P + rd + xe];
+    dst[8] = fin[8 * P + rd + xw];
+  };
+
+  // The four halo columns x0-2, x0-1, x0+BW, x0+BW+1 need rho only.  Lane
+  // L < 36 of wave 0 loads one population (column L/9, velocity L%9) per row;
+  // the nine lanes of a column are gathered by shuffles and summed in the
+  // same order as an interior column, so a node's rho is bit-identical in
+  // every block that computes it.
+  const bool hl = t < 4 * Q;
+  const int hcol = t / Q, hq = t - Q * (t / Q);
+  const int hslot = hcol < 2 ? hcol : BW + hcol;  // rho-ring column of the halo
+  int hsx = 0, hcy = 0;
+  long long hplane = 0;
+  if (hl) {
+    const int cxq[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cyq[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    int hc = hcol < 2 ? x0 - 2 + hcol : x0 + BW + hcol - 2;
+    hc = ((hc % g.nx) + g.nx) % g.nx;
+    hsx = hc - cxq[hq];
+    hsx = hsx < 0 ? hsx + g.nx : (hsx >= g.nx ? hsx - g.nx : hsx);
+    hcy = cyq[hq];
+    hplane = (long long)hq * g.plane;
+  }
+  auto load_halo = [&](int k, R& dst) {
+    if (hl) dst = fin[hplane + (long long)wrapy(row_of(k) - hcy) * g.pitch + hsx];
   };
 
   double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
 
-  R fo[Q], fm[Q], fc[Q], fn[Q];
+  // One row step: prefetch row k+D into `nxt`; publish rho of row k (`cur`,
+  // which then parks in LDS for two rows); mu of row k-1; update the node of
+  // row k-2.
+  auto stage = [&](int k, R(&nxt)[Q], R(&cur)[Q], R& hnxt, R& hcur) {
+    load_row(k + D, nxt);  // rows past the chunk are valid (periodic) and unused
+    load_halo(k + D, hnxt);
+    const int sk = k % 5;
+    rs[sk][t + 2] = p.rho_ref + sum9(cur);
+    if (t < 64) {
+      const int base = (hl ? hcol : 0) * Q;
+      R v[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fo[i] = fm[i] = fn[i] = (R)0;
-  load_row(0, fc);
-
-  for (int k = 0; k < K; ++k) {
-    if (k + 1 < K) load_row(k + 1, fn);
-    rs[k % 5][t] = p.rho_ref + sum9(fc);
-    __syncthreads();
-    if (k >= 2 && t >= 1 && t < BW - 1) {
-      // mu at row index k-1: mu0(rho) - kappa lap(rho), 9-point Laplacian
-      const int a = (k - 2) % 5, c0 = (k - 1) % 5, d = k % 5;
-      const R r0 = rs[c0][t];
-      const R ax = (rs[c0][t + 1] + rs[c0][t - 1]) + (rs[a][t] + rs[d][t]);
-      const R dg = (rs[a][t + 1] + rs[a][t - 1]) + (rs[d][t + 1] + rs[d][t - 1]);
-      const R lap = ((R)4 * ax + dg - (R)20 * r0) * ((R)1 / (R)6);
-      ms[(k - 1) % 3][t] = mu0(r0, p) - p.kappa * lap;
+      for (int i = 0; i < Q; ++i) v[i] = __shfl(hcur, base + i);
+      if (hl && hq == 0) rs[sk][hslot] = p.rho_ref + sum9(v);
+    }
+    R out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      out[i] = fl[k & 1][i][t];  // row k-2 (garbage for k < 2, unused)
+      fl[k & 1][i][t] = cur[i];
     }
     __syncthreads();
-    if (k >= 4 && outc) {
+    if (k >= 2) {
+      // mu at row index k-1: mu0(rho) - kappa lap(rho), 9-point Laplacian, at
+      // ring column m (rho-ring columns m .. m+2)
+      const int a = (k - 2) % 5, c0 = (k - 1) % 5, d = sk, mk = (k - 1) % 3;
+      auto mu_at = [&](int m) {
+        const R r0 = rs[c0][m + 1];
+        const R ax = (rs[c0][m + 2] + rs[c0][m]) + (rs[a][m + 1] + rs[d][m + 1]);
+        const R dg = (rs[a][m + 2] + rs[a][m]) + (rs[d][m + 2] + rs[d][m]);
+        const R lap = ((R)4 * ax + dg - (R)20 * r0) * ((R)1 / (R)6);
+        ms[mk][m] = mu0(r0, p) - p.kappa * lap;
+      };
+      mu_at(t + 1);
+      if (t == 0) mu_at(0);
+      if (t == 1) mu_at(BW + 1);
+    }
+    __syncthreads();
+    if (k >= 4 && k < K && outc) {
       const int sM = (k - 3) % 5, s0 = (k - 2) % 5, sP = (k - 1) % 5;
       const int mM = (k - 3) % 3, m0 = (k - 2) % 3, mP = (k - 1) % 3;
       const R third = (R)1 / (R)3, twelfth = (R)1 / (R)12;
-      const R rho = rs[s0][t];
-      const R grx = (rs[s0][t + 1] - rs[s0][t - 1]) * third +
-                    ((rs[sP][t + 1] - rs[sP][t - 1]) + (rs[sM][t + 1] - rs[sM][t - 1])) * twelfth;
-      const R gry = (rs[sP][t] - rs[sM][t]) * third +
-                    ((rs[sP][t + 1] + rs[sP][t - 1]) - (rs[sM][t + 1] + rs[sM][t - 1])) * twelfth;
-      const R gmx = (ms[m0][t + 1] - ms[m0][t - 1]) * third +
-                    ((ms[mP][t + 1] - ms[mP][t - 1]) + (ms[mM][t + 1] - ms[mM][t - 1])) * twelfth;
-      const R gmy = (ms[mP][t] - ms[mM][t]) * third +
-                    ((ms[mP][t + 1] + ms[mP][t - 1]) - (ms[mM][t + 1] + ms[mM][t - 1])) * twelfth;
+      const R rho = rs[s0][t + 2];
+      const R grx = (rs[s0][t + 3] - rs[s0][t + 1]) * third +
+                    ((rs[sP][t + 3] - rs[sP][t + 1]) + (rs[sM][t + 3] - rs[sM][t + 1])) * twelfth;
+      R gry = (rs[sP][t + 2] - rs[sM][t + 2]) * third +
+              ((rs[sP][t + 3] + rs[sP][t + 1]) - (rs[sM][t + 3] + rs[sM][t + 1])) * twelfth;
+      const R gmx = (ms[m0][t + 2] - ms[m0][t]) * third +
+                    ((ms[mP][t + 2] - ms[mP][t]) + (ms[mM][t + 2] - ms[mM][t])) * twelfth;
+      R gmy = (ms[mP][t + 1] - ms[mM][t + 1]) * third +
+              ((ms[mP][t + 2] + ms[mP][t]) - (ms[mM][t + 2] + ms[mM][t])) * twelfth;
+      if (up) {
+        gry = -gry;
+        gmy = -gmy;
+      }
       R Fx = -rho * gmx, Fy = -rho * gmy;
       if (SCHEME == STANDARD) {
         Fx += grx * third;
         Fy += gry * third;
       }
       R ux, uy;
-      velocity(fo, rho, Fx, Fy, ux, uy);
-      const int y = y0 + k - 4;
+      velocity(out, rho, Fx, Fy, ux, uy);
+      const int y = row_of(k - 2);
       if (!OBSERVE) {
-        const R drho = sum9(fo);
-        collide<R, SCHEME>(fo, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
-        const int xe = (x + 1 == g.nx) ? 0 : x + 1;
-        const int xw = (x == 0) ? g.nx - 1 : x - 1;
-        const int yn = (y + 1 == g.ny) ? 0 : y + 1;
-        const int ys = (y == 0) ? g.ny - 1 : y - 1;
-        const long long P = g.plane;
-        const long long ry = (long long)y * g.pitch, rn = (long long)yn * g.pitch,
-                        rsy = (long long)ys * g.pitch;
-        fout[ry + x] = fo[0];
-        fout[P + ry + xe] = fo[1];
-        fout[2 * P + rn + x] = fo[2];
-        fout[3 * P + ry + xw] = fo[3];
-        fout[4 * P + rsy + x] = fo[4];
-        fout[5 * P + rn + xe] = fo[5];
-        fout[6 * P + rn + xw] = fo[6];
-        fout[7 * P + rsy + xw] = fo[7];
-        fout[8 * P + rsy + xe] = fo[8];
+        const R drho = sum9(out);
+        collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
+        // post-collision populations stay at their node (aligned, streaming stores)
+        T* dst = fout + (long long)y * g.pitch + x;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(out[i], dst + (long long)i * g.plane);
       } else {
         const long long o = (long long)y * g.nx + x;
         const double drho = (double)rho, dux = (double)ux, duy = (double)uy;
         if (obs.rho) obs.rho[o] = drho;
         if (obs.ux) obs.ux[o] = dux;
         if (obs.uy) obs.uy[o] = duy;
-        if (obs.mu) obs.mu[o] = (double)ms[m0][t];
+        if (obs.mu) obs.mu[o] = (double)ms[m0][t + 1];
         const double u2 = dux * dux + duy * duy;
         const double um = sqrt(u2);
         if (!(isfinite(drho) && drho > 0.0 && isfinite(um))) bad = 1.0;
@@ -232,11 +298,39 @@ __global__ void __launch_bounds__(BW)
         ekin += 0.5 * drho * u2;
       }
     }
+  };
+
+  // Row r lives in register set r % (D+1).  The loop is unrolled by D+1 and
+  // is straight-line (the trip count is rounded up; the extra stages store
+  // nothing), so no set is copied and every prefetch stays in flight until
+  // its row is summed.
+  R s0[Q], s1[Q], s2[Q], s3[Q];
+  R h0 = (R)0, h1 = (R)0, h2 = (R)0, h3 = (R)0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      fo[i] = fm[i];
-      fm[i] = fc[i];
-      fc[i] = fn[i];
+  for (int i = 0; i < Q; ++i) s0[i] = s1[i] = s2[i] = s3[i] = (R)0;
+  load_row(0, s0);
+  load_halo(0, h0);
+  if (D >= 2) {
+    load_row(1, s1);
+    load_halo(1, h1);
+  }
+  if (D >= 3) {
+    load_row(2, s2);
+    load_halo(2, h2);
+  }
+  for (int k = 0; k < K; k += D + 1) {
+    if (D == 1) {
+      stage(k, s1, s0, h1, h0);
+      stage(k + 1, s0, s1, h0, h1);
+    } else if (D == 2) {
+      stage(k, s2, s0, h2, h0);
+      stage(k + 1, s0, s1, h0, h1);
+      stage(k + 2, s1, s2, h1, h2);
+    } else {
+      stage(k, s3, s0, h3, h0);
+      stage(k + 1, s0, s1, h0, h1);
+      stage(k + 2, s1, s2, h1, h2);
+      stage(k + 3, s2, s3, h2, h3);
     }
   }
 
@@ -275,6 +369,17 @@ __global__ void __launch_bounds__(BW)
   }
 }
 
+// Offset, within a plane, of the slot the next pull reads population q of
+// node (x, y) from: (x - c_qx, y - c_qy), periodic.
+__device__ __forceinline__ long long src_offset(const Geometry& g, int q, int x, int y) {
+  const int cx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  int xs = x - cx[q], ys = y - cy[q];
+  xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+  ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+  return (long long)ys * g.pitch + xs;
+}
+
 // f = feq(rho, u) - s from dense fields; arithmetic in double, stored as T.
 template <typename T, int SCHEME>
 __global__ void init_kernel(Geometry g, Physics phys, const double* __restrict__ rho,
@@ -295,9 +400,8 @@ __global__ void init_kernel(Geometry g, Physics phys, const double* __restrict__
   p1.omega = 1.0;
   p1.fpre = 0.0;
   collide<double, SCHEME>(q, r - p.rho_ref, r, vx, vy, 0.0, 0.0, 0.0, 0.0, p1);
-  const long long off = (long long)y * g.pitch + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[(long long)i * g.plane + off] = (T)q[i];
+  for (int i = 0; i < Q; ++i) f[(long long)i * g.plane + src_offset(g, i, x, y)] = (T)q[i];
 }
 
 struct Shift {
@@ -320,7 +424,7 @@ __global__ void pack_kernel(Geometry g, Shift shift, const double* __restrict__ 
   const int y = (int)(k / g.nx), x = (int)(k - (long long)y * g.nx);
   const int q = q0 + m;
   const double s = shift.s[q];
-  f[(long long)q * g.plane + (long long)y * g.pitch + x] = (T)(dense[(long long)m * n + k] - s);
+  f[(long long)q * g.plane + src_offset(g, q, x, y)] = (T)(dense[(long long)m * n + k] - s);
 }
 
 template <typename T>
@@ -333,7 +437,7 @@ __global__ void unpack_kernel(Geometry g, Shift shift, const T* __restrict__ f, 
   const int y = (int)(k / g.nx), x = (int)(k - (long long)y * g.nx);
   const int q = q0 + m;
   const double s = shift.s[q];
-  dense[(long long)m * n + k] = (double)f[(long long)q * g.plane + (long long)y * g.pitch + x] + s;
+  dense[(long long)m * n + k] = (double)f[(long long)q * g.plane + src_offset(g, q, x, y)] + s;
 }
 
 template <typename T>
@@ -350,23 +454,35 @@ __global__ void reshift_kernel(Geometry g, Physics d, T* __restrict__ f) {
   }
 }
 
-template <typename T, int SCHEME, int BW, bool OBS>
+template <typename T, int SCHEME, int BW, int D, bool OBS>
 hipError_t launch_march_t(const Geometry& g, const Physics& ph, const Tiling& t, const void* fin,
                           void* fout, const ObserveOut& o, hipStream_t s) {
-  hipLaunchKernelGGL((march<T, SCHEME, BW, OBS>), dim3(t.blocks()), dim3(BW), 0, s, g, ph, t,
+  hipLaunchKernelGGL((march<T, SCHEME, BW, D, OBS>), dim3(t.blocks()), dim3(BW), 0, s, g, ph, t,
                      (const T*)fin, (T*)fout, o);
   return hipGetLastError();
+}
+
+template <typename T, int SCHEME, int BW, bool OBS>
+hipError_t launch_march_d(const Geometry& g, const Physics& ph, const Tiling& t, const void* fin,
+                          void* fout, const ObserveOut& o, hipStream_t s) {
+  if (OBS) return launch_march_t<T, SCHEME, BW, 1, OBS>(g, ph, t, fin, fout, o, s);
+  switch (t.depth) {
+    case 1: return launch_march_t<T, SCHEME, BW, 1, OBS>(g, ph, t, fin, fout, o, s);
+    case 2: return launch_march_t<T, SCHEME, BW, 2, OBS>(g, ph, t, fin, fout, o, s);
+    case 3: return launch_march_t<T, SCHEME, BW, 3, OBS>(g, ph, t, fin, fout, o, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, int SCHEME, bool OBS>
 hipError_t launch_march_w(const Geometry& g, const Physics& ph, const Tiling& t, const void* fin,
                           void* fout, const ObserveOut& o, hipStream_t s) {
   switch (t.block) {
-    case 128: return launch_march_t<T, SCHEME, 128, OBS>(g, ph, t, fin, fout, o, s);
-    case 192: return launch_march_t<T, SCHEME, 192, OBS>(g, ph, t, fin, fout, o, s);
-    case 256: return launch_march_t<T, SCHEME, 256, OBS>(g, ph, t, fin, fout, o, s);
-    case 320: return launch_march_t<T, SCHEME, 320, OBS>(g, ph, t, fin, fout, o, s);
-    case 512: return launch_march_t<T, SCHEME, 512, OBS>(g, ph, t, fin, fout, o, s);
+    case 128: return launch_march_d<T, SCHEME, 128, OBS>(g, ph, t, fin, fout, o, s);
+    case 192: return launch_march_d<T, SCHEME, 192, OBS>(g, ph, t, fin, fout, o, s);
+    case 256: return launch_march_d<T, SCHEME, 256, OBS>(g, ph, t, fin, fout, o, s);
+    case 320: return launch_march_d<T, SCHEME, 320, OBS>(g, ph, t, fin, fout, o, s);
+    case 512: return launch_march_d<T, SCHEME, 512, OBS>(g, ph, t, fin, fout, o, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -79,8 +79,8 @@ def load():
         "lbm_observe": (st, [_VP, _D, _D, _D, _D, O]),
         "lbm_get_populations": (st, [_VP, _D]),
         "lbm_set_populations": (st, [_VP, _D, st, i64]),
-        "lbm_set_tile": (st, [_VP, i32, i32]),
-        "lbm_get_tile": (st, [_VP, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "lbm_set_tile": (st, [_VP, i32, i32, i32]),
+        "lbm_get_tile": (st, [_VP, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "lbm_set_graph_steps": (st, [_VP, i32]),
         "lbm_destroy": (st, [_VP]),
         "lbm_status_string": (ctypes.c_char_p, [st]),
@@ -193,14 +193,15 @@ class Solver:
         self._check(self.lib.lbm_set_populations(self.ctx, _dptr(f), _scheme(scheme), int(step)))
         return self
 
-    def set_tile(self, block=0, rows=0):
-        self._check(self.lib.lbm_set_tile(self.ctx, int(block), int(rows)))
+    def set_tile(self, block=0, rows=0, depth=0):
+        self._check(self.lib.lbm_set_tile(self.ctx, int(block), int(rows), int(depth)))
         return self
 
     def get_tile(self):
-        b, r = ctypes.c_int32(), ctypes.c_int32()
-        self._check(self.lib.lbm_get_tile(self.ctx, ctypes.byref(b), ctypes.byref(r)))
-        return b.value, r.value
+        b, r, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.lbm_get_tile(self.ctx, ctypes.byref(b), ctypes.byref(r),
+                                          ctypes.byref(d)))
+        return b.value, r.value, d.value
 
     def set_graph_steps(self, k):
         self._check(self.lib.lbm_set_graph_steps(self.ctx, int(k)))

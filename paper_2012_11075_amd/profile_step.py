@@ -1,0 +1,61 @@
+"""Workload driver for rocprofv3: a few step launches on the 4096^2
+throughput lattice, followed by a plain elementwise kernel of known traffic
+(reads and writes `--copy-mib` MiB each) that calibrates the HBM counters.
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run --output-format csv -- \
+        python -m paper_2012_11075_amd.profile_step --precision fp64 --steps 20
+    rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch --output-format csv -- \
+        python -m paper_2012_11075_amd.profile_step --precision fp64 --steps 20
+
+Prints one line per phase so a long run shows progress.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32s"])
+    ap.add_argument("--scheme", default="well_balanced")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--problem", default="droplet_4096")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--depth", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm, tune
+    prob = I.PROBLEMS[args.problem]
+    s = lbm.Solver.for_problem(prob, precision=args.precision)
+    tile = (args.block, args.rows, args.depth) if (args.block or args.rows or args.depth) else \
+        tune.bench_tile(prob.nx, prob.ny, args.precision)
+    s.set_tile(*tile)
+    s.init(prob.rho(), scheme=args.scheme)
+    print("profile_step: %s %s %s tile=%s" % (prob.name, args.precision, args.scheme,
+                                               s.get_tile()), flush=True)
+    s.step(args.steps, args.scheme)
+    torch.cuda.synchronize()
+    print("profile_step: %d steps done" % args.steps, flush=True)
+    n = args.copy_mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    print("profile_step: calibration kernel: 3 x (read %d MiB + write %d MiB)"
+          % (args.copy_mib, args.copy_mib), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

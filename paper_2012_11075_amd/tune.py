@@ -29,20 +29,21 @@ def _table() -> dict:
 
 
 def bench_tile(nx: int, ny: int, precision: str = "fp64"):
-    """(block width, rows) for a lattice; (0, 0) keeps the library default."""
+    """(block width, rows, depth) for a lattice; zeros keep the library default."""
     t = _table().get("%s/%s" % (_bucket(nx, ny), precision))
-    return (int(t[0]), int(t[1])) if t else (0, 0)
+    return (int(t[0]), int(t[1]), int(t[2])) if t else (0, 0, 0)
 
 
 def sweep(solver, scheme="well_balanced", blocks=(128, 192, 256, 320, 512),
-          rows=(8, 16, 24, 32, 48, 64, 96, 128), steps=20):
+          rows=(8, 16, 24, 32, 48, 64, 96, 128), depths=(1, 2, 3), steps=20):
     """Time each tile shape on an initialised solver; returns
-    [(ms_per_step, block, rows), ...] sorted fastest first."""
+    [(ms_per_step, block, rows, depth), ...] sorted fastest first."""
     import torch
     out = []
     for b in blocks:
-        for r in rows:
-            solver.set_tile(b, r)
+      for r in rows:
+        for d in depths:
+            solver.set_tile(b, r, d)
             solver.step(2, scheme)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
@@ -50,6 +51,6 @@ def sweep(solver, scheme="well_balanced", blocks=(128, 192, 256, 320, 512),
             solver.step(steps, scheme)
             e1.record()
             torch.cuda.synchronize()
-            out.append((e0.elapsed_time(e1) / steps, b, r))
+            out.append((e0.elapsed_time(e1) / steps, b, r, d))
     out.sort()
     return out

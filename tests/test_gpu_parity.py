@@ -98,7 +98,8 @@ def test_parity_ragged(orc, lbm, nx, ny, scheme):
     compare(orc, lbm, prob, scheme, 200)
 
 
-TILES = [(128, 4), (192, 7), (256, 16), (320, 33), (512, 64), (256, 256)]
+TILES = [(128, 4, 1), (192, 7, 2), (256, 16, 3), (320, 33, 1), (512, 64, 2), (256, 256, 3),
+         (128, 5, 3)]
 
 
 @pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
