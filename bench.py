@@ -36,7 +36,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
-    path = os.path.join(PROFILE_DIR, "step_droplet_4096_traffic.json")
+    path = os.path.join(PROFILE_DIR, "step_droplet_4096.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -44,7 +44,7 @@ def measured_traffic(precision: str):
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     e = d.get(precision)
-    return None if e is None else e.get("bytes_per_launch")
+    return None if e is None else round(e.get("bytes_per_launch"))
 
 
 def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):

@@ -1,0 +1,125 @@
+"""Summarise rocprofv3 output of ``profile_step.py`` runs into profiles/.
+
+For each precision it reads three rocprofv3 output directories (CSV format):
+
+  kt    --kernel-trace --stats       average duration of the step kernel
+  fetch --pmc FETCH_SIZE             KiB fetched per dispatch
+  write --pmc WRITE_SIZE             KiB written per dispatch
+
+and scales each counter by what it reads for the calibration kernel of known
+traffic (an elementwise kernel that reads and writes ``copy_mib`` MiB).  It
+writes ``<out>.json`` (read by bench.py together with the kernel source hash
+the counters were taken on) and ``<out>.md``.
+
+    python -m paper_2012_11075_amd.profile_summary --root gpurun_out/prof \
+        --out profiles/step_droplet_4096 --copy-mib 1024 --nodes 16777216 \
+        --command-kt "..." --command-pmc "..."
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BYTES_PER_UPDATE = {"fp64": 144, "fp32s": 72}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ["lbm_kernels.hip", "lbm_kernels.h"]:
+        with open(os.path.join(ROOT, "paper_2012_11075_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _csv(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _is_step(name):
+    return "march<" in name and "true>" not in name
+
+
+def _is_calib(name):
+    return "AUnaryFunctor" in name and "MulFunctor" in name
+
+
+def summarise(root, precision, copy_mib, nodes):
+    kt = _csv(os.path.join(root, "kt_" + precision), "kernel_trace.csv")
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in kt if _is_step(r["Kernel_Name"])]
+    names = sorted({r["Kernel_Name"] for r in kt if _is_step(r["Kernel_Name"])})
+    out = {"kernel": names[0] if names else None, "dispatches": len(durs),
+           "avg_ns": statistics.mean(durs), "min_ns": min(durs), "max_ns": max(durs)}
+    per = {}
+    for ctr, sub in [("FETCH_SIZE", "fetch_"), ("WRITE_SIZE", "write_")]:
+        rows = _csv(os.path.join(root, sub + precision), "counter_collection.csv")
+        step = [float(r["Counter_Value"]) for r in rows
+                if _is_step(r["Kernel_Name"]) and r["Counter_Name"] == ctr]
+        cal = [float(r["Counter_Value"]) for r in rows
+               if _is_calib(r["Kernel_Name"]) and r["Counter_Name"] == ctr]
+        cal_kib = statistics.mean(cal)
+        scale = copy_mib * 1024.0 / cal_kib
+        per[ctr] = {"raw_kib_per_dispatch": statistics.mean(step), "calibration_raw_kib": cal_kib,
+                    "scale": scale, "bytes_per_launch": statistics.mean(step) * 1024.0 * scale}
+    alg = BYTES_PER_UPDATE[precision] * nodes
+    total = per["FETCH_SIZE"]["bytes_per_launch"] + per["WRITE_SIZE"]["bytes_per_launch"]
+    out.update(counters=per, bytes_per_launch=total, algorithmic_bytes_per_launch=alg,
+               traffic_over_algorithmic=total / alg,
+               achieved_algorithmic_gbs=alg / out["avg_ns"],
+               achieved_measured_gbs=total / out["avg_ns"])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--root", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--nodes", type=int, default=4096 * 4096)
+    ap.add_argument("--precisions", default="fp64,fp32s")
+    ap.add_argument("--command-kt", default="")
+    ap.add_argument("--command-pmc", default="")
+    ap.add_argument("--tile", default="")
+    args = ap.parse_args()
+    res = {"kernel_source_hash": kernel_source_hash(), "nodes": args.nodes,
+           "commands": {"kernel_trace": args.command_kt, "pmc": args.command_pmc},
+           "tile": args.tile}
+    for prec in args.precisions.split(","):
+        res[prec] = summarise(args.root, prec, args.copy_mib, args.nodes)
+    with open(args.out + ".json", "w") as fh:
+        json.dump(res, fh, indent=1)
+    lines = ["# Step kernel on the 4096 x 4096 droplet lattice (rocprofv3)", "",
+             "Kernel source hash: `%s`; tile (block, rows, depth): %s" % (res["kernel_source_hash"], args.tile), "",
+             "Commands (run from `/tmp`, `TMPDIR=/tmp`, repository at `$R`):", "",
+             "```", args.command_kt, args.command_pmc, "```", "",
+             "| precision | dispatches | avg us | algorithmic B/launch | measured B/launch (FETCH+WRITE, calibrated) | measured/algorithmic | GB/s algorithmic | GB/s measured |",
+             "|---|---|---|---|---|---|---|---|"]
+    for prec in args.precisions.split(","):
+        r = res[prec]
+        lines.append("| %s | %d | %.1f | %.4g | %.4g | %.3f | %.0f | %.0f |" % (
+            prec, r["dispatches"], r["avg_ns"] / 1e3, r["algorithmic_bytes_per_launch"],
+            r["bytes_per_launch"], r["traffic_over_algorithmic"], r["achieved_algorithmic_gbs"],
+            r["achieved_measured_gbs"]))
+    lines += ["", "Counter calibration: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by "
+              "(calibration bytes / counter reading) of an elementwise kernel that reads and writes "
+              "%d MiB each:" % args.copy_mib, ""]
+    for prec in args.precisions.split(","):
+        for ctr, c in res[prec]["counters"].items():
+            lines.append("- %s %s: raw %.1f KiB/dispatch, calibration kernel %.1f KiB -> scale %.3f" % (
+                prec, ctr, c["raw_kib_per_dispatch"], c["calibration_raw_kib"], c["scale"]))
+    with open(args.out + ".md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(res, indent=1))
+
+
+if __name__ == "__main__":
+    main()
