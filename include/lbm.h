@@ -152,6 +152,77 @@ const char* lbm_last_error(const lbm_ctx* ctx);
 /* Number of kernel launches one lbm_step(ctx, 1, .) performs (for profiling). */
 int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
 
+/* ------------------------------------------------------------------ batch */
+/* Many independent lattices of uneven size advanced together: each step is
+ * one persistent launch per group of slots that share precision, scheme and
+ * block width, reading a device-resident slot table (HIP-graph replays stay
+ * valid when slots come and go).  Each slot is a complete single-instance
+ * state (same kernels, same arithmetic), so a lattice gives bit-identical
+ * populations alone and in a batch.  The caller owns the device arena; the
+ * library places slot workspaces and the tables inside it. */
+
+typedef enum {
+  LBM_SLOT_FREE = 0,
+  LBM_SLOT_ACTIVE = 1,     /* advanced by lbm_batch_run */
+  LBM_SLOT_CONVERGED = 2,  /* retired: max|u| < tol */
+  LBM_SLOT_CAPPED = 3,     /* retired: step cap reached */
+  LBM_SLOT_DIVERGED = 4    /* retired: NaN/Inf or rho <= 0 */
+} lbm_slot_status;
+
+/* Arena bytes a slot with these parameters occupies (its workspace). */
+size_t lbm_batch_slot_bytes(const lbm_params* params);
+
+/* Bytes the batch reserves at the start of the arena for tables and
+ * reduction partials, for a given arena size and slot count. */
+size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots);
+
+/* Create a batch over a caller-owned device arena (256-byte aligned). */
+lbm_status lbm_batch_create(void* dev_arena, size_t bytes, int32_t max_slots, void* hip_stream,
+                            lbm_batch** out);
+
+/* Admit a lattice: allocate its workspace in the arena, set f(0) = feq(rho, 0)
+ * (as lbm_init) and mark it active.  It retires at the first lbm_batch_poll
+ * that finds max|u| < tol (tol <= 0: never) or step >= step_cap (<= 0: no
+ * cap), or a non-finite state.  LBM_EBUSY if no slot or arena range is free
+ * (nothing changes).  Synchronous. */
+lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* params, const double* rho,
+                           lbm_scheme scheme, double tol, int64_t step_cap, int32_t* slot);
+
+/* Advance every active slot by k >= 0 steps of its own scheme
+ * (asynchronous).  Steps are replayed from captured HIP graphs in chunks of
+ * the graph size (lbm_batch_set_graph_steps). */
+lbm_status lbm_batch_run(lbm_batch* b, int32_t k_steps);
+
+/* Observe every active slot (one batched launch per group), retire the slots
+ * that meet their criterion and write their indices to retired[0..n) (at most
+ * cap).  Synchronous. */
+lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* n_retired);
+
+/* Status and last observation of a slot (from the last poll or fetch). */
+lbm_status lbm_batch_slot_info(const lbm_batch* b, int32_t slot, int32_t* status,
+                               lbm_observation* obs);
+
+/* Fields of a slot (as lbm_observe); any pointer may be NULL.  Synchronous. */
+lbm_status lbm_batch_fetch(lbm_batch* b, int32_t slot, double* rho, double* ux, double* uy,
+                           double* mu, lbm_observation* obs);
+
+/* Populations of a slot as double[9][ny][nx] (as lbm_get_populations). */
+lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
+
+/* Tile of a slot's kernels (as lbm_set_tile; block width 64, 128 or 256 and
+ * depth 1 or 2 for batches). */
+lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block_width, int32_t rows,
+                              int32_t depth);
+
+/* Steps per captured graph in lbm_batch_run (even, 0 = plain launches). */
+lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps);
+
+/* Free a slot and its arena range. */
+lbm_status lbm_batch_release(lbm_batch* b, int32_t slot);
+
+lbm_status lbm_batch_destroy(lbm_batch* b);
+const char* lbm_batch_last_error(const lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ constexpr double W[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.
                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 constexpr size_t ALIGN = 256;
 constexpr int MIN_ROWS = 4;
-constexpr int MIN_BLOCK = 128;
+constexpr int MIN_BLOCK = 64;
 
 thread_local std::string g_thread_error;
 
@@ -487,5 +487,492 @@ const char* lbm_last_error(const lbm_ctx* c) {
 }
 
 int32_t lbm_kernels_per_step(const lbm_ctx*) { return 1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+namespace {
+
+constexpr int kBatchBlocks[3] = {64, 128, 256};
+constexpr int kGroups = 2 * 2 * 3 * 2;  // storage x scheme x block x depth
+
+int block_index(int block) {
+  for (int i = 0; i < 3; ++i)
+    if (kBatchBlocks[i] == block) return i;
+  return -1;
+}
+
+struct Range {
+  size_t off, size;
+};
+
+}  // namespace
+
+struct lbm_batch {
+  char* arena = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  int max_slots = 0;
+  size_t tab_stride = 0;   // bytes per group table
+  size_t part_off = 0;     // partials region
+  size_t part_cap = 0;     // tiles it can hold
+  size_t heap_off = 0;     // start of the slot heap
+
+  struct Slot {
+    int status = LBM_SLOT_FREE;
+    lbm_ctx* ctx = nullptr;
+    Range r{0, 0};
+    double tol = 0.0;
+    int64_t cap = 0;
+    int scheme = LBM_WELL_BALANCED;
+    lbm_observation last{};
+    size_t part_index = 0;  // first tile's index in the partials region
+    int tiles = 0;
+  };
+  std::vector<Slot> slots;
+  std::vector<Range> free_ranges;  // sorted by offset, coalesced
+
+  std::vector<std::vector<char>> host_tab;  // per group
+  uint32_t group_mask = 0;                  // groups that have ever held a slot
+  bool dirty = true;
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
+  uint32_t graph_mask = 0;
+  int grid[kGroups][2] = {};  // residency of step / observe launches
+  std::string err;
+
+  lbmk::BatchTable* dev_tab(int g) const { return (lbmk::BatchTable*)(arena + g * tab_stride); }
+  double* partials() const { return (double*)(arena + part_off); }
+};
+
+namespace {
+
+lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
+  if (b)
+    b->err = msg;
+  else
+    g_thread_error = msg;
+  return s;
+}
+
+#define BHIP(b, call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return bfail((b), LBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int group_of(const lbm_ctx* c, int scheme) {
+  const int bi = block_index(c->tl.block);
+  return ((c->storage() * 2 + scheme) * 3 + bi) * 2 + (c->tl.depth - 1);
+}
+
+void group_decode(int g, int* storage, int* scheme, int* block, int* depth) {
+  *depth = g % 2 + 1;
+  g /= 2;
+  *block = kBatchBlocks[g % 3];
+  g /= 3;
+  *scheme = g % 2;
+  *storage = g / 2;
+}
+
+size_t part_capacity(size_t arena_bytes) { return arena_bytes / 8192 + 1024; }
+
+void free_range(lbm_batch* b, Range r) {
+  auto& v = b->free_ranges;
+  auto it = std::lower_bound(v.begin(), v.end(), r.off,
+                             [](const Range& a, size_t off) { return a.off < off; });
+  it = v.insert(it, r);
+  // coalesce with neighbours
+  size_t i = it - v.begin();
+  if (i + 1 < v.size() && v[i].off + v[i].size == v[i + 1].off) {
+    v[i].size += v[i + 1].size;
+    v.erase(v.begin() + i + 1);
+  }
+  if (i > 0 && v[i - 1].off + v[i - 1].size == v[i].off) {
+    v[i - 1].size += v[i].size;
+    v.erase(v.begin() + i);
+  }
+}
+
+bool alloc_range(lbm_batch* b, size_t size, Range* out) {
+  for (size_t i = 0; i < b->free_ranges.size(); ++i) {
+    Range& f = b->free_ranges[i];
+    if (f.size >= size) {
+      *out = Range{f.off, size};
+      f.off += size;
+      f.size -= size;
+      if (f.size == 0) b->free_ranges.erase(b->free_ranges.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Rebuild the group tables from the active slots and upload them.
+lbm_status upload_tables(lbm_batch* b) {
+  size_t part = 0;
+  for (int g = 0; g < kGroups; ++g) {
+    if (!(b->group_mask >> g & 1)) continue;
+    std::vector<char>& h = b->host_tab[g];
+    std::fill(h.begin(), h.end(), 0);
+    auto* tab = (lbmk::BatchTable*)h.data();
+    int n = 0, tiles = 0;
+    for (size_t s = 0; s < b->slots.size(); ++s) {
+      lbm_batch::Slot& sl = b->slots[s];
+      if (sl.status != LBM_SLOT_ACTIVE || group_of(sl.ctx, sl.scheme) != g) continue;
+      lbm_ctx* c = sl.ctx;
+      lbmk::BatchSlot& d = tab->slot[n++];
+      d.g = c->L.g;
+      d.ph = make_physics(c->prm, sl.scheme);
+      d.tl = c->tl;
+      d.buf[0] = c->buf(0);
+      d.buf[1] = c->buf(1);
+      d.cur = c->cur;
+      d.tile0 = tiles;
+      d.partials = b->partials() + 4 * (part + tiles);
+      sl.part_index = part + tiles;
+      sl.tiles = c->tl.blocks();
+      tiles += sl.tiles;
+    }
+    tab->nslots = n;
+    tab->total_tiles = tiles;
+    part += tiles;
+    if (part > b->part_cap) return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
+    const size_t used = sizeof(lbmk::BatchTable) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot);
+    BHIP(b, hipMemcpyAsync(b->dev_tab(g), h.data(), used, hipMemcpyHostToDevice, b->stream));
+  }
+  // the host copies must stay intact until the uploads have been consumed
+  BHIP(b, hipStreamSynchronize(b->stream));
+  b->dirty = false;
+  return LBM_OK;
+}
+
+lbm_status batch_launches(lbm_batch* b, int steps, hipStream_t s) {
+  for (int j = 0; j < steps; ++j) {
+    for (int g = 0; g < kGroups; ++g) {
+      if (!(b->group_mask >> g & 1)) continue;
+      int storage, scheme, block, depth;
+      group_decode(g, &storage, &scheme, &block, &depth);
+      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g),
+                                 b->grid[g][0], j & 1, s));
+    }
+  }
+  return LBM_OK;
+}
+
+void drop_batch_graph(lbm_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+}
+
+lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
+  if (b->graph && b->graph_mask == b->group_mask) {
+    *out = b->graph;
+    return LBM_OK;
+  }
+  drop_batch_graph(b);
+  hipStream_t cs;
+  BHIP(b, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return bfail(b, LBM_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  lbm_status st = batch_launches(b, b->graph_steps, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != LBM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess)
+    return bfail(b, LBM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->graph = nullptr;
+    return bfail(b, LBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  b->graph_mask = b->group_mask;
+  *out = b->graph;
+  return LBM_OK;
+}
+
+lbm_batch::Slot* slot_of(lbm_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= (int32_t)b->slots.size()) return nullptr;
+  lbm_batch::Slot* s = &b->slots[slot];
+  return s->status == LBM_SLOT_FREE ? nullptr : s;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_slot_bytes(const lbm_params* p) {
+  return align_up(lbm_workspace_bytes(p), ALIGN);
+}
+
+size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
+  if (max_slots < 1) return 0;
+  const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
+  return kGroups * stride + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+}
+
+lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
+                            lbm_batch** out) {
+  if (!out) return bfail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!arena) return bfail(nullptr, LBM_EINVAL, "arena is NULL");
+  if ((uintptr_t)arena % ALIGN) return bfail(nullptr, LBM_EINVAL, "arena not 256-byte aligned");
+  if (max_slots < 1 || max_slots > 65536) return bfail(nullptr, LBM_EINVAL, "max_slots out of range");
+  const size_t over = lbm_batch_overhead_bytes(bytes, max_slots);
+  if (bytes <= over) return bfail(nullptr, LBM_ENOSPACE, "arena smaller than the batch tables");
+  lbm_batch* b = new lbm_batch();
+  b->arena = (char*)arena;
+  b->bytes = bytes;
+  b->stream = (hipStream_t)stream;
+  b->max_slots = max_slots;
+  b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
+  b->part_off = kGroups * b->tab_stride;
+  b->part_cap = part_capacity(bytes);
+  b->heap_off = over;
+  b->slots.resize(max_slots);
+  b->free_ranges.push_back(Range{b->heap_off, bytes - b->heap_off});
+  b->host_tab.assign(kGroups, std::vector<char>(lbmk::batch_table_bytes(max_slots), 0));
+  for (int g = 0; g < kGroups; ++g) {
+    int storage, scheme, block, depth;
+    group_decode(g, &storage, &scheme, &block, &depth);
+    b->grid[g][0] = lbmk::batch_grid(storage, scheme, block, depth, false);
+    b->grid[g][1] = lbmk::batch_grid(storage, scheme, block, 1, true);
+    if (b->grid[g][0] <= 0 || b->grid[g][1] <= 0) {
+      delete b;
+      return bfail(nullptr, LBM_EHIP, "could not size the batched launches (no device?)");
+    }
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho, lbm_scheme scheme,
+                           double tol, int64_t cap, int32_t* slot) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+  if (!slot || !rho) return bfail(b, LBM_EINVAL, "slot and rho must not be NULL");
+  if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
+  std::string why;
+  if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
+  int idx = -1;
+  for (int i = 0; i < b->max_slots; ++i)
+    if (b->slots[i].status == LBM_SLOT_FREE) {
+      idx = i;
+      break;
+    }
+  if (idx < 0) return bfail(b, LBM_EBUSY, "no free slot");
+  const size_t need = lbm_batch_slot_bytes(p);
+  Range r;
+  if (!alloc_range(b, need, &r)) return bfail(b, LBM_EBUSY, "no arena range of " + std::to_string(need) + " bytes");
+  lbm_ctx* c = nullptr;
+  lbm_status st = lbm_create(p, b->arena + r.off, need, b->stream, &c);
+  if (st != LBM_OK) {
+    free_range(b, r);
+    return bfail(b, st, lbm_last_error(nullptr));
+  }
+  const int block = p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256);
+  c->tl = make_tiling(c->L.g, block, 32, 1);
+  st = lbm_init(c, rho, nullptr, nullptr, scheme);
+  if (st != LBM_OK) {
+    std::string m = c->err;
+    lbm_destroy(c);
+    free_range(b, r);
+    return bfail(b, st, m);
+  }
+  lbm_batch::Slot& s = b->slots[idx];
+  s = lbm_batch::Slot();
+  s.status = LBM_SLOT_ACTIVE;
+  s.ctx = c;
+  s.r = r;
+  s.tol = tol;
+  s.cap = cap;
+  s.scheme = scheme;
+  b->group_mask |= 1u << group_of(c, scheme);
+  b->dirty = true;
+  *slot = idx;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t rows, int32_t depth) {
+  lbm_batch::Slot* s = slot_of(b, slot);
+  if (!s) return bfail(b, LBM_EINVAL, "no such slot");
+  if (block != 0 && block_index(block) < 0) return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
+  if (depth != 0 && depth != 1 && depth != 2) return bfail(b, LBM_EINVAL, "batch depth must be 1 or 2");
+  lbm_status st = lbm_set_tile(s->ctx, block, rows, depth);
+  if (st != LBM_OK) return bfail(b, st, s->ctx->err);
+  b->group_mask |= 1u << group_of(s->ctx, s->scheme);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_graph_steps(lbm_batch* b, int32_t steps) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+  if (steps < 0 || steps > 4096 || (steps >= 2 && (steps & 1)))
+    return bfail(b, LBM_EINVAL, "graph steps must be even and in [0, 4096]");
+  drop_batch_graph(b);
+  b->graph_steps = steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_run(lbm_batch* b, int32_t k) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+  if (k < 0) return bfail(b, LBM_EINVAL, "k must be >= 0");
+  if (k == 0) return LBM_OK;
+  if (b->dirty) {
+    lbm_status st = upload_tables(b);
+    if (st != LBM_OK) return st;
+  }
+  int left = k;
+  if (b->graph_steps >= 2) {
+    while (left >= b->graph_steps) {
+      hipGraphExec_t ge;
+      lbm_status st = batch_graph(b, &ge);
+      if (st != LBM_OK) return st;
+      BHIP(b, hipGraphLaunch(ge, b->stream));
+      left -= b->graph_steps;
+    }
+  }
+  lbm_status st = batch_launches(b, left, b->stream);
+  if (st != LBM_OK) return st;
+  for (auto& s : b->slots) {
+    if (s.status != LBM_SLOT_ACTIVE) continue;
+    s.ctx->step += k;
+    if (k & 1) s.ctx->cur ^= 1;
+  }
+  if (k & 1) b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* n_retired) {
+  if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
+  if (n_retired) *n_retired = 0;
+  if (b->dirty) {
+    lbm_status st = upload_tables(b);
+    if (st != LBM_OK) return st;
+  }
+  size_t total = 0;
+  for (const auto& s : b->slots)
+    if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
+  if (total == 0) return LBM_OK;
+  for (int g = 0; g < kGroups; ++g) {
+    if (!(b->group_mask >> g & 1)) continue;
+    int storage, scheme, block, depth;
+    group_decode(g, &storage, &scheme, &block, &depth);
+    BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g), b->grid[g][1],
+                               0, b->stream));
+  }
+  std::vector<double> part(total * 4);
+  BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  int n = 0;
+  bool changed = false;
+  for (size_t i = 0; i < b->slots.size(); ++i) {
+    lbm_batch::Slot& s = b->slots[i];
+    if (s.status != LBM_SLOT_ACTIVE) continue;
+    double umax = 0.0, bad = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0;
+    auto neumaier = [](double& sum, double& comp, double v) {
+      const double t = sum + v;
+      if (std::fabs(sum) >= std::fabs(v))
+        comp += (sum - t) + v;
+      else
+        comp += (v - t) + sum;
+      sum = t;
+    };
+    for (int t = 0; t < s.tiles; ++t) {
+      const double* q = &part[4 * (s.part_index + t)];
+      umax = std::max(umax, q[0]);
+      neumaier(ms, mc, q[1]);
+      neumaier(es, ec, q[2]);
+      bad = std::max(bad, q[3]);
+      if (!is_finite(q[1]) || !is_finite(q[2])) bad = 1.0;
+    }
+    s.last.step = s.ctx->step;
+    s.last.max_u = umax;
+    s.last.mass = ms + mc;
+    s.last.kinetic_energy = es + ec;
+    s.last.nonfinite = bad != 0.0;
+    int st = LBM_SLOT_ACTIVE;
+    if (bad != 0.0)
+      st = LBM_SLOT_DIVERGED;
+    else if (s.tol > 0.0 && umax < s.tol)
+      st = LBM_SLOT_CONVERGED;
+    else if (s.cap > 0 && s.ctx->step >= s.cap)
+      st = LBM_SLOT_CAPPED;
+    if (st != LBM_SLOT_ACTIVE) {
+      s.status = st;
+      changed = true;
+      if (retired && n < cap) retired[n] = (int32_t)i;
+      ++n;
+    }
+  }
+  if (n_retired) *n_retired = std::min(n, std::max(cap, 0));
+  if (changed) b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_slot_info(const lbm_batch* b, int32_t slot, int32_t* status,
+                               lbm_observation* obs) {
+  if (!b || slot < 0 || slot >= (int32_t)b->slots.size())
+    return bfail(const_cast<lbm_batch*>(b), LBM_EINVAL, "no such slot");
+  const lbm_batch::Slot& s = b->slots[slot];
+  if (status) *status = s.status;
+  if (obs) *obs = s.last;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_fetch(lbm_batch* b, int32_t slot, double* rho, double* ux, double* uy,
+                           double* mu, lbm_observation* obs) {
+  lbm_batch::Slot* s = slot_of(b, slot);
+  if (!s) return bfail(b, LBM_EINVAL, "no such slot");
+  lbm_status st = lbm_observe(s->ctx, rho, ux, uy, mu, obs);
+  if (st != LBM_OK && st != LBM_ENONFINITE) return bfail(b, st, s->ctx->err);
+  if (obs) s->last = *obs;
+  return st;
+}
+
+lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f) {
+  lbm_batch::Slot* s = slot_of(b, slot);
+  if (!s) return bfail(b, LBM_EINVAL, "no such slot");
+  lbm_status st = lbm_get_populations(s->ctx, f);
+  return st == LBM_OK ? st : bfail(b, st, s->ctx->err);
+}
+
+lbm_status lbm_batch_release(lbm_batch* b, int32_t slot) {
+  lbm_batch::Slot* s = slot_of(b, slot);
+  if (!s) return bfail(b, LBM_EINVAL, "no such slot");
+  // work already enqueued on the stream may still use the slot's memory
+  BHIP(b, hipStreamSynchronize(b->stream));
+  lbm_destroy(s->ctx);
+  free_range(b, s->r);
+  *s = lbm_batch::Slot();
+  b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  (void)hipStreamSynchronize(b->stream);
+  drop_batch_graph(b);
+  for (auto& s : b->slots)
+    if (s.ctx) lbm_destroy(s.ctx);
+  delete b;
+  return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) {
+  return b ? b->err.c_str() : g_thread_error.c_str();
+}
 
 }  // extern "C"

@@ -45,6 +45,30 @@ struct ObserveOut {
 };
 
 enum Scheme { STANDARD = 0, WELL_BALANCED = 1 };
+
+// One lattice of a batched launch (lives in device memory).
+struct BatchSlot {
+  Geometry g;
+  Physics ph;
+  Tiling tl;
+  void* buf[2];      // the two population copies
+  double* partials;  // 4 doubles per tile, for observe launches
+  int cur;           // buffer holding the state at parity 0
+  int tile0;         // first work item of this slot in the concatenated list
+};
+
+// Device-resident table of one batched launch group: slots in order of
+// tile0, total_tiles = sum of their tiles.
+struct BatchTable {
+  int nslots;
+  int total_tiles;
+  int pad[2];
+  BatchSlot slot[1];  // nslots entries (allocated with room for the maximum)
+};
+
+inline size_t batch_table_bytes(int max_slots) {
+  return sizeof(BatchTable) + (size_t)(max_slots > 1 ? max_slots - 1 : 0) * sizeof(BatchSlot);
+}
 enum Storage { FP64 = 0, FP32 = 1 };
 
 // One step: populations fin -> fout (ping-pong buffers).
@@ -72,7 +96,16 @@ hipError_t launch_unpack(int storage, const Geometry& g, const double* shift, co
 hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, void* f,
                           hipStream_t s);
 
-// Largest block width the kernels are instantiated for, and a check.
+// Persistent batched launch of one group (one precision, scheme, block width
+// and depth) over the device table `tab`; observe = write per-tile partials
+// instead of stepping.  `grid` = batch_grid(...) blocks.
+hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
+                        const BatchTable* tab, int grid, int parity, hipStream_t s);
+
+// Blocks of a batched launch that fit on the device at once.
+int batch_grid(int storage, int scheme, int block, int depth, bool observe);
+
+// Block widths the kernels are instantiated for.
 bool block_width_supported(int block);
 
 }  // namespace lbmk

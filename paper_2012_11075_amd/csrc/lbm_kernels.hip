@@ -123,9 +123,10 @@ __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R 
 // threads per block = output columns per block; D: rows of populations in
 // flight ahead of the row being summed.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
-__global__ void __launch_bounds__(BW)
-    march(Geometry g, Physics phys, Tiling tl, const T* __restrict__ fin, T* __restrict__ fout,
-          ObserveOut obs) {
+__device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phys,
+                                           const Tiling& tl, int tile,
+                                           const T* __restrict__ fin, T* __restrict__ fout,
+                                           const ObserveOut& obs) {
   using R = T;
   // LDS column j of the rho ring holds lattice column x0 - 2 + j, column m of
   // the mu ring lattice column x0 - 1 + m (periodic).
@@ -134,13 +135,6 @@ __global__ void __launch_bounds__(BW)
   __shared__ R fl[2][Q][BW];   // populations of rows y and y+1, each thread its own column
   const PhysR<R> p = to_r<R>(phys);
   const int t = threadIdx.x;
-
-  // Tiles are assigned so that each XCD (blocks b, b+8, ...) walks a
-  // contiguous range of tiles: neighbouring strips share halo lines in L2.
-  const int nb = tl.strips * tl.chunks;
-  const int b = blockIdx.x;
-  const int xcd = b & 7, l = b >> 3, q8 = nb >> 3, r8 = nb & 7;
-  const int tile = xcd * q8 + min(xcd, r8) + l;
   const int chunk = tile / tl.strips;
   const int strip = tile - chunk * tl.strips;
 
@@ -369,6 +363,51 @@ __global__ void __launch_bounds__(BW)
   }
 }
 
+// Tiles are assigned so that each XCD (blocks b, b+8, ...) walks a contiguous
+// range of tiles: neighbouring strips share halo lines in L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int xcd = b & 7, l = b >> 3, q8 = nb >> 3, r8 = nb & 7;
+  return xcd * q8 + min(xcd, r8) + l;
+}
+
+// One lattice: one block per tile.
+template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
+__global__ void __launch_bounds__(BW)
+    march(Geometry g, Physics phys, Tiling tl, const T* __restrict__ fin, T* __restrict__ fout,
+          ObserveOut obs) {
+  const int tile = xcd_tile(blockIdx.x, tl.strips * tl.chunks);
+  march_tile<T, SCHEME, BW, D, OBSERVE>(g, phys, tl, tile, fin, fout, obs);
+}
+
+// Many lattices in one persistent launch: the grid is sized to residency and
+// block b takes work items b, b + grid, ... of the table's concatenated tile
+// list; the table lives in device memory, so a captured launch stays valid
+// when slots are admitted or released.  `parity` selects which of each
+// slot's two buffers is read.
+template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
+__global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__ tab, int parity) {
+  const int total = tab->total_tiles;
+  const int ns = tab->nslots;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // slot of this item: last slot whose first tile <= item (uniform search)
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab->slot[mid].tile0 <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const BatchSlot& sd = tab->slot[lo];
+    const int which = sd.cur ^ parity;
+    const T* fin = (const T*)sd.buf[which];
+    T* fout = (T*)sd.buf[which ^ 1];
+    ObserveOut o{nullptr, nullptr, nullptr, nullptr, sd.partials};
+    __syncthreads();  // the previous item's last reads of the LDS rings
+    march_tile<T, SCHEME, BW, D, OBSERVE>(sd.g, sd.ph, sd.tl, item - sd.tile0, fin, fout, o);
+  }
+}
+
 // Offset, within a plane, of the slot the next pull reads population q of
 // node (x, y) from: (x - c_qx, y - c_qy), periodic.
 __device__ __forceinline__ long long src_offset(const Geometry& g, int q, int x, int y) {
@@ -478,6 +517,7 @@ template <typename T, int SCHEME, bool OBS>
 hipError_t launch_march_w(const Geometry& g, const Physics& ph, const Tiling& t, const void* fin,
                           void* fout, const ObserveOut& o, hipStream_t s) {
   switch (t.block) {
+    case 64: return launch_march_d<T, SCHEME, 64, OBS>(g, ph, t, fin, fout, o, s);
     case 128: return launch_march_d<T, SCHEME, 128, OBS>(g, ph, t, fin, fout, o, s);
     case 192: return launch_march_d<T, SCHEME, 192, OBS>(g, ph, t, fin, fout, o, s);
     case 256: return launch_march_d<T, SCHEME, 256, OBS>(g, ph, t, fin, fout, o, s);
@@ -506,7 +546,72 @@ inline unsigned grid1(long long n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 bool block_width_supported(int block) {
-  return block == 128 || block == 192 || block == 256 || block == 320 || block == 512;
+  return block == 64 || block == 128 || block == 192 || block == 256 || block == 320 ||
+         block == 512;
+}
+
+namespace {
+
+template <typename T, int SCHEME, int BW, int D, bool OBS>
+const void* batch_fn() {
+  return (const void*)march_batch<T, SCHEME, BW, D, OBS>;
+}
+
+// Kernel of a batched group; null for unsupported combinations.  Batches use
+// block widths 64, 128 and 256 and depth 1 or 2.
+template <typename T, int SCHEME, bool OBS>
+const void* batch_kernel_t(int block, int depth) {
+  if (depth == 1) {
+    switch (block) {
+      case 64: return batch_fn<T, SCHEME, 64, 1, OBS>();
+      case 128: return batch_fn<T, SCHEME, 128, 1, OBS>();
+      case 256: return batch_fn<T, SCHEME, 256, 1, OBS>();
+    }
+  } else if (depth == 2 && !OBS) {
+    switch (block) {
+      case 64: return batch_fn<T, SCHEME, 64, 2, OBS>();
+      case 128: return batch_fn<T, SCHEME, 128, 2, OBS>();
+      case 256: return batch_fn<T, SCHEME, 256, 2, OBS>();
+    }
+  }
+  return nullptr;
+}
+
+const void* batch_kernel(int storage, int scheme, int block, int depth, bool observe) {
+  if (observe) depth = 1;
+  if (storage == FP64) {
+    if (scheme == STANDARD)
+      return observe ? batch_kernel_t<double, STANDARD, true>(block, depth)
+                     : batch_kernel_t<double, STANDARD, false>(block, depth);
+    return observe ? batch_kernel_t<double, WELL_BALANCED, true>(block, depth)
+                   : batch_kernel_t<double, WELL_BALANCED, false>(block, depth);
+  }
+  if (scheme == STANDARD)
+    return observe ? batch_kernel_t<float, STANDARD, true>(block, depth)
+                   : batch_kernel_t<float, STANDARD, false>(block, depth);
+  return observe ? batch_kernel_t<float, WELL_BALANCED, true>(block, depth)
+                 : batch_kernel_t<float, WELL_BALANCED, false>(block, depth);
+}
+
+}  // namespace
+
+int batch_grid(int storage, int scheme, int block, int depth, bool observe) {
+  const void* fn = batch_kernel(storage, scheme, block, depth, observe);
+  if (!fn) return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
+                        const BatchTable* tab, int grid, int parity, hipStream_t s) {
+  const void* fn = batch_kernel(storage, scheme, block, depth, observe);
+  if (!fn || grid <= 0) return hipErrorInvalidValue;
+  void* args[] = {(void*)&tab, (void*)&parity};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
 }
 
 hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics& ph,

@@ -86,6 +86,20 @@ def load():
         "lbm_status_string": (ctypes.c_char_p, [st]),
         "lbm_last_error": (ctypes.c_char_p, [_VP]),
         "lbm_kernels_per_step": (i32, [_VP]),
+        "lbm_batch_slot_bytes": (ctypes.c_size_t, [P]),
+        "lbm_batch_overhead_bytes": (ctypes.c_size_t, [ctypes.c_size_t, i32]),
+        "lbm_batch_create": (st, [_VP, ctypes.c_size_t, i32, _VP, ctypes.POINTER(_VP)]),
+        "lbm_batch_admit": (st, [_VP, P, _D, st, ctypes.c_double, i64, ctypes.POINTER(i32)]),
+        "lbm_batch_run": (st, [_VP, i32]),
+        "lbm_batch_poll": (st, [_VP, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]),
+        "lbm_batch_slot_info": (st, [_VP, i32, ctypes.POINTER(i32), O]),
+        "lbm_batch_fetch": (st, [_VP, i32, _D, _D, _D, _D, O]),
+        "lbm_batch_get_populations": (st, [_VP, i32, _D]),
+        "lbm_batch_set_tile": (st, [_VP, i32, i32, i32, i32]),
+        "lbm_batch_set_graph_steps": (st, [_VP, i32]),
+        "lbm_batch_release": (st, [_VP, i32]),
+        "lbm_batch_destroy": (st, [_VP]),
+        "lbm_batch_last_error": (ctypes.c_char_p, [_VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -211,6 +225,115 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.lbm_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SLOT_STATUS = {0: "free", 1: "active", 2: "converged", 3: "capped", 4: "diverged"}
+
+
+class Batch:
+    """Many independent lattices in one device arena, advanced together by
+    batched persistent launches (see the lbm_batch_* calls of lbm.h)."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 1024, stream=None):
+        import torch
+        self.lib = load()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        assert self.arena.data_ptr() % 256 == 0
+        h = _VP()
+        st = self.lib.lbm_batch_create(self.arena.data_ptr(), int(arena_bytes), int(max_slots),
+                                       stream_handle(stream), ctypes.byref(h))
+        if st != 0:
+            raise LbmError(st, self.lib.lbm_batch_last_error(None).decode())
+        self.b = h
+        self.shapes = {}
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lbm_batch_last_error(self.b).decode()
+            if st == -4:
+                raise NonFiniteState(st, msg)
+            raise LbmError(st, msg)
+
+    @staticmethod
+    def slot_bytes(params: Params) -> int:
+        return int(load().lbm_batch_slot_bytes(ctypes.byref(params)))
+
+    @staticmethod
+    def overhead_bytes(arena_bytes: int, max_slots: int) -> int:
+        return int(load().lbm_batch_overhead_bytes(int(arena_bytes), int(max_slots)))
+
+    def admit(self, params: Params, rho, scheme="well_balanced", tol=0.0, step_cap=0) -> int:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        assert rho.shape == (params.ny, params.nx)
+        slot = ctypes.c_int32()
+        self._check(self.lib.lbm_batch_admit(self.b, ctypes.byref(params), _dptr(rho), _scheme(scheme),
+                                             float(tol), int(step_cap), ctypes.byref(slot)))
+        self.shapes[slot.value] = (params.ny, params.nx)
+        return slot.value
+
+    def try_admit(self, *a, **kw):
+        """admit(), or None when no slot or arena range is free."""
+        try:
+            return self.admit(*a, **kw)
+        except LbmError as e:
+            if e.status == -6:
+                return None
+            raise
+
+    def run(self, k: int):
+        self._check(self.lib.lbm_batch_run(self.b, int(k)))
+
+    def poll(self, cap: int = 65536) -> list:
+        buf = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        self._check(self.lib.lbm_batch_poll(self.b, buf, cap, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def info(self, slot: int):
+        st, ob = ctypes.c_int32(), Observation()
+        self._check(self.lib.lbm_batch_slot_info(self.b, int(slot), ctypes.byref(st), ctypes.byref(ob)))
+        return SLOT_STATUS[st.value], {"step": ob.step, "max_u": ob.max_u, "mass": ob.mass,
+                                       "kinetic_energy": ob.kinetic_energy,
+                                       "nonfinite": bool(ob.nonfinite)}
+
+    def fetch(self, slot: int, fields=("rho", "ux", "uy", "mu")) -> dict:
+        ny, nx = self.shapes[slot]
+        out = {k: np.empty((ny, nx)) for k in fields}
+        ob = Observation()
+        st = self.lib.lbm_batch_fetch(self.b, int(slot), _dptr(out.get("rho")), _dptr(out.get("ux")),
+                                      _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(ob))
+        if st not in (0, -4):
+            self._check(st)
+        out.update(step=ob.step, max_u=ob.max_u, mass=ob.mass, kinetic_energy=ob.kinetic_energy,
+                   nonfinite=bool(ob.nonfinite))
+        return out
+
+    def get_populations(self, slot: int) -> np.ndarray:
+        ny, nx = self.shapes[slot]
+        f = np.empty((9, ny, nx))
+        self._check(self.lib.lbm_batch_get_populations(self.b, int(slot), _dptr(f)))
+        return f
+
+    def set_tile(self, slot, block=0, rows=0, depth=0):
+        self._check(self.lib.lbm_batch_set_tile(self.b, int(slot), int(block), int(rows), int(depth)))
+
+    def set_graph_steps(self, k: int):
+        self._check(self.lib.lbm_batch_set_graph_steps(self.b, int(k)))
+
+    def release(self, slot: int):
+        self._check(self.lib.lbm_batch_release(self.b, int(slot)))
+        self.shapes.pop(slot, None)
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.lbm_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:
