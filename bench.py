@@ -6,13 +6,17 @@ Workload: the 4096 x 4096 periodic droplet (radius 1024, density ratio 100,
 beta = 0.1, kappa = 0.02, tau = 0.8), well-balanced scheme, populations in
 FP64 (the headline line) and in the shifted FP32 form (reported beside it).
 A step is one launch of the fused step kernel over the whole lattice; the
-populations stay in HBM for the whole timed region.  Prints one JSON line.
+populations stay in HBM for the whole timed region.  Beside it: 512 batched
+uneven lattices (5,000 steps, FP32-shifted and FP64), a served stream of
+run-to-equilibrium requests (p50/p99 latency, aggregate MLUPS) and the FP64
+CPU oracle on a bounded sample.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -90,6 +94,86 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):
     }
 
 
+def time_batch(precision, steps, warmup, count=512, graph_steps=50):
+    """Batched uneven instances: `count` lattices (side log-uniform 32..512,
+    droplet or slab, density ratio 10 or 100, tau in [0.6, 1.2]) advanced
+    together for `steps` steps of the WB scheme."""
+    import torch
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm, tune
+    probs = I.batch_instances(count)
+    prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
+                            p.physics.rho_l, p.physics.rho_v, precision=precision) for p in probs]
+    need = sum(lbm.Batch.slot_bytes(q) for q in prms)
+    arena = need + lbm.Batch.overhead_bytes(2 * need, count) + (1 << 24)
+    b = lbm.Batch(arena, max_slots=count)
+    b.set_graph_steps(graph_steps)
+    for q, p in zip(prms, probs):
+        sl = b.admit(q, p.rho(), "well_balanced")
+        t = tune.batch_tile(p.nx, p.ny, precision)
+        if t:
+            b.set_tile(sl, *t)
+    b.run(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    retired = b.poll()
+    status = {}
+    for sl in retired:
+        st = b.info(sl)[0]
+        status[st] = status.get(st, 0) + 1
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    nodes = sum(p.nx * p.ny for p in probs)
+    bpu = BYTES_PER_UPDATE[precision]
+    gbs = bpu * nodes * steps / (ms / 1e3) / 1e9
+    return {"value": round(nodes * steps / (ms / 1e3) / 1e6, 1), "unit": "MLUPS",
+            "instances": count, "total_nodes": nodes, "steps": steps,
+            "ms_per_step": round(ms / steps, 5), "hbm_gbs_algorithmic": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_update": bpu,
+            "graph_steps": graph_steps,
+            "retired_at_end": status,
+            "active_at_end": count - len(retired)}
+
+
+def serve_stream(n_requests=24, rate_hz=None, arena_gb=8.0, k=250):
+    """Served stream: Poisson arrivals of run-to-equilibrium requests (side
+    log-uniform 64..2048, density ratio 10..1000, FP32-shifted by default and
+    FP64 for one request in ten), continuous batching over one arena."""
+    import torch
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import tune
+    from paper_2012_11075_amd.serve import BatchExecutor, Server, summarise
+    if rate_hz is None:
+        # offered load ~0.7 of a ~60 GLUPS device at the mean request size and cap
+        mean_nodes = (2048 ** 2 - 64 ** 2) / (2 * math.log(2048 / 64))
+        rate_hz = 0.7 * 60e9 / (mean_nodes * 50_000)
+    reqs = I.request_stream(n_requests, rate_hz)
+    ex = BatchExecutor(int(arena_gb * 1e9), max_slots=256, graph_steps=50,
+                       tiles=lambda nx, ny, prec: tune.batch_tile(nx, ny, prec))
+    srv = Server(ex, k=k)
+    t0 = time.perf_counter()
+    out = srv.serve(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    torch.cuda.empty_cache()
+    s = summarise(out, wall)
+    s.update(rate_hz=round(rate_hz, 4), steps_per_round=k, arena_bytes=int(arena_gb * 1e9),
+             max_concurrent=max(sum(1 for e in srv.log[:i + 1] if e[0] == "admit") -
+                                sum(1 for e in srv.log[:i + 1] if e[0] == "retire")
+                                for i in range(len(srv.log))))
+    for key in ("p50_latency_s", "p99_latency_s", "mean_latency_s", "aggregate_mlups", "wall_s"):
+        s[key] = round(s[key], 4)
+    return s
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the same lattice for a bounded number of steps."""
     import oracle
@@ -120,6 +204,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single device "
@@ -157,6 +245,10 @@ def main():
                                "ms_per_step": round(r32["ms_per_step"], 5),
                                "tile": r32["tile"], "roofline": r32["roofline"],
                                "state_after": r32["state_after"]}
+    if not args.no_batch:
+        out["batched"] = {prec: time_batch(prec, args.batch_steps, 50) for prec in ("fp32s", "fp64")}
+    if not args.no_serve:
+        out["served"] = serve_stream(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

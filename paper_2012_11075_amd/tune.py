@@ -54,3 +54,78 @@ def sweep(solver, scheme="well_balanced", blocks=(128, 192, 256, 320, 512),
             out.append((e0.elapsed_time(e1) / steps, b, r, d))
     out.sort()
     return out
+
+
+def batch_bucket(nx: int, ny: int) -> str:
+    return _bucket(nx, ny)
+
+
+def batch_tile(nx: int, ny: int, precision: str = "fp64"):
+    """(block, rows, depth) for a lattice inside a batch, or None (library default)."""
+    t = _table().get("batch/%s/%s" % (_bucket(nx, ny), precision))
+    return (int(t[0]), int(t[1]), int(t[2])) if t else None
+
+
+def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64), depths=(1, 2),
+               steps=40, per_bucket=24):
+    """Pick a tile per lattice-size bucket by timing batched launches of up to
+    `per_bucket` lattices of that bucket under each candidate tile.
+    Returns {bucket: (ms_per_step, block, rows, depth)}."""
+    import torch
+    from . import lbm
+    buckets = {}
+    for p in problems:
+        buckets.setdefault(_bucket(p.nx, p.ny), []).append(p)
+    best = {}
+    for bk, probs in sorted(buckets.items(), key=lambda kv: int(kv[0]) if kv[0].isdigit() else 1 << 30):
+        probs = probs[:per_bucket]
+        prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
+                                p.physics.rho_l, p.physics.rho_v, precision=precision) for p in probs]
+        need = sum(lbm.Batch.slot_bytes(q) for q in prms)
+        arena = need + lbm.Batch.overhead_bytes(2 * need, len(probs)) + (1 << 22)
+        b = lbm.Batch(arena, max_slots=len(probs))
+        b.set_graph_steps(2)
+        slots = [b.admit(q, p.rho(), "well_balanced") for q, p in zip(prms, probs)]
+        res = []
+        for bw in blocks:
+            for r in rows:
+                for d in depths:
+                    for s in slots:
+                        b.set_tile(s, bw, r, d)
+                    b.run(4)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    e0.record()
+                    b.run(steps)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    res.append((e0.elapsed_time(e1) / steps, bw, r, d))
+        b.close()
+        res.sort()
+        best[bk] = res[0]
+    return best
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="tile autotuning on the current device")
+    ap.add_argument("--batch", action="store_true", help="tune batch tiles per size bucket")
+    ap.add_argument("--write", action="store_true", help="store the result in tuned_tiles.json")
+    args = ap.parse_args()
+    from . import inputs as I
+    table = _table()
+    if args.batch:
+        probs = I.batch_instances(512)
+        for prec in ("fp64", "fp32s"):
+            for bk, (ms, bw, r, d) in tune_batch(probs, prec).items():
+                print("batch", bk, prec, bw, r, d, "%.4f ms/step" % ms, flush=True)
+                table["batch/%s/%s" % (bk, prec)] = [bw, r, d]
+    if args.write:
+        with open(TABLE, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+            fh.write("\n")
+
+
+if __name__ == "__main__":
+    main()

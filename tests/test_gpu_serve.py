@@ -1,0 +1,45 @@
+"""Served stream on the GPU: requests that arrive while others run share the
+device as batch slots; each result is bit-identical to the same request run
+alone for the same number of steps."""
+import numpy as np
+import pytest
+
+from paper_2012_11075_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_alone():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2012_11075_amd import lbm
+    from paper_2012_11075_amd.serve import BatchExecutor, Server, summarise
+    reqs = I.request_stream(12, rate_hz=400.0, seed=21, side_lo=32, side_hi=160, step_cap=1500,
+                            fp64_fraction=0.3)
+    # room for a few lattices at a time, so later requests queue and are
+    # admitted while earlier ones are still running
+    arena = 6 * 160 * 160 * 176 + lbm.Batch.overhead_bytes(1 << 26, 16)
+    ex = BatchExecutor(arena, max_slots=16, graph_steps=20, capture=True)
+    srv = Server(ex, k=100)
+    out = srv.serve(reqs)
+    ex.close()
+    assert sorted(o.rid for o in out) == list(range(len(reqs)))
+    admits = [e for e in srv.log if e[0] == "admit"]
+    retires = [e for e in srv.log if e[0] == "retire"]
+    assert admits[-1][3] > retires[0][3]            # some admission after a retirement
+    s = summarise(out, max(o.retired for o in out))
+    print("served", s, flush=True)
+    for o in out:
+        req = reqs[o.rid]
+        ph = req.problem.physics
+        sv = lbm.Solver(req.problem.nx, req.problem.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l,
+                        ph.rho_v, ph.rho0, precision=req.precision)
+        sv.init(req.problem.rho(), scheme="well_balanced")
+        sv.step(o.steps, "well_balanced")
+        f = sv.get_populations()
+        sv.close()
+        assert np.array_equal(f, o.result["populations"], equal_nan=True), (o.rid, o.status)
+        if o.status == "converged":
+            assert o.max_u < req.tol
+        elif o.status == "capped":
+            assert o.steps >= req.step_cap
