@@ -174,6 +174,36 @@ def serve_stream(n_requests=24, rate_hz=None, arena_gb=8.0, k=250):
     return s
 
 
+def fp32_errors(steps=20_000):
+    """FP32-shifted against FP64 on the 256^2 droplet (ratio 10, tau 1, WB,
+    20,000 steps): max|u|, bulk densities and the Laplace pressure jump
+    (the FP64 path matches the CPU oracle to 1e-11 in the parity tests)."""
+    import numpy as np
+    from paper_2012_11075_amd import diagnostics as D
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm
+    prob = I.DROPLET_256
+    ph = prob.physics
+    reads = {}
+    for prec in ("fp64", "fp32s"):
+        s = lbm.Solver.for_problem(prob, precision=prec)
+        s.set_graph_steps(100)
+        s.init(prob.rho(), scheme="well_balanced")
+        s.step(steps, "well_balanced")
+        ob = s.observe(fields=("rho", "ux", "uy"))
+        s.close()
+        r = D.droplet_reads(ob["rho"], ph.beta, ph.rho_l, ph.rho_v)
+        r["max_u"] = ob["max_u"]
+        r["mass"] = ob["mass"]
+        reads[prec] = (r, ob)
+    cmp_ = D.compare(reads["fp64"][0], reads["fp32s"][0])
+    drho = float(np.abs(reads["fp32s"][1]["rho"] - reads["fp64"][1]["rho"]).max())
+    return {"workload": "droplet_256 (256x256, R=64, ratio 10, tau 1), WB, %d steps" % steps,
+            "reads": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) and vv is not None else vv)
+                          for kk, vv in v.items()} for k, v in cmp_.items()},
+            "max_abs_rho_field_err": drho}
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the same lattice for a bounded number of steps."""
     import oracle
@@ -245,6 +275,8 @@ def main():
                                "ms_per_step": round(r32["ms_per_step"], 5),
                                "tile": r32["tile"], "roofline": r32["roofline"],
                                "state_after": r32["state_after"]}
+    if not args.no_fp32:
+        out["fp32_shifted"]["error_vs_fp64"] = fp32_errors()
     if not args.no_batch:
         out["batched"] = {prec: time_batch(prec, args.batch_steps, 50) for prec in ("fp32s", "fp64")}
     if not args.no_serve:

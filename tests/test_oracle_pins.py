@@ -332,7 +332,7 @@ def test_wb_flat_interface_is_a_discrete_fixed_point(orc, phys):
     p = params(orc, ph)
     n = 201
     W = orc.equilibrium_width(p)
-    guess = I.tanh_slab(n, p.rho_l, p.rho_v, 50.0, 150.0, W)
+    guess = I.tanh_slab(n, p.rho_l, p.rho_v, 50.5, 149.5, W)
     prof, mub = _discrete_flat_equilibrium(p, n, guess.sum(), guess)
     rho = np.ascontiguousarray(np.broadcast_to(prof[None, :], (3, n)))
     f = orc.init("well_balanced", p, rho)
@@ -348,6 +348,28 @@ def test_wb_flat_interface_is_a_discrete_fixed_point(orc, phys):
     obs = orc.observe("standard", p, gs)
     assert not obs["nonfinite"] and obs["max_u"] > 1e-6
     assert np.abs(gs - fs).max() > 1e-6
+
+
+def test_interfaces_between_nodes_are_the_stable_equilibrium(orc):
+    """Lattice pinning of the WB flat interface (a property of the discrete
+    dynamics, found with the oracle): the symmetric equilibrium with its
+    interfaces on lattice nodes is a saddle (a 1e-12 asymmetric seed grows),
+    the one with interfaces half-way between nodes is stable (it decays)."""
+    p = params(orc, I.BJ_PHYS)
+    n = 201
+    W = orc.equilibrium_width(p)
+    growth = {}
+    for a, b in [(50.0, 150.0), (50.5, 149.5)]:
+        guess = I.tanh_slab(n, p.rho_l, p.rho_v, a, b, W)
+        prof, _ = _discrete_flat_equilibrium(p, n, guess.sum(), guess)
+        rho = np.ascontiguousarray(np.broadcast_to(prof[None, :], (1, n))).copy()
+        rho[0, 60] += 1e-12
+        f = orc.step("well_balanced", p, orc.init("well_balanced", p, rho), 500)
+        u1 = orc.observe("well_balanced", p, f)["max_u"]
+        f = orc.step("well_balanced", p, f, 500)
+        u2 = orc.observe("well_balanced", p, f)["max_u"]
+        growth[a] = u2 / u1
+    assert growth[50.0] > 100 and growth[50.5] < 1
 
 
 def test_discrete_equilibrium_tends_to_tanh(orc):
