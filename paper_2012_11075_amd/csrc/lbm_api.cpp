@@ -60,9 +60,13 @@ Layout make_layout(const lbm_params& p) {
   L.elem = p.precision == LBM_FP64 ? 8 : 4;
   L.g.nx = p.nx;
   L.g.ny = p.ny;
-  L.g.pitch = (int)align_up((size_t)p.nx, 32);
-  L.g.plane = (long long)align_up((size_t)L.g.pitch * p.ny, ALIGN / L.elem);
-  L.state_bytes = align_up((size_t)Q * L.g.plane * L.elem, ALIGN);
+  // Row-interleaved planes, f[y][q][x]: the nine population rows of a lattice
+  // row are contiguous (each 32-element aligned), so a row's loads and stores
+  // stream through one region of memory instead of nine.
+  const size_t px = align_up((size_t)p.nx, 32);
+  L.g.plane = (long long)px;         // elements between populations of a row
+  L.g.pitch = (int)(Q * px);         // elements between lattice rows
+  L.state_bytes = align_up((size_t)p.ny * Q * px * L.elem, ALIGN);
   L.staging_bytes = align_up((size_t)4 * p.nx * p.ny * sizeof(double), ALIGN);
   const size_t strips = (p.nx + MIN_BLOCK - 1) / MIN_BLOCK;
   const size_t chunks = (p.ny + MIN_ROWS - 1) / MIN_ROWS;

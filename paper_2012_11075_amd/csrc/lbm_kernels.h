@@ -9,11 +9,13 @@ namespace lbmk {
 
 constexpr int Q = 9;
 
-// Geometry of one lattice's population storage: 9 planes of `pitch * ny`
-// elements (x fastest), each plane starting `plane` elements after the last.
+// Geometry of one lattice's population storage: population q of node (x, y)
+// is element q * plane + y * pitch + x (x fastest).  The library lays the
+// nine population rows of a lattice row out contiguously (plane = row length
+// rounded up to 32 elements, pitch = 9 * plane).
 struct Geometry {
-  int nx, ny, pitch;
-  long long plane;  // elements between consecutive planes
+  int nx, ny, pitch;  // pitch: elements between lattice rows
+  long long plane;    // elements between populations of one node
 };
 
 // Physical and storage constants of one lattice, in the step's arithmetic.
