@@ -519,6 +519,7 @@ struct lbm_batch {
   hipStream_t stream = nullptr;
   int max_slots = 0;
   size_t tab_stride = 0;   // bytes per group table
+  size_t ctr_off = 0;      // work counters, one int per group
   size_t part_off = 0;     // partials region
   size_t part_cap = 0;     // tiles it can hold
   size_t heap_off = 0;     // start of the slot heap
@@ -547,6 +548,7 @@ struct lbm_batch {
   std::string err;
 
   lbmk::BatchTable* dev_tab(int g) const { return (lbmk::BatchTable*)(arena + g * tab_stride); }
+  int* counters() const { return (int*)(arena + ctr_off); }
   double* partials() const { return (double*)(arena + part_off); }
 };
 
@@ -655,12 +657,13 @@ lbm_status upload_tables(lbm_batch* b) {
 
 lbm_status batch_launches(lbm_batch* b, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
+    BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups, s));
     for (int g = 0; g < kGroups; ++g) {
       if (!(b->group_mask >> g & 1)) continue;
       int storage, scheme, block, depth;
       group_decode(g, &storage, &scheme, &block, &depth);
       BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g),
-                                 b->grid[g][0], j & 1, s));
+                                 b->counters() + g, b->grid[g][0], j & 1, s));
     }
   }
   return LBM_OK;
@@ -724,7 +727,7 @@ size_t lbm_batch_slot_bytes(const lbm_params* p) {
 size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  return kGroups * stride + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+  return kGroups * stride + ALIGN + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
 }
 
 lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
@@ -742,7 +745,8 @@ lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* 
   b->stream = (hipStream_t)stream;
   b->max_slots = max_slots;
   b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  b->part_off = kGroups * b->tab_stride;
+  b->ctr_off = kGroups * b->tab_stride;
+  b->part_off = b->ctr_off + ALIGN;
   b->part_cap = part_capacity(bytes);
   b->heap_off = over;
   b->slots.resize(max_slots);
@@ -869,12 +873,13 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (const auto& s : b->slots)
     if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
   if (total == 0) return LBM_OK;
+  BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups, b->stream));
   for (int g = 0; g < kGroups; ++g) {
     if (!(b->group_mask >> g & 1)) continue;
     int storage, scheme, block, depth;
     group_decode(g, &storage, &scheme, &block, &depth);
-    BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g), b->grid[g][1],
-                               0, b->stream));
+    BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g),
+                               b->counters() + g, b->grid[g][1], 0, b->stream));
   }
   std::vector<double> part(total * 4);
   BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),

@@ -100,9 +100,13 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
 
 // Persistent batched launch of one group (one precision, scheme, block width
 // and depth) over the device table `tab`; observe = write per-tile partials
-// instead of stepping.  `grid` = batch_grid(...) blocks.
+// instead of stepping.  `counter` (device int, zero at launch) hands out work
+// items; `grid` = batch_grid(...) blocks.
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int grid, int parity, hipStream_t s);
+                        const BatchTable* tab, int* counter, int grid, int parity, hipStream_t s);
+
+// Set n device ints to zero (the work counters, before each batched step).
+hipError_t launch_reset_counters(int* c, int n, hipStream_t s);
 
 // Blocks of a batched launch that fit on the device at once.
 int batch_grid(int storage, int scheme, int block, int depth, bool observe);

@@ -380,15 +380,37 @@ __global__ void __launch_bounds__(BW)
 }
 
 // Many lattices in one persistent launch: the grid is sized to residency and
-// block b takes work items b, b + grid, ... of the table's concatenated tile
-// list; the table lives in device memory, so a captured launch stays valid
-// when slots are admitted or released.  `parity` selects which of each
-// slot's two buffers is read.
+// each block takes the next work item (one tile of one lattice) from a
+// counter in device memory until the concatenated tile list of the table is
+// exhausted, so uneven lattices balance across the device.  The table and
+// the counter live in device memory, so a captured launch stays valid when
+// slots are admitted or released; `parity` selects which of each slot's two
+// buffers is read.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
-__global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__ tab, int parity) {
+__global__ void __launch_bounds__(BW)
+    march_batch(const BatchTable* __restrict__ tab, int* __restrict__ next, int parity) {
+  __shared__ int item_s;
   const int total = tab->total_tiles;
   const int ns = tab->nslots;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  for (;;) {
+    // The first wave takes the next item: all of its lanes join the atomic
+    // (lane 0 adds 1, the others 0) and read lane 0's result, so the index is
+    // wave-uniform without a lane-0-only branch.  Such a branch plus an LDS
+    // broadcast lets the compiler split a one-wave block's loop into a lane-0
+    // path and an inner loop in which the other lanes re-read the broadcast
+    // slot without a new item, and spin.
+    int item = 0;
+    if (threadIdx.x < 64) {
+      const int v = atomicAdd(next, threadIdx.x == 0 ? 1 : 0);
+      item = __builtin_amdgcn_readfirstlane(v);
+      if (BW > 64 && threadIdx.x == 0) item_s = item;
+    }
+    if (BW > 64) {
+      __syncthreads();  // publishes item_s; the previous item's LDS reads are done
+      item = __builtin_amdgcn_readfirstlane(item_s);
+      __syncthreads();  // every wave has read item_s before it is replaced
+    }
+    if (item >= total) break;
     // slot of this item: last slot whose first tile <= item (uniform search)
     int lo = 0, hi = ns - 1;
     while (lo < hi) {
@@ -403,9 +425,15 @@ __global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__
     const T* fin = (const T*)sd.buf[which];
     T* fout = (T*)sd.buf[which ^ 1];
     ObserveOut o{nullptr, nullptr, nullptr, nullptr, sd.partials};
-    __syncthreads();  // the previous item's last reads of the LDS rings
     march_tile<T, SCHEME, BW, D, OBSERVE>(sd.g, sd.ph, sd.tl, item - sd.tile0, fin, fout, o);
   }
+}
+
+// Work counters of the batched launches start at zero for every launch (a
+// kernel rather than a memset, so that captured graphs replay it reliably).
+__global__ void reset_counters(int* __restrict__ c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0;
 }
 
 // Offset, within a plane, of the slot the next pull reads population q of
@@ -607,11 +635,16 @@ int batch_grid(int storage, int scheme, int block, int depth, bool observe) {
 }
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int grid, int parity, hipStream_t s) {
+                        const BatchTable* tab, int* counter, int grid, int parity, hipStream_t s) {
   const void* fn = batch_kernel(storage, scheme, block, depth, observe);
   if (!fn || grid <= 0) return hipErrorInvalidValue;
-  void* args[] = {(void*)&tab, (void*)&parity};
+  void* args[] = {(void*)&tab, (void*)&counter, (void*)&parity};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
+}
+
+hipError_t launch_reset_counters(int* c, int n, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counters, dim3((n + 63) / 64), dim3(64), 0, s, c, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics& ph,

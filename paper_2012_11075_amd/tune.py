@@ -107,22 +107,87 @@ def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64),
     return best
 
 
+def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64, 128),
+                    depths=(1, 2), steps=20, passes=2):
+    """Coordinate descent over size buckets on the whole batch: for each bucket
+    in turn, time the full batch under every candidate tile for that bucket's
+    lattices (the others fixed) and keep the fastest.  Returns
+    {bucket: (block, rows, depth)} and the final ms per step."""
+    import torch
+    from . import lbm
+    prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
+                            p.physics.rho_l, p.physics.rho_v, precision=precision) for p in problems]
+    need = sum(lbm.Batch.slot_bytes(q) for q in prms)
+    b = lbm.Batch(need + lbm.Batch.overhead_bytes(2 * need, len(problems)) + (1 << 24),
+                  max_slots=len(problems))
+    b.set_graph_steps(10)
+    slots = [b.admit(q, p.rho(), "well_balanced") for q, p in zip(prms, problems)]
+    by = {}
+    for s, p in zip(slots, problems):
+        by.setdefault(_bucket(p.nx, p.ny), []).append(s)
+    choice = {bk: (64, 32, 1) for bk in by}
+
+    def timed():
+        b.run(10)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        b.run(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for bk, ss in by.items():
+        for s in ss:
+            b.set_tile(s, *choice[bk])
+    best_ms = timed()
+    for _ in range(passes):
+        for bk, ss in sorted(by.items()):
+            for cand in [(bw, r, d) for bw in blocks for r in rows for d in depths]:
+                for s in ss:
+                    b.set_tile(s, *cand)
+                ms = timed()
+                if ms < best_ms:
+                    best_ms, choice[bk] = ms, cand
+            for s in ss:
+                b.set_tile(s, *choice[bk])
+    b.close()
+    return choice, best_ms
+
+
 def main():
     import argparse
     ap = argparse.ArgumentParser(description="tile autotuning on the current device")
     ap.add_argument("--batch", action="store_true", help="tune batch tiles per size bucket")
+    ap.add_argument("--single", action="store_true", help="tune the 4096^2 lattice tile")
     ap.add_argument("--write", action="store_true", help="store the result in tuned_tiles.json")
+    ap.add_argument("--out", default=None, help="write the table here instead of tuned_tiles.json")
     args = ap.parse_args()
     from . import inputs as I
     table = _table()
     if args.batch:
         probs = I.batch_instances(512)
         for prec in ("fp64", "fp32s"):
-            for bk, (ms, bw, r, d) in tune_batch(probs, prec).items():
-                print("batch", bk, prec, bw, r, d, "%.4f ms/step" % ms, flush=True)
+            choice, ms = tune_batch_full(probs, prec)
+            for bk, (bw, r, d) in sorted(choice.items()):
+                print("batch", bk, prec, bw, r, d, flush=True)
                 table["batch/%s/%s" % (bk, prec)] = [bw, r, d]
-    if args.write:
-        with open(TABLE, "w") as fh:
+            print("batch", prec, "%.4f ms/step for the 512-lattice batch" % ms, flush=True)
+    if args.single:
+        from . import lbm
+        prob = I.DROPLET_4096
+        for prec in ("fp64", "fp32s"):
+            s = lbm.Solver.for_problem(prob, precision=prec)
+            s.init(prob.rho(), scheme="well_balanced")
+            res = sweep(s, blocks=(128, 256, 512), rows=(32, 64, 96, 128, 160, 192, 256),
+                        depths=(1, 2, 3), steps=30)
+            s.close()
+            for ms, bw, r, d in res[:5]:
+                print("single 4096", prec, bw, r, d, "%.4f ms/step" % ms, flush=True)
+            table["4096/%s" % prec] = list(res[0][1:])
+    if args.write or args.out:
+        with open(args.out or TABLE, "w") as fh:
             json.dump(table, fh, indent=1, sort_keys=True)
             fh.write("\n")
 
