@@ -5,6 +5,11 @@
 Workload: the 4096 x 4096 periodic droplet (radius 1024, density ratio 100,
 beta = 0.1, kappa = 0.02, tau = 0.8), well-balanced scheme, populations in
 FP64 (the headline line) and in the shifted FP32 form (reported beside it).
+These constants make the interface 1.3 nodes wide and the state diverges
+within ~100 steps (in the CPU oracle as well); the step kernel's work does not
+depend on the values, and the same grid with the free-energy constants of
+Sec. IV, whose state stays finite, is timed beside it (finite_state) with the
+FP32 errors against FP64 at full size.
 A step is one launch of the fused step kernel over the whole lattice; the
 populations stay in HBM for the whole timed region.  Beside it: 512 batched
 uneven lattices (5,000 steps, FP32-shifted and FP64), a served stream of
@@ -51,7 +56,7 @@ def measured_traffic(precision: str):
     return None if e is None else round(e.get("bytes_per_launch"))
 
 
-def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):
+def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=False):
     import torch
     from paper_2012_11075_amd import lbm, tune
     s = lbm.Solver.for_problem(prob, precision=precision)
@@ -69,7 +74,7 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    ob = s.observe(fields=(), raise_nonfinite=False)
+    ob = s.observe(fields=("rho", "ux", "uy") if fields else (), raise_nonfinite=False)
     tile = s.get_tile()
     kps = s.lib.lbm_kernels_per_step(s.ctx)
     s.close()
@@ -91,13 +96,17 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced"):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_update": bpu},
         "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
+        "observation": ob if fields else None,
     }
 
 
 def time_batch(precision, steps, warmup, count=512, graph_steps=50):
     """Batched uneven instances: `count` lattices (side log-uniform 32..512,
     droplet or slab, density ratio 10 or 100, tau in [0.6, 1.2]) advanced
-    together for `steps` steps of the WB scheme."""
+    together for `steps` steps of the WB scheme.  Slots retire only at the
+    poll after the timed region, so every lattice is advanced every step;
+    the poll's count of diverged lattices is split at tau = 0.8, below which
+    the WB step has a growing mode in bulk liquid."""
     import torch
     from paper_2012_11075_amd import inputs as I
     from paper_2012_11075_amd import lbm, tune
@@ -108,8 +117,10 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
     arena = need + lbm.Batch.overhead_bytes(2 * need, count) + (1 << 24)
     b = lbm.Batch(arena, max_slots=count)
     b.set_graph_steps(graph_steps)
+    tau_of = {}
     for q, p in zip(prms, probs):
         sl = b.admit(q, p.rho(), "well_balanced")
+        tau_of[sl] = p.physics.tau
         t = tune.batch_tile(p.nx, p.ny, precision)
         if t:
             b.set_tile(sl, *t)
@@ -127,6 +138,8 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
     status = {}
     for sl in retired:
         st = b.info(sl)[0]
+        if st == "diverged":
+            st = "diverged_tau_lt_0.8" if tau_of[sl] < 0.8 else "diverged_tau_ge_0.8"
         status[st] = status.get(st, 0) + 1
     b.close()
     del b
@@ -204,6 +217,37 @@ def fp32_errors(steps=20_000):
             "max_abs_rho_field_err": drho}
 
 
+def finite_state(steps, warmup):
+    """The same 4096^2 droplet with the free-energy constants of Sec. IV
+    (interface 3.2 nodes wide), whose state stays finite: the FP64 and
+    FP32-shifted rates on a finite state, and the FP32 errors at full size
+    against the FP64 path (max|u|, bulk densities, Laplace pressure jump)."""
+    import numpy as np
+    from paper_2012_11075_amd import diagnostics as D
+    from paper_2012_11075_amd import inputs as I
+    prob = I.DROPLET_4096_FINITE
+    ph = prob.physics
+    res, reads = {}, {}
+    for prec in ("fp64", "fp32s"):
+        r = time_gpu(prob, prec, steps, warmup, fields=True)
+        ob = r.pop("observation")
+        rd = D.droplet_reads(ob["rho"], ph.beta, ph.rho_l, ph.rho_v)
+        rd["max_u"], rd["mass"] = ob["max_u"], ob["mass"]
+        reads[prec] = (rd, ob["rho"])
+        res[prec] = {"value": round(r["mlups"], 1), "unit": "MLUPS",
+                     "ms_per_step": round(r["ms_per_step"], 5), "hbm_frac": r["roofline"]["frac"],
+                     "state_after": r["state_after"]}
+    cmp_ = D.compare(reads["fp64"][0], reads["fp32s"][0])
+    res["fp32_error_vs_fp64"] = {
+        "reads": {k: {kk: (float("%.6g" % vv) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items()} for k, v in cmp_.items()},
+        "max_abs_rho_field_err": float(np.abs(reads["fp32s"][1] - reads["fp64"][1]).max())}
+    res["workload"] = ("droplet_4096_finite: 4096x4096, R=1024, rho_l=1, rho_v=0.01, beta=0.01, "
+                       "kappa=0.0128, tau=0.8, tanh width %.3f, WB, %d steps after %d warm-up"
+                       % (prob.width, steps, warmup))
+    return res
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the same lattice for a bounded number of steps."""
     import oracle
@@ -227,6 +271,10 @@ def cpu_baseline(prob, budget_s=15.0):
                       % (prob.nx, prob.ny, prob.name, k, oracle.get_threads())}
 
 
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +284,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-finite", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
@@ -248,6 +297,7 @@ def main():
     from paper_2012_11075_amd import inputs as I
     prob = I.DROPLET_4096
     r64 = time_gpu(prob, "fp64", args.steps, args.warmup)
+    progress("fp64 headline %.4f ms/step" % r64["ms_per_step"])
     out = {
         "metric": "MLUPS (million lattice-node updates per second), FP64 well-balanced step",
         "value": round(r64["mlups"], 1),
@@ -268,21 +318,34 @@ def main():
                    "tile": r64["tile"], "kernels_per_step": 1},
         "roofline": r64["roofline"],
         "state_after": r64["state_after"],
+        "note": "with these constants the interface is 1.3 nodes wide and the step (the FP64 "
+                "CPU oracle too) diverges within ~100 steps; the kernel does the same work "
+                "on any values, and finite_state times the same grid on a finite state",
     }
     if not args.no_fp32:
         r32 = time_gpu(prob, "fp32s", args.steps, args.warmup)
+        progress("fp32s %.4f ms/step" % r32["ms_per_step"])
         out["fp32_shifted"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
                                "ms_per_step": round(r32["ms_per_step"], 5),
                                "tile": r32["tile"], "roofline": r32["roofline"],
                                "state_after": r32["state_after"]}
     if not args.no_fp32:
         out["fp32_shifted"]["error_vs_fp64"] = fp32_errors()
+        progress("fp32 errors on droplet_256 done")
+    if not args.no_finite:
+        out["finite_state"] = finite_state(args.steps, args.warmup)
+        progress("finite-state companion done")
     if not args.no_batch:
-        out["batched"] = {prec: time_batch(prec, args.batch_steps, 50) for prec in ("fp32s", "fp64")}
+        out["batched"] = {}
+        for prec in ("fp32s", "fp64"):
+            out["batched"][prec] = time_batch(prec, args.batch_steps, 50)
+            progress("batched %s %.4f ms/step" % (prec, out["batched"][prec]["ms_per_step"]))
     if not args.no_serve:
         out["served"] = serve_stream(args.serve_requests)
+        progress("served stream done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -122,6 +122,14 @@ def initial_density(p: Problem) -> np.ndarray:
 BJ_PHYS = Physics(tau=1.0, beta=0.1, kappa=0.02, rho_l=1.0, rho_v=0.1)
 THROUGHPUT_PHYS = Physics(tau=0.8, beta=0.1, kappa=0.02, rho_l=1.0, rho_v=0.01)
 PAPER_PHYS = Physics(tau=0.85, beta=0.01, kappa=0.0128, rho_l=1.0, rho_v=0.2)
+# The free-energy constants of Sec. IV (beta 0.01, kappa 0.0128) at other
+# density ratios: the interface stays about 3.2 nodes wide at any ratio.
+PAPER_BETA, PAPER_KAPPA = 0.01, 0.0128
+
+
+def equilibrium_width(ph: Physics) -> float:
+    """D of Eq. (38) for the double well, sqrt(8 kappa / beta) / (rho_l - rho_v)."""
+    return math.sqrt(8.0 * ph.kappa / ph.beta) / (ph.rho_l - ph.rho_v)
 
 # Flat interface, 200 x 4, slab x in [50, 150), 10,000 steps.
 FLAT_200x4 = Problem("flat_200x4", 200, 4, BJ_PHYS, "slab_x", 5.0, 50.0, 150.0,
@@ -132,6 +140,12 @@ DROPLET_256 = Problem("droplet_256", 256, 256, BJ_PHYS, "droplet", 5.0, 64.0, 0.
 # Throughput grid: droplet of radius 1024 on 4096 x 4096, density ratio 100.
 DROPLET_4096 = Problem("droplet_4096", 4096, 4096, THROUGHPUT_PHYS, "droplet", 5.0,
                        1024.0, 0.0, 1e-3, "mul", 3, 2_000)
+# The same grid and droplet with the free-energy constants of Sec. IV: the
+# state stays finite for the whole run (the configured constants give an
+# interface 1.3 nodes wide, and the step diverges within ~100 steps).
+FINITE_PHYS = Physics(tau=0.8, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=0.01)
+DROPLET_4096_FINITE = Problem("droplet_4096_finite", 4096, 4096, FINITE_PHYS, "droplet",
+                              equilibrium_width(FINITE_PHYS), 1024.0, 0.0, 1e-3, "mul", 3, 2_000)
 # The same physics on a 512 x 512 crop (radius scaled), for parity at moderate size.
 DROPLET_512_RATIO100 = Problem("droplet_512_ratio100", 512, 512, THROUGHPUT_PHYS, "droplet",
                                5.0, 128.0, 0.0, 1e-3, "mul", 3, 1_000)
@@ -143,7 +157,8 @@ PAPER_FLAT = Problem("paper_flat_21x101", 21, 101, PAPER_PHYS, "slab_y", 4.0, 25
 PAPER_DROPLET = Problem("paper_droplet_100", 100, 100, PAPER_PHYS, "droplet", 4.0, 25.0, 0.0,
                         1e-2, "mul", 12, 0)
 
-PROBLEMS = {p.name: p for p in [FLAT_200x4, DROPLET_256, DROPLET_4096, DROPLET_512_RATIO100,
+PROBLEMS = {p.name: p for p in [FLAT_200x4, DROPLET_256, DROPLET_4096, DROPLET_4096_FINITE,
+                                DROPLET_512_RATIO100,
                                 PAPER_FLAT, PAPER_DROPLET]}
 
 
@@ -152,20 +167,24 @@ def batch_instances(count: int = 512, seed: int = 4, side_lo: int = 32, side_hi:
     """Uneven independent problems for one batched launch: side log-uniform on
     [side_lo, side_hi]; droplet (radius 0.15-0.35 of the side) or a slab of
     half the side with probability 1/2; density ratio 10 or 100; tau uniform
-    on [0.6, 1.2]; beta = 0.1, kappa = 0.02; multiplicative noise 1e-3."""
+    on [0.6, 1.2]; the free-energy constants of Sec. IV (beta 0.01, kappa
+    0.0128); tanh profile of the equilibrium width; multiplicative noise 1e-3.
+    The WB step has a growing grid-scale mode in bulk liquid for tau below
+    about 0.8, so the instances drawn there diverge whatever the ratio."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):
         side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
         ratio = 10.0 if rng.uniform() < 0.5 else 100.0
         tau = float(rng.uniform(0.6, 1.2))
-        ph = Physics(tau=tau, beta=0.1, kappa=0.02, rho_l=1.0, rho_v=1.0 / ratio)
+        ph = Physics(tau=tau, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=1.0 / ratio)
+        w = equilibrium_width(ph)
         if rng.uniform() < 0.5:
             radius = float(rng.uniform(0.15, 0.35)) * side
-            prob = Problem("batch%03d" % k, side, side, ph, "droplet", 5.0, radius, 0.0,
+            prob = Problem("batch%03d" % k, side, side, ph, "droplet", w, radius, 0.0,
                            1e-3, "mul", seed * 100_000 + k, steps)
         else:
-            prob = Problem("batch%03d" % k, side, side, ph, "slab_x", 5.0, side / 4.0,
+            prob = Problem("batch%03d" % k, side, side, ph, "slab_x", w, side / 4.0,
                            3.0 * side / 4.0, 1e-3, "mul", seed * 100_000 + k, steps)
         out.append(prob)
     return out
@@ -185,9 +204,10 @@ class Request:
 def request_stream(n: int, rate_hz: float, seed: int = 5, side_lo: int = 64,
                    side_hi: int = 2048, step_cap: int = 50_000, fp64_fraction: float = 0.1) -> list:
     """Poisson arrivals at rate_hz; side log-uniform on [side_lo, side_hi];
-    droplet or slab; density ratio log-uniform on [10, 1000]; FP32-shifted by
-    default (tolerance 1e-6) and FP64 with probability fp64_fraction
-    (tolerance 1e-10)."""
+    droplet or slab; density ratio log-uniform on [10, 1000]; tau 1 and the
+    free-energy constants of Sec. IV; tanh profile of the equilibrium width;
+    FP32-shifted by default (tolerance 1e-6) and FP64 with probability
+    fp64_fraction (tolerance 1e-10)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -195,12 +215,13 @@ def request_stream(n: int, rate_hz: float, seed: int = 5, side_lo: int = 64,
         t += float(rng.exponential(1.0 / rate_hz))
         side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
         ratio = math.exp(rng.uniform(math.log(10.0), math.log(1000.0)))
-        ph = Physics(tau=1.0, beta=0.1, kappa=0.02, rho_l=1.0, rho_v=1.0 / ratio)
+        ph = Physics(tau=1.0, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=1.0 / ratio)
+        w = equilibrium_width(ph)
         if rng.uniform() < 0.5:
-            prob = Problem("req%05d" % k, side, side, ph, "droplet", 5.0,
+            prob = Problem("req%05d" % k, side, side, ph, "droplet", w,
                            float(rng.uniform(0.15, 0.35)) * side, 0.0, 1e-3, "mul", seed * 1_000_000 + k)
         else:
-            prob = Problem("req%05d" % k, side, side, ph, "slab_x", 5.0, side / 4.0, 3.0 * side / 4.0,
+            prob = Problem("req%05d" % k, side, side, ph, "slab_x", w, side / 4.0, 3.0 * side / 4.0,
                            1e-3, "mul", seed * 1_000_000 + k)
         fp64 = rng.uniform() < fp64_fraction
         out.append(Request(k, t, prob, "fp64" if fp64 else "fp32s", 1e-10 if fp64 else 1e-6, step_cap))
