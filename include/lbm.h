@@ -64,9 +64,9 @@ typedef enum { LBM_STANDARD = 0, LBM_WELL_BALANCED = 1 } lbm_scheme;
 /* LBM_FP64: populations stored and updated in double precision.
  * LBM_FP32_SHIFTED: populations stored as float g_i = f_i - s_i and updated
  * in single precision, with s_i = feq_i(rho_ref, u = 0) of the scheme in use
- * (rho_ref for i = 0 and 0 otherwise under WB; w_i rho_ref under the
- * standard scheme); mass, kinetic energy and max|u| are accumulated in
- * double precision. */
+ * (under WB rho_ref - (1 - w_0) rho0 for i = 0 and w_i rho0 otherwise,
+ * Eq. 24; w_i rho_ref under the standard scheme); mass, kinetic energy and
+ * max|u| are accumulated in double precision. */
 typedef enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1 } lbm_precision;
 
 typedef struct {
@@ -210,7 +210,7 @@ lbm_status lbm_batch_fetch(lbm_batch* b, int32_t slot, double* rho, double* ux, 
 lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
 
 /* Tile of a slot's kernels (as lbm_set_tile; block width 64, 128 or 256 and
- * depth 1 or 2 for batches). */
+ * depth 1, 2 or 3 for batches). */
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block_width, int32_t rows,
                               int32_t depth);
 

@@ -79,17 +79,6 @@ Layout make_layout(const lbm_params& p) {
   return L;
 }
 
-// Storage shift s_i of a scheme (zero for FP64).
-void shift_of(const lbm_params& p, int scheme, double* s) {
-  for (int i = 0; i < Q; ++i) s[i] = 0.0;
-  if (p.precision == LBM_FP64) return;
-  if (scheme == LBM_WELL_BALANCED && !p.shift_all) {
-    s[0] = p.rho_ref;
-  } else {
-    for (int i = 0; i < Q; ++i) s[i] = W[i] * p.rho_ref;
-  }
-}
-
 // Equilibrium at rest feq_i(rho, 0) of a scheme (Eq. 3 / Eq. 24).
 void feq_rest(const lbm_params& p, int scheme, double rho, double* f) {
   for (int i = 0; i < Q; ++i) {
@@ -97,6 +86,20 @@ void feq_rest(const lbm_params& p, int scheme, double rho, double* f) {
       f[i] = W[i] * rho;
     else
       f[i] = (i == 0) ? rho - (1.0 - W[0]) * p.rho0 : W[i] * p.rho0;
+  }
+}
+
+// Storage shift s_i of a scheme (zero for FP64): the scheme's equilibrium at
+// rest at rho_ref, so that stored values are departures from it (for WB with
+// rho0 = 0 that is rho_ref on f_0 only); shift_all selects w_i rho_ref for
+// either scheme.
+void shift_of(const lbm_params& p, int scheme, double* s) {
+  for (int i = 0; i < Q; ++i) s[i] = 0.0;
+  if (p.precision == LBM_FP64) return;
+  if (p.shift_all) {
+    for (int i = 0; i < Q; ++i) s[i] = W[i] * p.rho_ref;
+  } else {
+    feq_rest(p, scheme, p.rho_ref, s);
   }
 }
 
@@ -499,7 +502,8 @@ int32_t lbm_kernels_per_step(const lbm_ctx*) { return 1; }
 namespace {
 
 constexpr int kBatchBlocks[3] = {64, 128, 256};
-constexpr int kGroups = 2 * 2 * 3 * 2;  // storage x scheme x block x depth
+constexpr int kGroups = 2 * 2 * 3 * 3;  // storage x scheme x block x depth
+static_assert(kGroups <= 64, "group masks are 64-bit");
 
 int block_index(int block) {
   for (int i = 0; i < 3; ++i)
@@ -519,7 +523,7 @@ struct lbm_batch {
   hipStream_t stream = nullptr;
   int max_slots = 0;
   size_t tab_stride = 0;   // bytes per group table
-  size_t ctr_off = 0;      // work counters, one int per group
+  size_t ctr_off = 0;      // work queues, kQueueInts ints per group
   size_t part_off = 0;     // partials region
   size_t part_cap = 0;     // tiles it can hold
   size_t heap_off = 0;     // start of the slot heap
@@ -539,16 +543,18 @@ struct lbm_batch {
   std::vector<Range> free_ranges;  // sorted by offset, coalesced
 
   std::vector<std::vector<char>> host_tab;  // per group
-  uint32_t group_mask = 0;                  // groups that have ever held a slot
+  uint64_t group_mask = 0;                  // groups that have ever held a slot
+  uint64_t active_mask = 0;                 // groups with an active slot (launched)
   bool dirty = true;
   int graph_steps = 0;
   hipGraphExec_t graph = nullptr;
-  uint32_t graph_mask = 0;
+  uint64_t graph_mask = 0;
   int grid[kGroups][2] = {};  // residency of step / observe launches
   std::string err;
 
   lbmk::BatchTable* dev_tab(int g) const { return (lbmk::BatchTable*)(arena + g * tab_stride); }
   int* counters() const { return (int*)(arena + ctr_off); }
+  int* queues(int g) const { return counters() + g * lbmk::kQueueInts; }
   double* partials() const { return (double*)(arena + part_off); }
 };
 
@@ -571,12 +577,12 @@ lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
 
 int group_of(const lbm_ctx* c, int scheme) {
   const int bi = block_index(c->tl.block);
-  return ((c->storage() * 2 + scheme) * 3 + bi) * 2 + (c->tl.depth - 1);
+  return ((c->storage() * 2 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
 }
 
 void group_decode(int g, int* storage, int* scheme, int* block, int* depth) {
-  *depth = g % 2 + 1;
-  g /= 2;
+  *depth = g % 3 + 1;
+  g /= 3;
   *block = kBatchBlocks[g % 3];
   g /= 3;
   *scheme = g % 2;
@@ -619,6 +625,7 @@ bool alloc_range(lbm_batch* b, size_t size, Range* out) {
 // Rebuild the group tables from the active slots and upload them.
 lbm_status upload_tables(lbm_batch* b) {
   size_t part = 0;
+  uint64_t active = 0;
   for (int g = 0; g < kGroups; ++g) {
     if (!(b->group_mask >> g & 1)) continue;
     std::vector<char>& h = b->host_tab[g];
@@ -644,6 +651,7 @@ lbm_status upload_tables(lbm_batch* b) {
     }
     tab->nslots = n;
     tab->total_tiles = tiles;
+    if (n > 0) active |= 1ull << g;
     part += tiles;
     if (part > b->part_cap) return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
     const size_t used = sizeof(lbmk::BatchTable) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot);
@@ -651,19 +659,20 @@ lbm_status upload_tables(lbm_batch* b) {
   }
   // the host copies must stay intact until the uploads have been consumed
   BHIP(b, hipStreamSynchronize(b->stream));
+  b->active_mask = active;
   b->dirty = false;
   return LBM_OK;
 }
 
 lbm_status batch_launches(lbm_batch* b, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
-    BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups, s));
+    BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups * lbmk::kQueueInts, s));
     for (int g = 0; g < kGroups; ++g) {
-      if (!(b->group_mask >> g & 1)) continue;
+      if (!(b->active_mask >> g & 1)) continue;
       int storage, scheme, block, depth;
       group_decode(g, &storage, &scheme, &block, &depth);
       BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g),
-                                 b->counters() + g, b->grid[g][0], j & 1, s));
+                                 b->queues(g), b->grid[g][0], j & 1, s));
     }
   }
   return LBM_OK;
@@ -677,7 +686,7 @@ void drop_batch_graph(lbm_batch* b) {
 }
 
 lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
-  if (b->graph && b->graph_mask == b->group_mask) {
+  if (b->graph && b->graph_mask == b->active_mask) {
     *out = b->graph;
     return LBM_OK;
   }
@@ -705,7 +714,7 @@ lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
     b->graph = nullptr;
     return bfail(b, LBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
-  b->graph_mask = b->group_mask;
+  b->graph_mask = b->active_mask;
   *out = b->graph;
   return LBM_OK;
 }
@@ -727,7 +736,8 @@ size_t lbm_batch_slot_bytes(const lbm_params* p) {
 size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  return kGroups * stride + ALIGN + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+  return kGroups * stride + align_up(kGroups * lbmk::kQueueInts * sizeof(int), ALIGN) +
+         align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
 }
 
 lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
@@ -746,7 +756,7 @@ lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* 
   b->max_slots = max_slots;
   b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
   b->ctr_off = kGroups * b->tab_stride;
-  b->part_off = b->ctr_off + ALIGN;
+  b->part_off = b->ctr_off + align_up(kGroups * lbmk::kQueueInts * sizeof(int), ALIGN);
   b->part_cap = part_capacity(bytes);
   b->heap_off = over;
   b->slots.resize(max_slots);
@@ -806,7 +816,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   s.tol = tol;
   s.cap = cap;
   s.scheme = scheme;
-  b->group_mask |= 1u << group_of(c, scheme);
+  b->group_mask |= 1ull << group_of(c, scheme);
   b->dirty = true;
   *slot = idx;
   return LBM_OK;
@@ -816,10 +826,10 @@ lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t
   lbm_batch::Slot* s = slot_of(b, slot);
   if (!s) return bfail(b, LBM_EINVAL, "no such slot");
   if (block != 0 && block_index(block) < 0) return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
-  if (depth != 0 && depth != 1 && depth != 2) return bfail(b, LBM_EINVAL, "batch depth must be 1 or 2");
+  if (depth < 0 || depth > 3) return bfail(b, LBM_EINVAL, "batch depth must be 1, 2 or 3");
   lbm_status st = lbm_set_tile(s->ctx, block, rows, depth);
   if (st != LBM_OK) return bfail(b, st, s->ctx->err);
-  b->group_mask |= 1u << group_of(s->ctx, s->scheme);
+  b->group_mask |= 1ull << group_of(s->ctx, s->scheme);
   b->dirty = true;
   return LBM_OK;
 }
@@ -873,13 +883,13 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (const auto& s : b->slots)
     if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
   if (total == 0) return LBM_OK;
-  BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups, b->stream));
+  BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups * lbmk::kQueueInts, b->stream));
   for (int g = 0; g < kGroups; ++g) {
-    if (!(b->group_mask >> g & 1)) continue;
+    if (!(b->active_mask >> g & 1)) continue;
     int storage, scheme, block, depth;
     group_decode(g, &storage, &scheme, &block, &depth);
     BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g),
-                               b->counters() + g, b->grid[g][1], 0, b->stream));
+                               b->queues(g), b->grid[g][1], 0, b->stream));
   }
   std::vector<double> part(total * 4);
   BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),

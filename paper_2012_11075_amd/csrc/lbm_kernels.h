@@ -71,6 +71,12 @@ struct BatchTable {
 inline size_t batch_table_bytes(int max_slots) {
   return sizeof(BatchTable) + (size_t)(max_slots > 1 ? max_slots - 1 : 0) * sizeof(BatchSlot);
 }
+
+// Work queues of one batched launch: kQueues device ints (one per XCD),
+// kQueueStride ints apart so that each sits on its own 64-byte line.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16;
+constexpr int kQueueInts = kQueues * kQueueStride;
 enum Storage { FP64 = 0, FP32 = 1 };
 
 // One step: populations fin -> fout (ping-pong buffers).
@@ -100,12 +106,12 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
 
 // Persistent batched launch of one group (one precision, scheme, block width
 // and depth) over the device table `tab`; observe = write per-tile partials
-// instead of stepping.  `counter` (device int, zero at launch) hands out work
-// items; `grid` = batch_grid(...) blocks.
+// instead of stepping.  `queues` (kQueueInts device ints, zero at launch)
+// hand out work items; `grid` = batch_grid(...) blocks.
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int* counter, int grid, int parity, hipStream_t s);
+                        const BatchTable* tab, int* queues, int grid, int parity, hipStream_t s);
 
-// Set n device ints to zero (the work counters, before each batched step).
+// Set n device ints to zero (the work queues, before each batched step).
 hipError_t launch_reset_counters(int* c, int n, hipStream_t s);
 
 // Blocks of a batched launch that fit on the device at once.

@@ -119,13 +119,22 @@ __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R 
   }
 }
 
+// Populations are addressed through global-address-space pointers.  A
+// pointer read from device memory (the batched slot table) is otherwise
+// generic to the compiler, which then emits flat loads and stores; those
+// count against the LDS wait counter as well, so every LDS wait of the march
+// would also wait for the rows in flight.
+template <typename T>
+using Global = __attribute__((address_space(1))) T;
+
 // Marching step / observe kernel.  T: storage and arithmetic type; BW:
 // threads per block = output columns per block; D: rows of populations in
 // flight ahead of the row being summed.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
 __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phys,
                                            const Tiling& tl, int tile,
-                                           const T* __restrict__ fin, T* __restrict__ fout,
+                                           const Global<T>* __restrict__ fin,
+                                           Global<T>* __restrict__ fout,
                                            const ObserveOut& obs) {
   using R = T;
   // LDS column j of the rho ring holds lattice column x0 - 2 + j, column m of
@@ -274,7 +283,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
         const R drho = sum9(out);
         collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
         // post-collision populations stay at their node (aligned, streaming stores)
-        T* dst = fout + (long long)y * g.pitch + x;
+        Global<T>* dst = fout + (long long)y * g.pitch + x;
 #pragma unroll
         for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(out[i], dst + (long long)i * g.plane);
       } else {
@@ -376,41 +385,61 @@ __global__ void __launch_bounds__(BW)
     march(Geometry g, Physics phys, Tiling tl, const T* __restrict__ fin, T* __restrict__ fout,
           ObserveOut obs) {
   const int tile = xcd_tile(blockIdx.x, tl.strips * tl.chunks);
-  march_tile<T, SCHEME, BW, D, OBSERVE>(g, phys, tl, tile, fin, fout, obs);
+  march_tile<T, SCHEME, BW, D, OBSERVE>(g, phys, tl, tile, (const Global<T>*)fin,
+                                        (Global<T>*)fout, obs);
 }
 
 // Many lattices in one persistent launch: the grid is sized to residency and
-// each block takes the next work item (one tile of one lattice) from a
-// counter in device memory until the concatenated tile list of the table is
-// exhausted, so uneven lattices balance across the device.  The table and
-// the counter live in device memory, so a captured launch stays valid when
+// blocks take work items (one tile of one lattice) from queues in device
+// memory until the concatenated tile list of the table is exhausted, so
+// uneven lattices balance across the device.  The list is cut into eight
+// contiguous ranges, one queue each; block b starts on queue b mod 8, the XCD
+// the hardware places it on, so horizontally adjacent tiles (consecutive
+// items) run together on one XCD and share their halo lines in its L2.  A
+// block whose queue is empty moves on to the next queues in turn, which
+// balances the tail.  Every grab either returns an item of a finite range or
+// moves the block to its next queue, so each block leaves after at most
+// eight empty grabs and each item is taken exactly once.  The table and the
+// counters live in device memory, so a captured launch stays valid when
 // slots are admitted or released; `parity` selects which of each slot's two
 // buffers is read.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
 __global__ void __launch_bounds__(BW)
-    march_batch(const BatchTable* __restrict__ tab, int* __restrict__ next, int parity) {
+    march_batch(const BatchTable* __restrict__ tab, int* __restrict__ queues, int parity) {
   __shared__ int item_s;
   const int total = tab->total_tiles;
   const int ns = tab->nslots;
-  for (;;) {
-    // The first wave takes the next item: all of its lanes join the atomic
-    // (lane 0 adds 1, the others 0) and read lane 0's result, so the index is
-    // wave-uniform without a lane-0-only branch.  Such a branch plus an LDS
-    // broadcast lets the compiler split a one-wave block's loop into a lane-0
-    // path and an inner loop in which the other lanes re-read the broadcast
-    // slot without a new item, and spin.
-    int item = 0;
-    if (threadIdx.x < 64) {
-      const int v = atomicAdd(next, threadIdx.x == 0 ? 1 : 0);
-      item = __builtin_amdgcn_readfirstlane(v);
-      if (BW > 64 && threadIdx.x == 0) item_s = item;
-    }
-    if (BW > 64) {
+  const int q8 = total >> 3, r8 = total & 7;
+  const int home = blockIdx.x & 7;
+  int k = 0;
+  while (k < kQueues) {
+    // Queue index and grab result are made wave-uniform explicitly, so the
+    // loop control stays scalar and the compiler combines the wave's atomic
+    // into one memory operation.  All lanes of the first wave join the
+    // atomic (lane 0 adds 1, the others 0) and read lane 0's result, without
+    // a lane-0-only branch: such a branch plus an LDS broadcast let the
+    // compiler split a one-wave block's loop into a lane-0 path and an inner
+    // loop in which the other lanes re-read the broadcast slot without a new
+    // item, and spin.
+    const int q = __builtin_amdgcn_readfirstlane((home + k) & 7);
+    int* const qp = queues + q * kQueueStride;
+    int v;
+    if (BW == 64) {
+      v = __builtin_amdgcn_readfirstlane(atomicAdd(qp, threadIdx.x == 0 ? 1 : 0));
+    } else {
+      if (threadIdx.x < 64) {
+        const int a = __builtin_amdgcn_readfirstlane(atomicAdd(qp, threadIdx.x == 0 ? 1 : 0));
+        if (threadIdx.x == 0) item_s = a;
+      }
       __syncthreads();  // publishes item_s; the previous item's LDS reads are done
-      item = __builtin_amdgcn_readfirstlane(item_s);
+      v = __builtin_amdgcn_readfirstlane(item_s);
       __syncthreads();  // every wave has read item_s before it is replaced
     }
-    if (item >= total) break;
+    if (v >= q8 + (q < r8 ? 1 : 0)) {
+      ++k;
+      continue;
+    }
+    const int item = q * q8 + min(q, r8) + v;
     // slot of this item: last slot whose first tile <= item (uniform search)
     int lo = 0, hi = ns - 1;
     while (lo < hi) {
@@ -420,16 +449,24 @@ __global__ void __launch_bounds__(BW)
       else
         hi = mid - 1;
     }
-    const BatchSlot& sd = tab->slot[lo];
-    const int which = sd.cur ^ parity;
-    const T* fin = (const T*)sd.buf[which];
-    T* fout = (T*)sd.buf[which ^ 1];
-    ObserveOut o{nullptr, nullptr, nullptr, nullptr, sd.partials};
-    march_tile<T, SCHEME, BW, D, OBSERVE>(sd.g, sd.ph, sd.tl, item - sd.tile0, fin, fout, o);
+    // The slot's record is copied into locals once per item: read through a
+    // reference into the table, its fields would be re-loaded after every
+    // population store (the compiler cannot rule out that the stores alias
+    // the table), and each scalar re-load waits on outstanding LDS traffic.
+    const BatchSlot* sp = &tab->slot[lo];
+    const Geometry g = sp->g;
+    const Physics ph = sp->ph;
+    const Tiling tl = sp->tl;
+    const int which = sp->cur ^ parity;
+    const Global<T>* fin = (const Global<T>*)(const T*)sp->buf[which];
+    Global<T>* fout = (Global<T>*)(T*)sp->buf[which ^ 1];
+    const ObserveOut o{nullptr, nullptr, nullptr, nullptr, sp->partials};
+    const int tile = item - sp->tile0;
+    march_tile<T, SCHEME, BW, D, OBSERVE>(g, ph, tl, tile, fin, fout, o);
   }
 }
 
-// Work counters of the batched launches start at zero for every launch (a
+// Work queues of the batched launches start at zero for every launch (a
 // kernel rather than a memset, so that captured graphs replay it reliably).
 __global__ void reset_counters(int* __restrict__ c, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -586,7 +623,7 @@ const void* batch_fn() {
 }
 
 // Kernel of a batched group; null for unsupported combinations.  Batches use
-// block widths 64, 128 and 256 and depth 1 or 2.
+// block widths 64, 128 and 256 and depth 1, 2 or 3 (observe: depth 1).
 template <typename T, int SCHEME, bool OBS>
 const void* batch_kernel_t(int block, int depth) {
   if (depth == 1) {
@@ -600,6 +637,12 @@ const void* batch_kernel_t(int block, int depth) {
       case 64: return batch_fn<T, SCHEME, 64, 2, OBS>();
       case 128: return batch_fn<T, SCHEME, 128, 2, OBS>();
       case 256: return batch_fn<T, SCHEME, 256, 2, OBS>();
+    }
+  } else if (depth == 3 && !OBS) {
+    switch (block) {
+      case 64: return batch_fn<T, SCHEME, 64, 3, OBS>();
+      case 128: return batch_fn<T, SCHEME, 128, 3, OBS>();
+      case 256: return batch_fn<T, SCHEME, 256, 3, OBS>();
     }
   }
   return nullptr;
@@ -635,10 +678,10 @@ int batch_grid(int storage, int scheme, int block, int depth, bool observe) {
 }
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int* counter, int grid, int parity, hipStream_t s) {
+                        const BatchTable* tab, int* queues, int grid, int parity, hipStream_t s) {
   const void* fn = batch_kernel(storage, scheme, block, depth, observe);
   if (!fn || grid <= 0) return hipErrorInvalidValue;
-  void* args[] = {(void*)&tab, (void*)&counter, (void*)&parity};
+  void* args[] = {(void*)&tab, (void*)&queues, (void*)&parity};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
 }
 

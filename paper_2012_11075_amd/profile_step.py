@@ -30,10 +30,16 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="profile the batched launch over this many uneven instances instead")
     args = ap.parse_args()
     import torch
     from paper_2012_11075_amd import inputs as I
     from paper_2012_11075_amd import lbm, tune
+    if args.batch:
+        run_batch(args, torch, I, lbm, tune)
+        calibrate(args, torch)
+        return
     prob = I.PROBLEMS[args.problem]
     s = lbm.Solver.for_problem(prob, precision=args.precision)
     tile = (args.block, args.rows, args.depth) if (args.block or args.rows or args.depth) else \
@@ -45,6 +51,35 @@ def main():
     s.step(args.steps, args.scheme)
     torch.cuda.synchronize()
     print("profile_step: %d steps done" % args.steps, flush=True)
+    calibrate(args, torch)
+    s.close()
+
+
+def run_batch(args, torch, I, lbm, tune):
+    """The batched workload: `args.batch` uneven instances (side 32..512)
+    in one arena, tuned tiles, `args.steps` steps without graphs (one
+    counter reset and one persistent launch per step)."""
+    probs = I.batch_instances(args.batch)
+    prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
+                            p.physics.rho_l, p.physics.rho_v, precision=args.precision) for p in probs]
+    need = sum(lbm.Batch.slot_bytes(q) for q in prms)
+    b = lbm.Batch(need + lbm.Batch.overhead_bytes(2 * need, len(probs)) + (1 << 24),
+                  max_slots=len(probs))
+    for q, p in zip(prms, probs):
+        sl = b.admit(q, p.rho(), args.scheme)
+        t = tune.batch_tile(p.nx, p.ny, args.precision)
+        if t:
+            b.set_tile(sl, *t)
+    nodes = sum(p.nx * p.ny for p in probs)
+    print("profile_step: batch of %d instances, %d nodes, %s" % (len(probs), nodes, args.precision),
+          flush=True)
+    b.run(args.steps)
+    torch.cuda.synchronize()
+    print("profile_step: %d batched steps done" % args.steps, flush=True)
+    b.close()
+
+
+def calibrate(args, torch):
     n = args.copy_mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -54,7 +89,6 @@ def main():
     torch.cuda.synchronize()
     print("profile_step: calibration kernel: 3 x (read %d MiB + write %d MiB)"
           % (args.copy_mib, args.copy_mib), flush=True)
-    s.close()
 
 
 if __name__ == "__main__":

@@ -45,8 +45,11 @@ def _csv(d, suffix):
         return list(csv.DictReader(fh))
 
 
+KERNEL = "march<"
+
+
 def _is_step(name):
-    return "march<" in name and "true>" not in name
+    return KERNEL in name and "true>" not in name
 
 
 def _is_calib(name):
@@ -89,7 +92,12 @@ def main():
     ap.add_argument("--command-kt", default="")
     ap.add_argument("--command-pmc", default="")
     ap.add_argument("--tile", default="")
+    ap.add_argument("--kernel", default="march<",
+                    help="name prefix of the kernel to summarise (march< or march_batch<)")
+    ap.add_argument("--title", default="Step kernel on the 4096 x 4096 droplet lattice")
     args = ap.parse_args()
+    global KERNEL
+    KERNEL = args.kernel
     res = {"kernel_source_hash": kernel_source_hash(), "nodes": args.nodes,
            "commands": {"kernel_trace": args.command_kt, "pmc": args.command_pmc},
            "tile": args.tile}
@@ -97,7 +105,7 @@ def main():
         res[prec] = summarise(args.root, prec, args.copy_mib, args.nodes)
     with open(args.out + ".json", "w") as fh:
         json.dump(res, fh, indent=1)
-    lines = ["# Step kernel on the 4096 x 4096 droplet lattice (rocprofv3)", "",
+    lines = ["# %s (rocprofv3)" % args.title, "",
              "Kernel source hash: `%s`; tile (block, rows, depth): %s" % (res["kernel_source_hash"], args.tile), "",
              "Commands (run from `/tmp`, `TMPDIR=/tmp`, repository at `$R`):", "",
              "```", args.command_kt, args.command_pmc, "```", "",

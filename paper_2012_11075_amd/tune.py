@@ -66,7 +66,7 @@ def batch_tile(nx: int, ny: int, precision: str = "fp64"):
     return (int(t[0]), int(t[1]), int(t[2])) if t else None
 
 
-def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64), depths=(1, 2),
+def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64), depths=(1, 2, 3),
                steps=40, per_bucket=24):
     """Pick a tile per lattice-size bucket by timing batched launches of up to
     `per_bucket` lattices of that bucket under each candidate tile.
@@ -108,11 +108,16 @@ def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64),
 
 
 def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64, 128),
-                    depths=(1, 2), steps=20, passes=2):
-    """Coordinate descent over size buckets on the whole batch: for each bucket
-    in turn, time the full batch under every candidate tile for that bucket's
-    lattices (the others fixed) and keep the fastest.  Returns
-    {bucket: (block, rows, depth)} and the final ms per step."""
+                    depths=(1, 2, 3), steps=20, passes=2):
+    """Tile per size bucket on the whole batch.  First every lattice gets the
+    same candidate tile (one launch group) and the fastest is kept; then
+    coordinate descent over the buckets: for each bucket in turn, time the
+    full batch under every candidate for that bucket's lattices (the others
+    fixed) and keep the fastest.  Starting from one shared tile matters: a
+    bucket moved alone to another block width or depth forms a second group,
+    launched after the first, so single-bucket moves are judged against a
+    one-group start.  Returns {bucket: (block, rows, depth)}, the final ms
+    per step and the uniform sweep [(ms, tile), ...]."""
     import torch
     from . import lbm
     prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
@@ -138,13 +143,21 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
+    cands = [(bw, r, d) for bw in blocks for r in rows for d in depths]
+    uniform = []
+    for cand in cands:
+        for s in slots:
+            b.set_tile(s, *cand)
+        uniform.append((timed(), cand))
+    uniform.sort()
+    choice = {bk: uniform[0][1] for bk in by}
     for bk, ss in by.items():
         for s in ss:
             b.set_tile(s, *choice[bk])
     best_ms = timed()
     for _ in range(passes):
         for bk, ss in sorted(by.items()):
-            for cand in [(bw, r, d) for bw in blocks for r in rows for d in depths]:
+            for cand in cands:
                 for s in ss:
                     b.set_tile(s, *cand)
                 ms = timed()
@@ -153,7 +166,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
             for s in ss:
                 b.set_tile(s, *choice[bk])
     b.close()
-    return choice, best_ms
+    return choice, best_ms, uniform
 
 
 def main():
@@ -169,7 +182,9 @@ def main():
     if args.batch:
         probs = I.batch_instances(512)
         for prec in ("fp64", "fp32s"):
-            choice, ms = tune_batch_full(probs, prec)
+            choice, ms, uniform = tune_batch_full(probs, prec)
+            for ums, cand in uniform:
+                print("batch uniform", prec, cand, "%.4f ms/step" % ums, flush=True)
             for bk, (bw, r, d) in sorted(choice.items()):
                 print("batch", bk, prec, bw, r, d, flush=True)
                 table["batch/%s/%s" % (bk, prec)] = [bw, r, d]

@@ -66,6 +66,34 @@ def test_alone_vs_mix_bit_exact(lbm, graph_steps):
     b.close()
 
 
+BATCH_TILES = [(64, 8, 1), (128, 16, 2), (256, 32, 3), (64, 33, 3), (128, 5, 1), (256, 64, 2),
+               (64, 128, 2), (128, 32, 3)]
+
+
+def test_batch_tiles_bit_exact(lbm):
+    """Slots of one batch on every batched block width and depth (several
+    launch groups at once, each on its work queues) give the populations of
+    the lattice run alone."""
+    cases = mix_cases()
+    steps = 40
+    need = sum(lbm.Batch.slot_bytes(params_of(lbm, p, prec)) for p, prec, _ in cases)
+    b = lbm.Batch(need + lbm.Batch.overhead_bytes(need * 2, 64) + (1 << 20), max_slots=64)
+    b.set_graph_steps(10)
+    slots = []
+    for k, (p, prec, scheme) in enumerate(cases):
+        sl = b.admit(params_of(lbm, p, prec), p.rho(), scheme)
+        b.set_tile(sl, *BATCH_TILES[k % len(BATCH_TILES)])
+        slots.append(sl)
+    b.run(steps - 5)
+    b.run(5)
+    for k, ((p, prec, scheme), sl) in enumerate(zip(cases, slots)):
+        print("batch tile", BATCH_TILES[k % len(BATCH_TILES)], p.name, p.nx, p.ny, prec, scheme,
+              flush=True)
+        assert np.array_equal(b.get_populations(sl), alone(lbm, p, prec, scheme, steps),
+                              equal_nan=True), (p.name, prec, scheme)
+    b.close()
+
+
 def test_batch_fp64_slots_match_oracle(orc, lbm):
     probs = [I.with_size(I.PAPER_DROPLET, 64, 48), I.with_size(I.PAPER_DROPLET, 33, 70),
              I.PAPER_FLAT]

@@ -102,3 +102,30 @@ def test_wb_discrete_equilibrium_stays_at_rest(lbm, precision, floor):
     s.close()
     print(precision, "max|u| after 2000 steps from the discrete equilibrium: %.3e" % ob["max_u"])
     assert ob["max_u"] < floor
+
+
+def test_fp32_wb_rho0_keeps_precision(lbm):
+    """With rho0 != 0 in Eq. (24) the WB storage shift is the rest equilibrium
+    at rho_ref including the rho0 terms, so the stored non-rest populations
+    stay departures from w_i rho0 and the FP32 error is that of rho0 = 0
+    (to within a small factor, the trajectories differing only by round-off)."""
+    from dataclasses import replace
+    base = I.with_size(I.DROPLET_256, 96, 96)
+    err = {}
+    for rho0 in (0.0, 1.0):
+        prob = replace(base, physics=replace(base.physics, rho0=rho0))
+        ph = prob.physics
+        obs = {}
+        for prec in ("fp64", "fp32s"):
+            s = lbm.Solver(prob.nx, prob.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v,
+                           rho0=rho0, precision=prec)
+            s.init(prob.rho(), scheme="well_balanced")
+            s.step(500, "well_balanced")
+            obs[prec] = s.observe()
+            s.close()
+        err[rho0] = (np.abs(obs["fp32s"]["rho"] - obs["fp64"]["rho"]).max(),
+                     max(np.abs(obs["fp32s"]["ux"] - obs["fp64"]["ux"]).max(),
+                         np.abs(obs["fp32s"]["uy"] - obs["fp64"]["uy"]).max()))
+    print("fp32 error (rho, u) after 500 steps by rho0:", err)
+    assert err[1.0][0] < 2e-5 and err[1.0][1] < 1e-5
+    assert err[1.0][0] < 3 * err[0.0][0] + 1e-7 and err[1.0][1] < 3 * err[0.0][1] + 1e-8

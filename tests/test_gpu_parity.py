@@ -87,6 +87,14 @@ def test_parity_workloads(orc, lbm, name, scheme, steps):
     compare(orc, lbm, I.PROBLEMS[name], scheme, steps)
 
 
+@pytest.mark.parametrize("rho0", [0.5, 1.0])
+def test_parity_wb_rho0(orc, lbm, rho0):
+    """The WB equilibrium with the constant rho0 of Eq. (24) set nonzero."""
+    from dataclasses import replace
+    prob = replace(I.with_size(I.PAPER_DROPLET, 64, 48), physics=replace(I.PAPER_PHYS, rho0=rho0))
+    compare(orc, lbm, prob, "well_balanced", 1000)
+
+
 RAGGED = [(37, 53), (1, 7), (7, 1), (1, 1), (2, 2), (300, 5), (5, 300), (253, 3), (505, 9),
           (129, 130)]
 

@@ -16,9 +16,15 @@ def test_served_results_equal_alone():
     from paper_2012_11075_amd.serve import BatchExecutor, Server, summarise
     reqs = I.request_stream(12, rate_hz=400.0, seed=21, side_lo=32, side_hi=160, step_cap=1500,
                             fp64_fraction=0.3)
-    # room for a few lattices at a time, so later requests queue and are
-    # admitted while earlier ones are still running
-    arena = 6 * 160 * 160 * 176 + lbm.Batch.overhead_bytes(1 << 26, 16)
+    # room for the three largest requests only: the stream as a whole does
+    # not fit, so later requests queue and are admitted while earlier ones
+    # are still running or after they retire
+    sizes = sorted((lbm.Batch.slot_bytes(lbm.make_params(
+        r.problem.nx, r.problem.ny, r.problem.physics.tau, r.problem.physics.beta,
+        r.problem.physics.kappa, r.problem.physics.rho_l, r.problem.physics.rho_v,
+        precision=r.precision)) for r in reqs), reverse=True)
+    arena = sum(sizes[:3]) + lbm.Batch.overhead_bytes(1 << 26, 16)
+    assert sum(sizes) > sum(sizes[:3])
     ex = BatchExecutor(arena, max_slots=16, graph_steps=20, capture=True)
     srv = Server(ex, k=100)
     out = srv.serve(reqs)

@@ -169,6 +169,31 @@ def test_uniform_state_is_fixed(orc, scheme):
         assert np.abs(f - g).max() <= 1e-15
 
 
+@pytest.mark.parametrize("rho0", [0.5, 2.0])
+def test_wb_rho0_only_offsets_the_trajectory(orc, rho0):
+    """Sec. III: the constant rho0 of Eq. (24) does not change the theoretical
+    results.  At rest it moves -(1 - w_0) rho0 into f_0 and w_i rho0 into
+    each f_{i != 0}: an offset with zero density and momentum, affine under
+    BGK relaxation and, being uniform, carried onto itself by streaming.  So
+    from the same density the rho0 trajectory is the rho0 = 0 one plus that
+    constant, up to round-off, step after step."""
+    pr = I.with_size(I.PAPER_DROPLET, 40, 36)
+    p0 = params(orc, pr.physics, rho0=0.0)
+    pa = params(orc, pr.physics, rho0=rho0)
+    rho = pr.rho()
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    off = rho0 * w
+    off[0] = -(1.0 - w[0]) * rho0
+    assert abs(off.sum()) < 1e-15 and np.abs(C.T @ off).max() < 1e-15
+    f0 = orc.init("well_balanced", p0, rho)
+    fa = orc.init("well_balanced", pa, rho)
+    for _ in range(4):
+        assert np.abs(fa - off - f0).max() < 1e-12
+        f0 = orc.step("well_balanced", p0, f0, 50)
+        fa = orc.step("well_balanced", pa, fa, 50)
+    assert np.abs(fa - off - f0).max() < 1e-12
+
+
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_translation_equivariance(orc, scheme):
     """The step commutes with lattice translations on the torus, bit for bit."""
