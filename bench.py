@@ -61,7 +61,12 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
     from paper_2012_11075_amd import lbm, tune
     s = lbm.Solver.for_problem(prob, precision=precision)
     s.set_tile(*tune.bench_tile(prob.nx, prob.ny, precision))
-    s.init(prob.rho(), scheme=scheme)
+    rho0 = prob.rho()
+    torch.cuda.synchronize()
+    t_init = time.perf_counter()
+    s.init(rho0, scheme=scheme)          # host density -> device populations
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
     s.step(warmup, scheme)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -74,7 +79,9 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    ob = s.observe(fields=("rho", "ux", "uy") if fields else (), raise_nonfinite=False)
+    t_obs = time.perf_counter()
+    ob = s.observe(fields=("rho", "ux", "uy", "mu"), raise_nonfinite=False)   # device -> host fields
+    t_obs = time.perf_counter() - t_obs
     tile = s.get_tile()
     kps = s.lib.lbm_kernels_per_step(s.ctx)
     s.close()
@@ -97,6 +104,10 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
                      "traffic": traffic, "bytes_per_update": bpu},
         "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
         "observation": ob if fields else None,
+        # the whole job through the host boundary: density in over PCIe, the
+        # timed steps, and rho, u, mu back (context only, never the value)
+        "host_io": {"init_s": round(t_init, 4), "observe_fields_s": round(t_obs, 4),
+                    "pcie_inclusive_mlups": round(nodes * steps / (t_init + ms / 1e3 + t_obs) / 1e6, 1)},
     }
 
 
@@ -318,6 +329,7 @@ def main():
                    "tile": r64["tile"], "kernels_per_step": 1},
         "roofline": r64["roofline"],
         "state_after": r64["state_after"],
+        "host_io": r64["host_io"],
         "note": "with these constants the interface is 1.3 nodes wide and the step (the FP64 "
                 "CPU oracle too) diverges within ~100 steps; the kernel does the same work "
                 "on any values, and finite_state times the same grid on a finite state",

@@ -424,6 +424,43 @@ def test_discrete_equilibrium_tends_to_tanh(orc):
     assert -2.3 < order < -1.7, (errs, order)
 
 
+def test_surface_tension_is_the_interface_excess(orc):
+    """Sec. IV.B quotes sigma = (rho_l - rho_v)^3 sqrt(2 beta kappa) / 6 for
+    the double well.  Independently, the excess free energy of a flat
+    interface of the square-gradient model is kappa times the integral of
+    rho'^2 (at equilibrium half of it sits in psi0, half in the gradient
+    term); summed over the discrete equilibrium profile (two interfaces on
+    the torus) it approaches the closed form as the interface widens."""
+    rel = []
+    for beta in [0.01, 0.001, 0.0002]:
+        p = orc.Params(0.85, beta, 0.0128, 1.0, 0.2)
+        W = orc.equilibrium_width(p)
+        n = int(12 * W) * 2 + 1
+        guess = I.tanh_slab(n, p.rho_l, p.rho_v, n / 4 + 0.5, 3 * n / 4 - 0.5, W)
+        prof, _ = _discrete_flat_equilibrium(p, n, guess.sum(), guess)
+        d = np.diff(np.concatenate([prof, prof[:1]]))
+        sigma = p.kappa * np.sum(d * d) / 2
+        rel.append(abs(sigma / orc.surface_tension(p) - 1))
+    assert rel[0] > rel[1] > rel[2] and rel[2] < 5e-4, rel
+
+
+def test_wb_droplet_obeys_laplace_law(orc):
+    """Sec. IV.B: the bulk densities of a droplet at rest move off saturation
+    by the Laplace pressure.  A WB droplet relaxed on the oracle has
+    p0(rho_in) - p0(rho_out) (Eq. 37) = sigma / R, R the equivalent radius
+    of its density excess, to a fraction of a percent."""
+    ph = I.PAPER_PHYS
+    p = params(orc, ph)
+    n, R = 64, 16.0
+    prob = I.Problem("laplace", n, n, ph, "droplet", 4.0, R)
+    f = orc.step("well_balanced", p, orc.init("well_balanced", p, prob.rho()), 10_000)
+    d = orc.droplet_diagnostics(p, f.sum(-1), n // 2, n // 2)
+    laplace = orc.surface_tension(p) / d["r_eff"]
+    assert abs(d["r_eff"] - R) < 1.0
+    assert d["rho_in"] > p.rho_l and d["rho_out"] > p.rho_v
+    assert abs(d["dp"] / laplace - 1) < 0.01, (d, laplace)
+
+
 # ------------------------------------------------------- the paper's numbers
 @pytest.fixture(scope="module")
 def paper_flat_steady(orc):
