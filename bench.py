@@ -23,6 +23,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -259,6 +260,21 @@ def finite_state(steps, warmup):
     return res
 
 
+def copy_reference(nx, ny):
+    """The step's traffic without its arithmetic: `hbm_ceiling` (built next to
+    the library) streams the nine population rows of every lattice row from
+    one buffer to another in the same layout, FP64 and FP32, and times a
+    plain vectorised copy.  Run as a child process before this process uses
+    the GPU."""
+    exe = os.path.join(ROOT, "paper_2012_11075_amd", "_lib", "hbm_ceiling")
+    if not os.path.exists(exe):
+        return None
+    r = subprocess.run([exe, str(nx), str(ny), "20"], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return {"error": (r.stderr or r.stdout).strip()[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(prob, budget_s=15.0):
     """The FP64 oracle on the same lattice for a bounded number of steps."""
     import oracle
@@ -303,10 +319,12 @@ def main():
         print("bench.py measures one GPU: this build runs the step on a single device "
               "(multi-GPU decomposition is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import torch
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
     from paper_2012_11075_amd import inputs as I
     prob = I.DROPLET_4096
+    ref = copy_reference(prob.nx, prob.ny)
+    progress("copy reference %s" % ref)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
     r64 = time_gpu(prob, "fp64", args.steps, args.warmup)
     progress("fp64 headline %.4f ms/step" % r64["ms_per_step"])
     out = {
@@ -330,6 +348,10 @@ def main():
         "roofline": r64["roofline"],
         "state_after": r64["state_after"],
         "host_io": r64["host_io"],
+        # the same bytes moved with no arithmetic: the practical ceiling for
+        # this traffic (frac_* = the step's algorithmic GB/s over it)
+        "copy_reference": None if not ref or "error" in ref else dict(
+            ref, frac_fp64=round(r64["roofline"]["achieved"] / ref["rows_copy_fp64_gbs"], 4)),
         "note": "with these constants the interface is 1.3 nodes wide and the step (the FP64 "
                 "CPU oracle too) diverges within ~100 steps; the kernel does the same work "
                 "on any values, and finite_state times the same grid on a finite state",
@@ -337,6 +359,9 @@ def main():
     if not args.no_fp32:
         r32 = time_gpu(prob, "fp32s", args.steps, args.warmup)
         progress("fp32s %.4f ms/step" % r32["ms_per_step"])
+        if out["copy_reference"]:
+            out["copy_reference"]["frac_fp32"] = round(
+                r32["roofline"]["achieved"] / out["copy_reference"]["rows_copy_fp32_gbs"], 4)
         out["fp32_shifted"] = {"value": round(r32["mlups"], 1), "unit": "MLUPS",
                                "ms_per_step": round(r32["ms_per_step"], 5),
                                "tile": r32["tile"], "roofline": r32["roofline"],

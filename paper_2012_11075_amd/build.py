@@ -2,8 +2,11 @@
 
     python -m paper_2012_11075_amd.build
 
-The library lands in paper_2012_11075_amd/_lib/liblbm.so.  Every call
-recompiles (the build is a few tens of seconds); nothing is cached elsewhere.
+The library lands in paper_2012_11075_amd/_lib/liblbm.so, next to
+hbm_ceiling (a small program that times the step's memory traffic without
+its arithmetic, the reference for the bandwidth the step reaches).  Every
+call recompiles (the build is a few tens of seconds); nothing is cached
+elsewhere.
 """
 from __future__ import annotations
 
@@ -18,6 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "liblbm.so")
+CEILING = os.path.join(LIB_DIR, "hbm_ceiling")
 SOURCES = ["lbm_kernels.hip", "lbm_api.cpp"]
 
 HIPCC_FLAGS = [
@@ -59,6 +63,12 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    tmp = CEILING + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), *HIPCC_FLAGS, os.path.join(CSRC, "hbm_ceiling.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, CEILING)
     return LIB
 
 
