@@ -260,6 +260,40 @@ def finite_state(steps, warmup):
     return res
 
 
+STENCIL4_BYTES = 256   # FP64 bytes per node of the three-pass variant step
+
+
+def time_stencil4(prob, steps, warmup, scheme="standard"):
+    """The force-stencil variant (fourth-order gradients in the force, FP64):
+    three passes per step, so 256 algorithmic bytes per node (density: 72
+    read + 8 written; chemical potential: 8 + 8; collide-stream: 9 + 2 fields
+    read, 9 written)."""
+    import torch
+    from paper_2012_11075_amd import lbm
+    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    s.init(prob.rho(), scheme=scheme)
+    s.step(warmup, scheme)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps, scheme)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    nodes = prob.nx * prob.ny
+    gbs = STENCIL4_BYTES * nodes / (ms / 1e3) / 1e9
+    return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
+            "scheme": scheme, "kernels_per_step": 3, "bytes_per_update": STENCIL4_BYTES,
+            "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "workload": "%s, %s scheme, fourth-order force stencil, FP64, %d steps"
+                        % (prob.name, scheme, steps)}
+
+
 def copy_reference(nx, ny):
     """The step's traffic without its arithmetic: `hbm_ceiling` (built next to
     the library) streams the nine population rows of every lattice row from
@@ -312,6 +346,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-finite", action="store_true")
+    ap.add_argument("--no-stencil4", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
@@ -372,6 +407,9 @@ def main():
     if not args.no_finite:
         out["finite_state"] = finite_state(args.steps, args.warmup)
         progress("finite-state companion done")
+    if not args.no_stencil4:
+        out["force_stencil4"] = time_stencil4(prob, 200, 5)
+        progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
     if not args.no_batch:
         out["batched"] = {}
         for prec in ("fp32s", "fp64"):

@@ -80,6 +80,12 @@ typedef struct {
   double rho_ref;   /* reference density of the FP32 shift; ignored for FP64 */
   int32_t precision;   /* lbm_precision */
   int32_t shift_all;   /* FP32 only: 1 = shift every scheme by w_i rho_ref */
+  int32_t force_stencil; /* gradients of the force (and of Eq. 26): 0 the
+                          * isotropic central scheme of Sec. II; 1 the
+                          * fourth-order form grad - (1/6) grad(lap), the
+                          * higher-order discretisation discussed after
+                          * Eq. (23) (FP64 only, ny <= 65535, not in batches;
+                          * three kernels per step instead of one) */
 } lbm_params;
 
 typedef struct {

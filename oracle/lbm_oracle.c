@@ -43,6 +43,13 @@
  *     force evaluated from the fields at time t (explicit; F does not depend
  *     on u).
  *   - The WB constant rho0 of Eq. (24) is a parameter; the paper uses 0.
+ *   - Force-stencil variant (Sec. II, after Eq. 23: higher-order gradients in
+ *     the force reduce but cannot remove the net force): with force_stencil
+ *     = 1 every gradient in the force and in Eq. (26) is the fourth-order
+ *     gradient grad(phi) - (1/6) grad(lap(phi)) built from the two stencils
+ *     above; it removes the isotropic second-order error of the central
+ *     scheme and reduces to (-phi_{j+2} + 8 phi_{j+1} - 8 phi_{j-1} +
+ *     phi_{j-2})/12 in 1-D.
  *   - Initial populations: f_i(0) = feq_i(rho, u) of the scheme in use.
  */
 #include <math.h>
@@ -74,6 +81,8 @@ typedef struct {
   double rho_l; /* saturation liquid density, Eq. (36) */
   double rho_v; /* saturation vapour density, Eq. (36) */
   double rho0;  /* constant in the WB equilibrium, Eq. (24) */
+  int force_stencil; /* gradients of the force: 0 the isotropic central
+                        scheme (Sec. II), 1 the fourth-order form below */
 } orc_params;
 
 static inline int wrap(int a, int n) {
@@ -186,11 +195,34 @@ void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
   }
 }
 
+/* Fourth-order gradient: the isotropic central gradient of phi minus one
+ * sixth of the isotropic central gradient of lap(phi).  The central
+ * gradient's leading error is (1/6) grad(lap(phi)); subtracting it leaves a
+ * fourth-order error.  Periodic. */
+void orc_gradient4(int nx, int ny, const double *phi, double *gx, double *gy) {
+  size_t n = (size_t)nx * ny;
+  double *lap = (double *)malloc(n * sizeof(double));
+  double *lx = (double *)malloc(n * sizeof(double));
+  double *ly = (double *)malloc(n * sizeof(double));
+  orc_laplacian(nx, ny, phi, lap);
+  orc_gradient(nx, ny, phi, gx, gy);
+  orc_gradient(nx, ny, lap, lx, ly);
+  for (size_t k = 0; k < n; ++k) {
+    gx[k] -= lx[k] / 6.0;
+    gy[k] -= ly[k] / 6.0;
+  }
+  free(lap);
+  free(lx);
+  free(ly);
+}
+
 /* All macroscopic fields at time t from the populations f(t).
  *   rho = sum_i f_i                                         (Eq. 4)
  *   mu  = mu0(rho) - kappa lap(rho)                         (Sec. II, Eq. 37)
  *   F   = grad(cs2 rho) - rho grad(mu)  (standard, Eq. 6)
  *       = -rho grad(mu)                 (WB, Eq. 25)
+ *   (grad: the central gradient, or the fourth-order one with
+ *    force_stencil = 1)
  *   u   = (sum_i c_i f_i + F/2) / rho                       (Eq. 4)
  * Any output pointer may be NULL except those the next step needs; scratch is
  * allocated here. */
@@ -209,8 +241,13 @@ void orc_macro(int scheme, const orc_params *p, int nx, int ny,
   }
   orc_laplacian(nx, ny, rho, lap);
   for (size_t k = 0; k < n; ++k) mu[k] = orc_mu0(p, rho[k]) - p->kappa * lap[k];
-  orc_gradient(nx, ny, mu, gmx, gmy);
-  orc_gradient(nx, ny, rho, grx, gry);
+  if (p->force_stencil == 1) {
+    orc_gradient4(nx, ny, mu, gmx, gmy);
+    orc_gradient4(nx, ny, rho, grx, gry);
+  } else {
+    orc_gradient(nx, ny, mu, gmx, gmy);
+    orc_gradient(nx, ny, rho, grx, gry);
+  }
   for (size_t k = 0; k < n; ++k) {
     double fx = -rho[k] * gmx[k];
     double fy = -rho[k] * gmy[k];

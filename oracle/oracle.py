@@ -54,22 +54,27 @@ def build(force: bool = False) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("beta", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("rho_l", ctypes.c_double),
-                ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double)]
+                ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("force_stencil", ctypes.c_int)]
 
 
 @dataclass(frozen=True)
 class Params:
     """Physical parameters in lattice units (Eq. 2 tau; Eq. 36 beta, rho_l,
-    rho_v; kappa of mu = mu0 - kappa lap rho; rho0 of Eq. 24)."""
+    rho_v; kappa of mu = mu0 - kappa lap rho; rho0 of Eq. 24; force_stencil:
+    0 the central gradients of Sec. II in the force, 1 the fourth-order ones
+    of ``gradient4``)."""
     tau: float
     beta: float
     kappa: float
     rho_l: float
     rho_v: float
     rho0: float = 0.0
+    force_stencil: int = 0
 
     def c(self) -> _Params:
-        return _Params(self.tau, self.beta, self.kappa, self.rho_l, self.rho_v, self.rho0)
+        return _Params(self.tau, self.beta, self.kappa, self.rho_l, self.rho_v, self.rho0,
+                       int(self.force_stencil))
 
 
 _lib = None
@@ -89,6 +94,7 @@ def _load():
             "orc_feq": (None, [i, P, d, d, d, _D]),
             "orc_forcing": (None, [i, d, d, d, d, d, d, _D]),
             "orc_gradient": (None, [i, i, _D, _D, _D]),
+            "orc_gradient4": (None, [i, i, _D, _D, _D]),
             "orc_laplacian": (None, [i, i, _D, _D]),
             "orc_macro": (None, [i, P, i, i, _D] + [_D] * 8),
             "orc_fields": (None, [i, P, i, i, _D, _D, _D, _D, _D]),
@@ -162,6 +168,17 @@ def gradient(phi: np.ndarray):
     ny, nx = phi.shape
     gx, gy = np.empty_like(phi), np.empty_like(phi)
     _load().orc_gradient(nx, ny, _ptr(phi), _ptr(gx), _ptr(gy))
+    return gx, gy
+
+
+def gradient4(phi: np.ndarray):
+    """Fourth-order gradient: the central gradient of phi minus 1/6 of the
+    central gradient of its isotropic Laplacian, periodic (the force-stencil
+    variant; 1-D: (-phi_{j+2} + 8 phi_{j+1} - 8 phi_{j-1} + phi_{j-2})/12)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    ny, nx = phi.shape
+    gx, gy = np.empty_like(phi), np.empty_like(phi)
+    _load().orc_gradient4(nx, ny, _ptr(phi), _ptr(gx), _ptr(gy))
     return gx, gy
 
 

@@ -52,6 +52,11 @@ bool valid_params(const lbm_params* p, std::string* why) {
     return *why = "densities must be finite", false;
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED)
     return *why = "unknown precision", false;
+  if (p->force_stencil != 0 && p->force_stencil != 1) return *why = "force_stencil must be 0 or 1", false;
+  if (p->force_stencil == 1 && p->precision != LBM_FP64)
+    return *why = "the fourth-order force stencil is FP64 only", false;
+  if (p->force_stencil == 1 && p->ny > 65535)
+    return *why = "the fourth-order force stencil needs ny <= 65535", false;
   return true;
 }
 
@@ -198,8 +203,14 @@ void drop_graphs(lbm_ctx* c) {
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   const lbmk::Physics ph = make_physics(c->prm, scheme);
   for (int64_t k = 0; k < n; ++k) {
-    HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
-                                c->buf(1 - c->cur), s));
+    if (c->prm.force_stencil == 1) {
+      // rho and mu of the step go through the staging fields 0 and 3
+      HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->buf(c->cur), c->buf(1 - c->cur),
+                                   c->staging(), c->staging() + 3 * c->nodes(), s));
+    } else {
+      HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
+                                  c->buf(1 - c->cur), s));
+    }
     c->cur = 1 - c->cur;
   }
   return LBM_OK;
@@ -353,14 +364,20 @@ lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* 
   lbmk::ObserveOut o{rho ? st : nullptr, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
                      mu ? st + 3 * n : nullptr, c->partials()};
   const lbmk::Physics ph = make_physics(c->prm, c->scheme);
-  HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,
-                                 c->stream));
+  if (c->prm.force_stencil == 1) {
+    // the variant always computes rho and mu into staging fields 0 and 3
+    HIPCHK(c, lbmk::launch_observe4(c->scheme, c->L.g, ph, c->state(), st, st + 3 * n, o,
+                                    c->stream));
+  } else {
+    HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,
+                                   c->stream));
+  }
   const size_t fb = (size_t)n * sizeof(double);
   if (rho) HIPCHK(c, hipMemcpyAsync(rho, st, fb, hipMemcpyDeviceToHost, c->stream));
   if (ux) HIPCHK(c, hipMemcpyAsync(ux, st + n, fb, hipMemcpyDeviceToHost, c->stream));
   if (uy) HIPCHK(c, hipMemcpyAsync(uy, st + 2 * n, fb, hipMemcpyDeviceToHost, c->stream));
   if (mu) HIPCHK(c, hipMemcpyAsync(mu, st + 3 * n, fb, hipMemcpyDeviceToHost, c->stream));
-  const int nb = c->tl.blocks();
+  const int nb = c->prm.force_stencil == 1 ? lbmk::stencil4_blocks(c->L.g) : c->tl.blocks();
   std::vector<double> part((size_t)nb * 4);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->partials(), part.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
@@ -493,7 +510,7 @@ const char* lbm_last_error(const lbm_ctx* c) {
   return c ? c->err.c_str() : g_thread_error.c_str();
 }
 
-int32_t lbm_kernels_per_step(const lbm_ctx*) { return 1; }
+int32_t lbm_kernels_per_step(const lbm_ctx* c) { return c && c->prm.force_stencil == 1 ? 3 : 1; }
 
 }  // extern "C"
 
@@ -783,6 +800,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
+  if (p->force_stencil != 0) return bfail(b, LBM_EINVAL, "batches use the central force stencil");
   int idx = -1;
   for (int i = 0; i < b->max_slots; ++i)
     if (b->slots[i].status == LBM_SLOT_FREE) {

@@ -484,6 +484,161 @@ __device__ __forceinline__ long long src_offset(const Geometry& g, int q, int x,
   return (long long)ys * g.pitch + xs;
 }
 
+// ---------------------------------------------------------------------------
+// Force-stencil variant (Sec. II, after Eq. 23): the gradients of the force
+// (and of Eq. 26) use the fourth-order form grad(phi) - (1/6) grad(lap phi)
+// of the central gradient and the isotropic Laplacian above, which removes
+// the central gradient's isotropic second-order error (1-D:
+// (-phi_{j+2} + 8 phi_{j+1} - 8 phi_{j-1} + phi_{j-2})/12).  The paper's
+// point is that this shrinks the net force of the standard scheme at
+// equilibrium but cannot remove it.  FP64, three passes per step: density,
+// chemical potential, then collide-stream on LDS tiles of rho and mu with a
+// 2-node halo.  Expanded, the x-derivative's 5 x 5 weights are, for rows
+// dy = 0, +-1, +-2 and columns dx = 1, 2 (odd in dx):
+//   dy = 0:   1/2,    -1/24
+//   dy = +-1: 5/54,   -1/54
+//   dy = +-2: -1/108, -1/432
+// and the y-derivative's are their transpose.
+
+// Pass 1: rho = sum_i f_i of every node (pulled populations, Eq. 4).
+__global__ void __launch_bounds__(256)
+    density4(Geometry g, const Global<double>* __restrict__ fin, double* __restrict__ rho) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  double f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src_offset(g, i, x, y)];
+  rho[(long long)y * g.nx + x] = sum9(f);
+}
+
+// Pass 2: mu = mu0(rho) - kappa lap(rho), 9-point isotropic Laplacian.
+__global__ void __launch_bounds__(256)
+    potential4(Geometry g, Physics phys, const double* __restrict__ rho, double* __restrict__ mu) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  if (x >= g.nx) return;
+  const PhysR<double> p = to_r<double>(phys);
+  const int xw = x == 0 ? g.nx - 1 : x - 1, xe = x + 1 == g.nx ? 0 : x + 1;
+  const int ys = y == 0 ? g.ny - 1 : y - 1, yn = y + 1 == g.ny ? 0 : y + 1;
+  const double* r0 = rho + (long long)y * g.nx;
+  const double* rs = rho + (long long)ys * g.nx;
+  const double* rn = rho + (long long)yn * g.nx;
+  const double c = r0[x];
+  const double ax = (r0[xe] + r0[xw]) + (rs[x] + rn[x]);
+  const double dg = (rs[xe] + rs[xw]) + (rn[xe] + rn[xw]);
+  const double lap = (4.0 * ax + dg - 20.0 * c) * (1.0 / 6.0);
+  mu[(long long)y * g.nx + x] = mu0(c, p) - p.kappa * lap;
+}
+
+constexpr int S4X = 64, S4Y = 4;  // collide-stream tile (threads)
+
+// Fourth-order gradient of a (S4Y+4) x (S4X+4) LDS tile at tile point (i, j).
+__device__ __forceinline__ void grad4(const double (&a)[S4Y + 4][S4X + 4], int i, int j,
+                                      double& gx, double& gy) {
+  auto dx1 = [&](int r) { return a[r][j + 1] - a[r][j - 1]; };
+  auto dx2 = [&](int r) { return a[r][j + 2] - a[r][j - 2]; };
+  auto dy1 = [&](int c) { return a[i + 1][c] - a[i - 1][c]; };
+  auto dy2 = [&](int c) { return a[i + 2][c] - a[i - 2][c]; };
+  gx = 0.5 * dx1(i) - (1.0 / 24.0) * dx2(i) + (5.0 / 54.0) * (dx1(i + 1) + dx1(i - 1)) -
+       (1.0 / 54.0) * (dx2(i + 1) + dx2(i - 1)) - (1.0 / 108.0) * (dx1(i + 2) + dx1(i - 2)) -
+       (1.0 / 432.0) * (dx2(i + 2) + dx2(i - 2));
+  gy = 0.5 * dy1(j) - (1.0 / 24.0) * dy2(j) + (5.0 / 54.0) * (dy1(j + 1) + dy1(j - 1)) -
+       (1.0 / 54.0) * (dy2(j + 1) + dy2(j - 1)) - (1.0 / 108.0) * (dy1(j + 2) + dy1(j - 2)) -
+       (1.0 / 432.0) * (dy2(j + 2) + dy2(j - 2));
+}
+
+// Pass 3: force with the fourth-order gradients, velocity, equilibrium,
+// forcing term and BGK of every node; the post-collision populations stay at
+// their node (pull form, as in the fused step).  With OBSERVE it writes the
+// fields and per-block partials (max|u|, mass, kinetic energy, non-finite)
+// instead of stepping.
+template <int SCHEME, bool OBSERVE>
+__global__ void __launch_bounds__(S4X * S4Y)
+    collide4(Geometry g, Physics phys, const Global<double>* __restrict__ fin,
+             Global<double>* __restrict__ fout, const double* __restrict__ rho,
+             const double* __restrict__ mu, ObserveOut obs) {
+  __shared__ double rt[S4Y + 4][S4X + 4];
+  __shared__ double mt[S4Y + 4][S4X + 4];
+  const PhysR<double> p = to_r<double>(phys);
+  const int tx = threadIdx.x % S4X, ty = threadIdx.x / S4X;
+  const int x0 = blockIdx.x * S4X, y0 = blockIdx.y * S4Y;
+  for (int e = threadIdx.x; e < (S4Y + 4) * (S4X + 4); e += S4X * S4Y) {
+    const int i = e / (S4X + 4), j = e - i * (S4X + 4);
+    int yy = (y0 + i - 2) % g.ny, xx = (x0 + j - 2) % g.nx;
+    yy = yy < 0 ? yy + g.ny : yy;
+    xx = xx < 0 ? xx + g.nx : xx;
+    const long long o = (long long)yy * g.nx + xx;
+    rt[i][j] = rho[o];
+    mt[i][j] = mu[o];
+  }
+  __syncthreads();
+  const int x = x0 + tx, y = y0 + ty;
+  double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
+  if (x < g.nx && y < g.ny) {
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src_offset(g, i, x, y)];
+    const double r = rt[ty + 2][tx + 2];
+    double grx, gry, gmx, gmy;
+    grad4(rt, ty + 2, tx + 2, grx, gry);
+    grad4(mt, ty + 2, tx + 2, gmx, gmy);
+    double Fx = -r * gmx, Fy = -r * gmy;
+    if (SCHEME == STANDARD) {
+      Fx += grx * (1.0 / 3.0);
+      Fy += gry * (1.0 / 3.0);
+    }
+    double ux, uy;
+    velocity(f, r, Fx, Fy, ux, uy);
+    if (!OBSERVE) {
+      collide<double, SCHEME>(f, r, r, ux, uy, Fx, Fy, grx, gry, p);
+      Global<double>* dst = fout + (long long)y * g.pitch + x;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + (long long)i * g.plane);
+    } else {
+      const long long o = (long long)y * g.nx + x;
+      if (obs.ux) obs.ux[o] = ux;
+      if (obs.uy) obs.uy[o] = uy;
+      const double u2 = ux * ux + uy * uy;
+      const double um = sqrt(u2);
+      if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
+      umax = um;
+      mass = r;
+      ekin = 0.5 * r * u2;
+    }
+  }
+  if (OBSERVE && obs.partials) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      umax = fmax(umax, __shfl_xor(umax, off));
+      bad = fmax(bad, __shfl_xor(bad, off));
+      mass += __shfl_xor(mass, off);
+      ekin += __shfl_xor(ekin, off);
+    }
+    __shared__ double red[S4Y][4];
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      red[wv][0] = umax;
+      red[wv][1] = mass;
+      red[wv][2] = ekin;
+      red[wv][3] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, m = 0.0, e = 0.0, z = 0.0;
+      for (int w = 0; w < S4Y; ++w) {
+        a = fmax(a, red[w][0]);
+        m += red[w][1];
+        e += red[w][2];
+        z = fmax(z, red[w][3]);
+      }
+      double* out = obs.partials + 4LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x);
+      out[0] = a;
+      out[1] = m;
+      out[2] = e;
+      out[3] = z;
+    }
+  }
+}
+
 // f = feq(rho, u) - s from dense fields; arithmetic in double, stored as T.
 template <typename T, int SCHEME>
 __global__ void init_kernel(Geometry g, Physics phys, const double* __restrict__ rho,
@@ -699,6 +854,43 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,
                           const Tiling& t, const void* f, const ObserveOut& o, hipStream_t s) {
   return launch_march<true>(storage, scheme, g, ph, t, f, nullptr, o, s);
+}
+
+int stencil4_blocks(const Geometry& g) {
+  return ((g.nx + S4X - 1) / S4X) * ((g.ny + S4Y - 1) / S4Y);
+}
+
+namespace {
+
+template <bool OBS>
+hipError_t launch4(int scheme, const Geometry& g, const Physics& ph, const void* fin, void* fout,
+                   double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
+  const dim3 g1((g.nx + 255) / 256, g.ny);
+  const auto* in = (const Global<double>*)(const double*)fin;
+  auto* out = (Global<double>*)(double*)fout;
+  hipLaunchKernelGGL(density4, g1, dim3(256), 0, s, g, in, rho);
+  hipLaunchKernelGGL(potential4, g1, dim3(256), 0, s, g, ph, (const double*)rho, mu);
+  const dim3 g3((g.nx + S4X - 1) / S4X, (g.ny + S4Y - 1) / S4Y);
+  if (scheme == STANDARD)
+    hipLaunchKernelGGL((collide4<STANDARD, OBS>), g3, dim3(S4X * S4Y), 0, s, g, ph, in, out,
+                       (const double*)rho, (const double*)mu, o);
+  else
+    hipLaunchKernelGGL((collide4<WELL_BALANCED, OBS>), g3, dim3(S4X * S4Y), 0, s, g, ph, in, out,
+                       (const double*)rho, (const double*)mu, o);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step4(int scheme, const Geometry& g, const Physics& ph, const void* fin,
+                        void* fout, double* rho, double* mu, hipStream_t s) {
+  const ObserveOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
+  return launch4<false>(scheme, g, ph, fin, fout, rho, mu, none, s);
+}
+
+hipError_t launch_observe4(int scheme, const Geometry& g, const Physics& ph, const void* f,
+                           double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
+  return launch4<true>(scheme, g, ph, f, nullptr, rho, mu, o, s);
 }
 
 hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics& ph,

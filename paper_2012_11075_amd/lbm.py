@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("rho_l", ctypes.c_double),
                 ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("shift_all", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("shift_all", ctypes.c_int32),
+                ("force_stencil", ctypes.c_int32)]
 
 
 class Observation(ctypes.Structure):
@@ -121,12 +122,15 @@ def _scheme(s) -> int:
 
 
 def make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                rho_ref=None, shift_all=False) -> Params:
+                rho_ref=None, shift_all=False, force_stencil=0) -> Params:
+    """force_stencil: 0 the central gradients of Sec. II in the force, 1 the
+    fourth-order ones (FP64 single lattices only)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     if rho_ref is None:
         rho_ref = 0.5 * (rho_l + rho_v)
     return Params(int(nx), int(ny), float(tau), float(beta), float(kappa), float(rho_l),
-                  float(rho_v), float(rho0), float(rho_ref), prec, int(bool(shift_all)))
+                  float(rho_v), float(rho0), float(rho_ref), prec, int(bool(shift_all)),
+                  int(force_stencil))
 
 
 def stream_handle(stream=None) -> int:
@@ -139,11 +143,11 @@ class Solver:
     """One periodic lattice on the current HIP device."""
 
     def __init__(self, nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                 rho_ref=None, shift_all=False, stream=None):
+                 rho_ref=None, shift_all=False, stream=None, force_stencil=0):
         import torch
         self.lib = load()
         self.params = make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0, precision,
-                                  rho_ref, shift_all)
+                                  rho_ref, shift_all, force_stencil)
         self.nx, self.ny = int(nx), int(ny)
         nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:

@@ -30,6 +30,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--depth", type=int, default=0)
+    ap.add_argument("--force-stencil", type=int, default=0,
+                    help="1: the fourth-order force-stencil variant (FP64, three kernels per step)")
     ap.add_argument("--batch", type=int, default=0,
                     help="profile the batched launch over this many uneven instances instead")
     args = ap.parse_args()
@@ -41,7 +43,7 @@ def main():
         calibrate(args, torch)
         return
     prob = I.PROBLEMS[args.problem]
-    s = lbm.Solver.for_problem(prob, precision=args.precision)
+    s = lbm.Solver.for_problem(prob, precision=args.precision, force_stencil=args.force_stencil)
     tile = (args.block, args.rows, args.depth) if (args.block or args.rows or args.depth) else \
         tune.bench_tile(prob.nx, prob.ny, args.precision)
     s.set_tile(*tile)

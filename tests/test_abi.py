@@ -35,8 +35,25 @@ def test_workspace_bytes_rejects_bad_params(lib):
     for bad in [P(0, 4, 1.0, 0.1, 0.02, 1, 0.1), P(4, -1, 1.0, 0.1, 0.02, 1, 0.1),
                 P(4, 4, 0.5, 0.1, 0.02, 1, 0.1), P(4, 4, float("nan"), 0.1, 0.02, 1, 0.1),
                 P(4, 4, 1.0, -0.1, 0.02, 1, 0.1), P(4, 4, 1.0, 0.1, -1.0, 1, 0.1),
-                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision=7)]:
+                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision=7),
+                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=2),
+                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision="fp32s", force_stencil=1),
+                P(4, 70000, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1)]:
         assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    # the fourth-order force stencil is accepted in FP64
+    good = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1)
+    assert lib.lbm_workspace_bytes(ctypes.byref(good)) > 0
+
+
+def test_params_struct_matches_header(lib):
+    """lbm_params as ctypes lays it out: the field order of include/lbm.h."""
+    import re
+    with open(os.path.join(ROOT, "include", "lbm.h")) as fh:
+        text = fh.read()
+    body = re.search(r"typedef struct \{(.*?)\} lbm_params;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)\s*[,;]", body)
+    assert names == [f[0] for f in lbm.Params._fields_], names
 
 
 def test_workspace_bytes_layout(lib):

@@ -95,6 +95,57 @@ def test_parity_wb_rho0(orc, lbm, rho0):
     compare(orc, lbm, prob, "well_balanced", 1000)
 
 
+STENCIL4 = [(64, 48, 1000), (37, 53, 200), (1, 7, 200), (7, 1, 200), (2, 2, 200), (5, 300, 200),
+            (300, 5, 200), (129, 130, 200)]
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+@pytest.mark.parametrize("nx,ny,steps", STENCIL4)
+def test_parity_force_stencil4(orc, lbm, nx, ny, steps, scheme):
+    """Force-stencil variant (fourth-order gradients in the force and in
+    Eq. 26; three kernels per step) against the oracle's composition of its
+    own stencils, including lattices smaller than the 5 x 5 stencil."""
+    prob = I.with_size(I.PAPER_DROPLET, nx, ny)
+    ph = prob.physics
+    print("parity case force_stencil=1", nx, ny, scheme, steps, flush=True)
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
+    rho0 = prob.rho()
+    fo = orc.step(scheme, p, orc.init(scheme, p, rho0), steps)
+    ro, uxo, uyo, muo = orc.fields(scheme, p, fo)
+    oo = orc.observe(scheme, p, fo)
+    assert np.isfinite(fo).all() and ro.min() > 0
+    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    assert s.lib.lbm_kernels_per_step(s.ctx) == 3
+    s.init(rho0, scheme=scheme)
+    s.step(steps, scheme)
+    fg = to_oracle(s.get_populations())
+    ob = s.observe()
+    s.close()
+    assert np.abs(fg - fo).max() <= TOL
+    assert np.abs(ob["rho"] - ro).max() <= TOL
+    assert np.abs(ob["ux"] - uxo).max() <= TOL
+    assert np.abs(ob["uy"] - uyo).max() <= TOL
+    assert np.abs(ob["mu"] - muo).max() <= 1e-9 * max(1.0, np.abs(muo).max())
+    assert abs(ob["max_u"] - oo["max_u"]) <= TOL
+    assert abs(ob["mass"] - oo["mass"]) <= 1e-12 * oo["mass"]
+
+
+def test_force_stencil4_graph_replay_bit_exact(lbm):
+    """The three-kernel step captured in graphs gives the populations of the
+    same steps launched one by one."""
+    prob = I.with_size(I.PAPER_DROPLET, 96, 80)
+    out = []
+    for graph in (0, 16):
+        s = lbm.Solver.for_problem(prob, force_stencil=1)
+        s.set_graph_steps(graph)
+        s.init(prob.rho(), scheme="standard")
+        s.step(64, "standard")
+        s.step(3, "standard")
+        out.append(s.get_populations())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
 RAGGED = [(37, 53), (1, 7), (7, 1), (1, 1), (2, 2), (300, 5), (5, 300), (253, 3), (505, 9),
           (129, 130)]
 

@@ -123,6 +123,78 @@ def test_stencils_exact_on_quadratics(orc):
     np.testing.assert_allclose(lap[s], 0.002 - 0.003, atol=1e-13)
 
 
+def test_fourth_order_gradient_exact_on_cubics(orc):
+    """The force-stencil variant's gradient (the higher-order discretisation
+    discussed after Eq. 23) is exact for cubic fields away from the periodic
+    seam, where the central gradient is off by grad(lap)/6, and on a field
+    that varies along y only it is the textbook five-point derivative."""
+    ny, nx = 24, 28
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = (0.3 + 0.02 * x - 0.05 * y + 0.001 * x * x + 0.002 * x * y - 0.0015 * y * y
+           + 1e-4 * x ** 3 - 2e-4 * x * x * y + 3e-4 * x * y * y + 5e-5 * y ** 3)
+    gx, gy = orc.gradient4(phi)
+    ex = 0.02 + 0.002 * x + 0.002 * y + 3e-4 * x * x - 4e-4 * x * y + 3e-4 * y * y
+    ey = -0.05 + 0.002 * x - 0.003 * y - 2e-4 * x * x + 6e-4 * x * y + 1.5e-4 * y * y
+    s = (slice(3, ny - 3), slice(3, nx - 3))
+    np.testing.assert_allclose(gx[s], ex[s], atol=1e-12)
+    np.testing.assert_allclose(gy[s], ey[s], atol=1e-12)
+    cx, _ = orc.gradient(phi)
+    assert np.abs(cx[s] - ex[s]).max() > 1e-4
+    prof = np.random.default_rng(3).normal(size=31)
+    field = np.ascontiguousarray(np.broadcast_to(prof[:, None], (31, 5)))
+    _, g1 = orc.gradient4(field)
+    five = (-np.roll(prof, -2) + 8 * np.roll(prof, -1) - 8 * np.roll(prof, 1) + np.roll(prof, 2)) / 12
+    np.testing.assert_allclose(g1[:, 2], five, atol=1e-14)
+
+
+def test_fourth_order_gradient_converges_at_fourth_order(orc):
+    """On a smooth periodic field the variant's gradient error falls as h^4
+    (the central gradient's as h^2)."""
+    errs4, errs2, ns = [], [], [16, 32, 64]
+    for n in ns:
+        y, x = np.mgrid[0:n, 0:n].astype(float)
+        k = 2 * np.pi / n
+        phi = np.sin(k * x + 2 * k * y) + 0.5 * np.cos(3 * k * x - k * y)
+        ex = k * np.cos(k * x + 2 * k * y) - 1.5 * k * np.sin(3 * k * x - k * y)
+        g4, _ = orc.gradient4(phi)
+        g2, _ = orc.gradient(phi)
+        errs4.append(np.abs(g4 - ex).max() / k)
+        errs2.append(np.abs(g2 - ex).max() / k)
+    o4 = np.polyfit(np.log(ns), np.log(errs4), 1)[0]
+    o2 = np.polyfit(np.log(ns), np.log(errs2), 1)[0]
+    assert -4.3 < o4 < -3.7 and -2.2 < o2 < -1.8, (o4, o2)
+
+
+def test_net_force_structure_at_equilibrium(orc):
+    """Eqs. (21)-(23): at the equilibrium state S (mu = const, u = 0) of a flat
+    interface the standard LBE's discrete momentum balance leaves the net
+    force Delta F = cs2 (delta^F - delta^LB) rho.  With the central gradient
+    this is, exactly, cs2 (rho_{j+2} - 2 rho_{j+1} + 2 rho_{j-1} - rho_{j-2})/8
+    (about dx^2 d3rho/dy3 / 12, Eq. 23); with the fourth-order gradient it
+    tends to a third of that as the interface widens (about dx^2 d3rho/dy3
+    / 36): a better delta^F shrinks the net force but cannot remove it."""
+    ratios = []
+    for beta in [0.01, 0.000625, 0.00015625]:
+        dF = {}
+        for st in (0, 1):
+            p = orc.Params(0.85, beta, 0.0128, 1.0, 0.2, 0.0, st)
+            W = orc.equilibrium_width(p)
+            n = int(12 * W) * 2 + 1
+            guess = I.tanh_slab(n, 1.0, 0.2, n / 4 + 0.5, 3 * n / 4 - 0.5, W)
+            prof, _ = _discrete_flat_equilibrium(p, n, guess.sum(), guess)
+            rho = np.ascontiguousarray(np.broadcast_to(prof[:, None], (n, 3)))
+            m = orc.macro("standard", p, orc.init("standard", p, rho))
+            r, F = m["rho"][:, 0], m["Fy"][:, 0]
+            dF[st] = (-CS2 * (np.roll(r, -1) - np.roll(r, 1)) / 2
+                      + (np.roll(F, -1) + 2 * F + np.roll(F, 1)) / 4)
+            if st == 0:
+                exact = CS2 * (np.roll(r, -2) - 2 * np.roll(r, -1) + 2 * np.roll(r, 1)
+                               - np.roll(r, 2)) / 8
+                np.testing.assert_allclose(dF[0], exact, atol=1e-14)
+        ratios.append(np.abs(dF[0]).max() / np.abs(dF[1]).max())
+    assert ratios[0] < ratios[1] < ratios[2] and 2.9 < ratios[2] < 3.05, ratios
+
+
 # ---------------------------------------------------------------- dynamics
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_mass_conservation(orc, scheme):
@@ -503,6 +575,18 @@ def test_paper_flat_standard_discrete_balance(orc, paper_flat_steady):
     scale = np.abs(CS2 * (np.roll(rho, -1) - np.roll(rho, 1)) / 2).max()
     assert scale > 1e-2
     assert np.abs(lhs).max() < 1e-5 * scale
+
+
+def test_paper_flat_fourth_order_force_keeps_spurious_velocity(orc, paper_flat_steady):
+    """Sec. II, after Eq. (23): with the higher-order gradient in the force the
+    standard LBE's steady spurious velocity on the paper's flat interface is
+    smaller than with the central gradient but does not vanish."""
+    p, st = paper_flat_steady
+    u2 = orc.observe("standard", p, st["standard"])["max_u"]
+    p4 = orc.Params(p.tau, p.beta, p.kappa, p.rho_l, p.rho_v, p.rho0, 1)
+    f = orc.step("standard", p4, orc.init("standard", p4, I.initial_density(I.PAPER_FLAT)), 30_000)
+    u4 = orc.observe("standard", p4, f)["max_u"]
+    assert 1e-9 < u4 < u2 / 1.5, (u4, u2)
 
 
 def test_paper_flat_wb_chemical_potential_nearly_constant(orc, paper_flat_steady):
