@@ -25,6 +25,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
+SRC3 = os.path.join(HERE, "lbm_oracle3d.c")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD_DIR, "liboracle.so")
 
@@ -40,12 +41,13 @@ CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fused multiply-add, OpenMP rows)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(LIB) and \
+            os.path.getmtime(LIB) >= max(os.path.getmtime(SRC), os.path.getmtime(SRC3)):
         return LIB
     os.makedirs(BUILD_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, SRC3, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -101,6 +103,14 @@ def _load():
             "orc_init": (None, [i, P, i, i, _D, _D, _D, _D]),
             "orc_step": (None, [i, P, i, i, _D, i64]),
             "orc_observe": (None, [i, P, i, i, _D, _D]),
+            "orc3_feq": (None, [i, P, d, d, d, d, _D]),
+            "orc3_forcing": (None, [i] + [d] * 9 + [_D]),
+            "orc3_gradient": (None, [i, i, i, _D, _D, _D, _D]),
+            "orc3_laplacian": (None, [i, i, i, _D, _D]),
+            "orc3_macro": (None, [i, P, i, i, i, _D] + [_D] * 11),
+            "orc3_init": (None, [i, P, i, i, i, _D, _D, _D, _D, _D]),
+            "orc3_step": (None, [i, P, i, i, i, _D, i64]),
+            "orc3_observe": (None, [i, P, i, i, i, _D, _D]),
             "orc_set_threads": (None, [i]),
             "orc_get_threads": (i, []),
         }
@@ -275,3 +285,76 @@ def droplet_diagnostics(p: Params, rho: np.ndarray, cx: float, cy: float) -> dic
         "dp": p0(p, rho_in) - p0(p, rho_out),
         "r_eff": float(np.sqrt(max(area, 0.0) / np.pi)),
     }
+
+
+# ------------------------------------------------------- three dimensions (D3Q19)
+# Populations: shape (nz, ny, nx, 19); fields: (nz, ny, nx).  Velocities:
+# rest, the six axis directions, the twelve edge directions (order of C3).
+C3 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+               [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+               [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+
+
+def feq3(scheme, p: Params, rho, ux, uy, uz) -> np.ndarray:
+    """D3Q19 equilibrium: Eq. (3) standard, Eq. (24) well-balanced."""
+    out = np.zeros(19)
+    _load().orc3_feq(_scheme(scheme), ctypes.byref(p.c()), rho, ux, uy, uz, _ptr(out))
+    return out
+
+
+def forcing3(scheme, u, F, gr=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """D3Q19 forcing term: Eq. (5) standard, Eq. (26) with D = 3."""
+    out = np.zeros(19)
+    _load().orc3_forcing(_scheme(scheme), *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
+    return out
+
+
+def gradient3(phi: np.ndarray):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    g = [np.empty_like(phi) for _ in range(3)]
+    _load().orc3_gradient(nx, ny, nz, _ptr(phi), *[_ptr(a) for a in g])
+    return tuple(g)
+
+
+def laplacian3(phi: np.ndarray) -> np.ndarray:
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    out = np.empty_like(phi)
+    _load().orc3_laplacian(nx, ny, nz, _ptr(phi), _ptr(out))
+    return out
+
+
+def macro3(scheme, p: Params, f: np.ndarray) -> dict:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nz, ny, nx, _ = f.shape
+    names = ["rho", "ux", "uy", "uz", "mu", "Fx", "Fy", "Fz", "grx", "gry", "grz"]
+    out = {k: np.empty((nz, ny, nx)) for k in names}
+    _load().orc3_macro(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f),
+                       *[_ptr(out[k]) for k in names])
+    return out
+
+
+def init3(scheme, p: Params, rho: np.ndarray, u=None) -> np.ndarray:
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    nz, ny, nx = rho.shape
+    comps = [None, None, None] if u is None else [np.ascontiguousarray(a, dtype=np.float64) for a in u]
+    f = np.empty((nz, ny, nx, 19))
+    _load().orc3_init(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(rho),
+                      *[_ptr(a) for a in comps], _ptr(f))
+    return f
+
+
+def step3(scheme, p: Params, f: np.ndarray, n: int = 1) -> np.ndarray:
+    g = np.array(f, dtype=np.float64, order="C", copy=True)
+    nz, ny, nx, _ = g.shape
+    _load().orc3_step(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(g), int(n))
+    return g
+
+
+def observe3(scheme, p: Params, f: np.ndarray) -> dict:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nz, ny, nx, _ = f.shape
+    out = np.zeros(4)
+    _load().orc3_observe(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
+    return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3])}
