@@ -294,6 +294,49 @@ def time_stencil4(prob, steps, warmup, scheme="standard"):
                         % (prob.name, scheme, steps)}
 
 
+D3_BYTES = 496         # FP64 bytes per node of the three-pass 3-D step
+D3_FUSED_BYTES = 304   # 19 populations read and written once
+
+
+def time_d3q19(steps, warmup, side=None):
+    """The 3-D (D3Q19) WB step on a side^3 droplet (FP64), three passes per
+    step: density (19 reads + 1 write), chemical potential (1 + 1),
+    collide-stream (19 + 2 reads, 19 writes) = 496 algorithmic bytes per
+    node (a single fused pass would need 304)."""
+    import torch
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm
+    n = side or I.DROPLET3_SIDE
+    ph = I.PHYS3
+    rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
+                             I.equilibrium_width(ph), 1e-3, seed=13)
+    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n)
+    s.init(rho, scheme="well_balanced")
+    del rho
+    s.step(warmup, "well_balanced")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps, "well_balanced")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ob = s.observe(fields=(), raise_nonfinite=False)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    nodes = n ** 3
+    gbs = D3_BYTES * nodes / (ms / 1e3) / 1e9
+    return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
+            "kernels_per_step": 3, "bytes_per_update": D3_BYTES, "fused_bytes_per_update": D3_FUSED_BYTES,
+            "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
+            "workload": "D3Q19 droplet %d^3, R=%g, rho_l=1, rho_v=0.1, beta=0.01, kappa=0.0128, tau=1, "
+                        "WB, FP64, %d steps" % (n, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE, steps)}
+
+
 def copy_reference(nx, ny):
     """The step's traffic without its arithmetic: `hbm_ceiling` (built next to
     the library) streams the nine population rows of every lattice row from
@@ -347,6 +390,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-finite", action="store_true")
     ap.add_argument("--no-stencil4", action="store_true")
+    ap.add_argument("--no-d3", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
@@ -410,6 +454,9 @@ def main():
     if not args.no_stencil4:
         out["force_stencil4"] = time_stencil4(prob, 200, 5)
         progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
+    if not args.no_d3:
+        out["d3q19"] = time_d3q19(100, 5)
+        progress("D3Q19 %.4f ms/step" % out["d3q19"]["ms_per_step"])
     if not args.no_batch:
         out["batched"] = {}
         for prec in ("fp32s", "fp64"):

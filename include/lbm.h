@@ -86,6 +86,13 @@ typedef struct {
                           * higher-order discretisation discussed after
                           * Eq. (23) (FP64 only, ny <= 65535, not in batches;
                           * three kernels per step instead of one) */
+  int32_t nz;            /* lattice depth: 0 or 1 for the 2-D D2Q9 lattice;
+                          * > 1 for the 3-D D3Q19 lattice of the same method
+                          * (Eqs. 24 and 26 hold for general dimension; here
+                          * D = 3).  3-D lattices are FP64 with the central
+                          * force stencil, single lattices only, ny and
+                          * nz <= 65535; three kernels per step.  Fields are
+                          * then double[nz][ny][nx]. */
 } lbm_params;
 
 typedef struct {
@@ -131,8 +138,20 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n, lbm_scheme scheme);
 lbm_status lbm_observe(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* mu,
                        lbm_observation* obs);
 
+/* 3-D forms of lbm_init and lbm_observe with the third velocity component
+ * (D3Q19 lattices; on a 2-D lattice uz must be NULL and they act as
+ * lbm_init / lbm_observe).  lbm_init3d takes ux, uy and uz together or none
+ * of them; lbm_init on a 3-D lattice accepts only u = 0. */
+lbm_status lbm_init3d(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                      const double* uz, lbm_scheme scheme);
+lbm_status lbm_observe3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz,
+                         double* mu, lbm_observation* obs);
+
 /* Copy the populations f_i (unshifted, double) to / from host
- * double[9][ny][nx].  Used for checkpoints and tests.  Synchronous.
+ * double[9][ny][nx] (3-D: double[19][nz][ny][nx], velocities in the order
+ * rest, +x, -x, +y, -y, +z, -z, then the edges (1,1,0), (-1,-1,0), (1,-1,0),
+ * (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1),
+ * (0,1,-1), (0,-1,1)).  Used for checkpoints and tests.  Synchronous.
  * lbm_set_populations makes the context initialised with `scheme` and sets
  * the step counter to `step`. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);

@@ -34,9 +34,12 @@ bool is_finite(double v) { return std::isfinite(v); }
 // Layout of a context's workspace.
 struct Layout {
   lbmk::Geometry g;
+  lbmk::Geometry3 g3;   // 3-D lattices (nz > 1) only
+  bool d3 = false;
+  int q = Q;            // populations per node: 9 (D2Q9) or 19 (D3Q19)
   size_t elem;
   size_t state_bytes;   // one population copy
-  size_t staging_bytes; // 4 dense double fields
+  size_t staging_bytes; // dense double fields: 4 (2-D: rho, ux, uy, mu) or 5 (3-D: + uz)
   size_t partial_count; // blocks of the smallest tiling
   size_t off_a, off_b, off_staging, off_partials, total;
 };
@@ -44,7 +47,9 @@ struct Layout {
 bool valid_params(const lbm_params* p, std::string* why) {
   if (!p) return *why = "params is NULL", false;
   if (p->nx < 1 || p->ny < 1) return *why = "nx and ny must be >= 1", false;
-  if ((long long)p->nx * p->ny > (1LL << 31)) return *why = "lattice larger than 2^31 nodes", false;
+  if (p->nz < 0) return *why = "nz must be >= 0", false;
+  if ((long long)p->nx * p->ny * std::max(1, p->nz) > (1LL << 31))
+    return *why = "lattice larger than 2^31 nodes", false;
   if (!is_finite(p->tau) || p->tau <= 0.5) return *why = "tau must be finite and > 1/2", false;
   if (!is_finite(p->beta) || p->beta < 0) return *why = "beta must be finite and >= 0", false;
   if (!is_finite(p->kappa) || p->kappa < 0) return *why = "kappa must be finite and >= 0", false;
@@ -57,6 +62,11 @@ bool valid_params(const lbm_params* p, std::string* why) {
     return *why = "the fourth-order force stencil is FP64 only", false;
   if (p->force_stencil == 1 && p->ny > 65535)
     return *why = "the fourth-order force stencil needs ny <= 65535", false;
+  if (p->nz > 1) {
+    if (p->precision != LBM_FP64) return *why = "3-D lattices are FP64 only", false;
+    if (p->force_stencil != 0) return *why = "3-D lattices use the central force stencil", false;
+    if (p->ny > 65535 || p->nz > 65535) return *why = "3-D lattices need ny, nz <= 65535", false;
+  }
   return true;
 }
 
@@ -76,6 +86,22 @@ Layout make_layout(const lbm_params& p) {
   const size_t strips = (p.nx + MIN_BLOCK - 1) / MIN_BLOCK;
   const size_t chunks = (p.ny + MIN_ROWS - 1) / MIN_ROWS;
   L.partial_count = strips * chunks;
+  if (p.nz > 1) {
+    // D3Q19, f[z][y][q][x]: the 19 population rows of a lattice row are
+    // contiguous, as in two dimensions
+    L.d3 = true;
+    L.q = lbmk::Q3;
+    L.g3.nx = p.nx;
+    L.g3.ny = p.ny;
+    L.g3.nz = p.nz;
+    L.g3.plane = (long long)px;
+    L.g3.pitch = (long long)lbmk::Q3 * px;
+    L.g3.slab = L.g3.pitch * p.ny;
+    const size_t n = (size_t)p.nx * p.ny * p.nz;
+    L.state_bytes = align_up((size_t)p.nz * p.ny * lbmk::Q3 * px * L.elem, ALIGN);
+    L.staging_bytes = align_up(5 * n * sizeof(double), ALIGN);
+    L.partial_count = (size_t)lbmk::blocks3(L.g3);
+  }
   L.off_a = 0;
   L.off_b = L.off_a + L.state_bytes;
   L.off_staging = L.off_b + L.state_bytes;
@@ -124,6 +150,18 @@ lbmk::Physics make_physics(const lbm_params& p, int scheme) {
   return ph;
 }
 
+lbmk::Physics3 make_physics3(const lbm_params& p) {
+  lbmk::Physics3 ph{};
+  ph.omega = 1.0 / p.tau;
+  ph.fpre = 1.0 - 0.5 / p.tau;
+  ph.beta = p.beta;
+  ph.kappa = p.kappa;
+  ph.rho_l = p.rho_l;
+  ph.rho_v = p.rho_v;
+  ph.rho0 = p.rho0;
+  return ph;
+}
+
 lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows, int depth) {
   lbmk::Tiling t{};
   t.block = block;
@@ -167,7 +205,8 @@ struct lbm_ctx {
   double* staging() const { return (double*)(ws + L.off_staging); }
   double* partials() const { return (double*)(ws + L.off_partials); }
   int storage() const { return prm.precision == LBM_FP64 ? lbmk::FP64 : lbmk::FP32; }
-  long long nodes() const { return (long long)prm.nx * prm.ny; }
+  long long nodes() const { return (long long)prm.nx * prm.ny * std::max(1, prm.nz); }
+  bool d3() const { return L.d3; }
 };
 
 namespace {
@@ -202,8 +241,13 @@ void drop_graphs(lbm_ctx* c) {
 // Enqueue n plain step launches.
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   const lbmk::Physics ph = make_physics(c->prm, scheme);
+  const lbmk::Physics3 ph3 = make_physics3(c->prm);
   for (int64_t k = 0; k < n; ++k) {
-    if (c->prm.force_stencil == 1) {
+    if (c->d3()) {
+      // rho and mu of the step go through the staging fields 0 and 4
+      HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->buf(c->cur), c->buf(1 - c->cur),
+                                   c->staging(), c->staging() + 4 * c->nodes(), s));
+    } else if (c->prm.force_stencil == 1) {
       // rho and mu of the step go through the staging fields 0 and 3
       HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->buf(c->cur), c->buf(1 - c->cur),
                                    c->staging(), c->staging() + 3 * c->nodes(), s));
@@ -301,17 +345,27 @@ lbm_status lbm_create(const lbm_params* p, void* ws, size_t bytes, void* stream,
   return LBM_OK;
 }
 
-lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
-                    lbm_scheme scheme) {
+}  // extern "C"
+
+namespace {
+
+// Populations f = feq(rho, u) of the scheme from host fields (uz: 3-D only).
+lbm_status init_impl(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                     const double* uz, int scheme) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!rho) return fail(c, LBM_EINVAL, "rho is NULL");
-  if ((ux == nullptr) != (uy == nullptr)) return fail(c, LBM_EINVAL, "give both ux and uy or neither");
   if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  const bool d3 = c->d3();
+  if (!d3 && uz) return fail(c, LBM_EINVAL, "uz is for 3-D lattices");
+  if (!d3 && (ux == nullptr) != (uy == nullptr))
+    return fail(c, LBM_EINVAL, "give both ux and uy or neither");
+  if (d3 && !((ux && uy && uz) || (!ux && !uy && !uz)))
+    return fail(c, LBM_EINVAL, "give ux, uy and uz or none of them");
   const long long n = c->nodes();
   for (long long k = 0; k < n; ++k) {
     if (!is_finite(rho[k]) || !(rho[k] > 0.0))
       return fail(c, LBM_EINVAL, "rho must be finite and > 0 (node " + std::to_string(k) + ")");
-    if (ux && (!is_finite(ux[k]) || !is_finite(uy[k])))
+    if (ux && (!is_finite(ux[k]) || !is_finite(uy[k]) || (uz && !is_finite(uz[k]))))
       return fail(c, LBM_EINVAL, "u must be finite (node " + std::to_string(k) + ")");
   }
   double* st = c->staging();
@@ -320,16 +374,39 @@ lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const doubl
   if (ux) {
     HIPCHK(c, hipMemcpyAsync(st + n, ux, fb, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(st + 2 * n, uy, fb, hipMemcpyHostToDevice, c->stream));
+    if (uz) HIPCHK(c, hipMemcpyAsync(st + 3 * n, uz, fb, hipMemcpyHostToDevice, c->stream));
   }
   c->cur = 0;
   c->scheme = scheme;
-  const lbmk::Physics ph = make_physics(c->prm, scheme);
-  HIPCHK(c, lbmk::launch_init(c->storage(), scheme, c->L.g, ph, st, ux ? st + n : nullptr,
-                              ux ? st + 2 * n : nullptr, c->state(), c->stream));
+  if (d3) {
+    HIPCHK(c, lbmk::launch_init3(scheme, c->L.g3, make_physics3(c->prm), st, ux ? st + n : nullptr,
+                                 ux ? st + 2 * n : nullptr, ux ? st + 3 * n : nullptr, c->state(),
+                                 c->stream));
+  } else {
+    const lbmk::Physics ph = make_physics(c->prm, scheme);
+    HIPCHK(c, lbmk::launch_init(c->storage(), scheme, c->L.g, ph, st, ux ? st + n : nullptr,
+                                ux ? st + 2 * n : nullptr, c->state(), c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->step = 0;
   c->initialised = true;
   return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                    lbm_scheme scheme) {
+  if (c && c->d3() && (ux || uy))
+    return fail(c, LBM_EINVAL, "3-D lattices take u through lbm_init3d");
+  return init_impl(c, rho, ux, uy, nullptr, scheme);
+}
+
+lbm_status lbm_init3d(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                      const double* uz, lbm_scheme scheme) {
+  return init_impl(c, rho, ux, uy, uz, scheme);
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
@@ -355,34 +432,52 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
   return LBM_OK;
 }
 
-lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* mu,
-                       lbm_observation* obs) {
+}  // extern "C"
+
+namespace {
+
+lbm_status observe_impl(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, double* mu,
+                        lbm_observation* obs) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_observe before lbm_init");
+  if (uz && !c->d3()) return fail(c, LBM_EINVAL, "uz is for 3-D lattices");
   const long long n = c->nodes();
   double* st = c->staging();
-  lbmk::ObserveOut o{rho ? st : nullptr, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
-                     mu ? st + 3 * n : nullptr, c->partials()};
-  const lbmk::Physics ph = make_physics(c->prm, c->scheme);
-  if (c->prm.force_stencil == 1) {
-    // the variant always computes rho and mu into staging fields 0 and 3
-    HIPCHK(c, lbmk::launch_observe4(c->scheme, c->L.g, ph, c->state(), st, st + 3 * n, o,
-                                    c->stream));
+  double* st_mu = st + (c->d3() ? 4 : 3) * n;
+  int nb = 0;
+  if (c->d3()) {
+    // the 3-D pass always computes rho and mu (staging fields 0 and 4)
+    const lbmk::ObserveOut3 o{st, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
+                              uz ? st + 3 * n : nullptr, st_mu, c->partials()};
+    HIPCHK(c, lbmk::launch_observe3(c->scheme, c->L.g3, make_physics3(c->prm), c->state(), st,
+                                    st_mu, o, c->stream));
+    nb = lbmk::blocks3(c->L.g3);
   } else {
-    HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,
-                                   c->stream));
+    lbmk::ObserveOut o{rho ? st : nullptr, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
+                       mu ? st_mu : nullptr, c->partials()};
+    const lbmk::Physics ph = make_physics(c->prm, c->scheme);
+    if (c->prm.force_stencil == 1) {
+      // the variant always computes rho and mu into staging fields 0 and 3
+      HIPCHK(c, lbmk::launch_observe4(c->scheme, c->L.g, ph, c->state(), st, st_mu, o,
+                                      c->stream));
+      nb = lbmk::stencil4_blocks(c->L.g);
+    } else {
+      HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,
+                                     c->stream));
+      nb = c->tl.blocks();
+    }
   }
   const size_t fb = (size_t)n * sizeof(double);
   if (rho) HIPCHK(c, hipMemcpyAsync(rho, st, fb, hipMemcpyDeviceToHost, c->stream));
   if (ux) HIPCHK(c, hipMemcpyAsync(ux, st + n, fb, hipMemcpyDeviceToHost, c->stream));
   if (uy) HIPCHK(c, hipMemcpyAsync(uy, st + 2 * n, fb, hipMemcpyDeviceToHost, c->stream));
-  if (mu) HIPCHK(c, hipMemcpyAsync(mu, st + 3 * n, fb, hipMemcpyDeviceToHost, c->stream));
-  const int nb = c->prm.force_stencil == 1 ? lbmk::stencil4_blocks(c->L.g) : c->tl.blocks();
+  if (uz) HIPCHK(c, hipMemcpyAsync(uz, st + 3 * n, fb, hipMemcpyDeviceToHost, c->stream));
+  if (mu) HIPCHK(c, hipMemcpyAsync(mu, st_mu, fb, hipMemcpyDeviceToHost, c->stream));
   std::vector<double> part((size_t)nb * 4);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->partials(), part.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  // fixed-order finish: tiles in order, compensated sums
+  // fixed-order finish: blocks in order, compensated sums
   double umax = 0.0, bad = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0;
   auto neumaier = [](double& s, double& comp, double v) {
     const double t = s + v;
@@ -410,6 +505,20 @@ lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* 
   return LBM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* mu,
+                       lbm_observation* obs) {
+  return observe_impl(c, rho, ux, uy, nullptr, mu, obs);
+}
+
+lbm_status lbm_observe3d(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, double* mu,
+                         lbm_observation* obs) {
+  return observe_impl(c, rho, ux, uy, uz, mu, obs);
+}
+
 lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!f) return fail(c, LBM_EINVAL, "f is NULL");
@@ -417,10 +526,14 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
   const long long n = c->nodes();
   double s[Q];
   shift_of(c->prm, c->scheme, s);
-  for (int q0 = 0; q0 < Q; q0 += 4) {
-    const int m = std::min(4, Q - q0);
-    HIPCHK(c, lbmk::launch_unpack(c->storage(), c->L.g, s, c->state(), q0, m, c->staging(),
-                                  c->stream));
+  const int nq = c->L.q;
+  for (int q0 = 0; q0 < nq; q0 += 4) {
+    const int m = std::min(4, nq - q0);
+    if (c->d3())
+      HIPCHK(c, lbmk::launch_unpack3(c->L.g3, c->state(), q0, m, c->staging(), c->stream));
+    else
+      HIPCHK(c, lbmk::launch_unpack(c->storage(), c->L.g, s, c->state(), q0, m, c->staging(),
+                                    c->stream));
     HIPCHK(c, hipMemcpyAsync(f + (size_t)q0 * n, c->staging(), (size_t)m * n * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -433,17 +546,21 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, i
   if (!f) return fail(c, LBM_EINVAL, "f is NULL");
   if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
   const long long n = c->nodes();
-  for (long long k = 0; k < (long long)Q * n; ++k)
+  const int nq = c->L.q;
+  for (long long k = 0; k < (long long)nq * n; ++k)
     if (!is_finite(f[k])) return fail(c, LBM_EINVAL, "populations must be finite");
   double s[Q];
   shift_of(c->prm, scheme, s);
   c->cur = 0;
-  for (int q0 = 0; q0 < Q; q0 += 4) {
-    const int m = std::min(4, Q - q0);
+  for (int q0 = 0; q0 < nq; q0 += 4) {
+    const int m = std::min(4, nq - q0);
     HIPCHK(c, hipMemcpyAsync(c->staging(), f + (size_t)q0 * n, (size_t)m * n * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, lbmk::launch_pack(c->storage(), c->L.g, s, c->staging(), q0, m, c->state(),
-                                c->stream));
+    if (c->d3())
+      HIPCHK(c, lbmk::launch_pack3(c->L.g3, c->staging(), q0, m, c->state(), c->stream));
+    else
+      HIPCHK(c, lbmk::launch_pack(c->storage(), c->L.g, s, c->staging(), q0, m, c->state(),
+                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   c->scheme = scheme;
@@ -454,6 +571,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, i
 
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (c->d3()) return fail(c, LBM_EINVAL, "3-D lattices have no tile choice");
   if (block == 0) block = c->tl.block;
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
@@ -510,7 +628,9 @@ const char* lbm_last_error(const lbm_ctx* c) {
   return c ? c->err.c_str() : g_thread_error.c_str();
 }
 
-int32_t lbm_kernels_per_step(const lbm_ctx* c) { return c && c->prm.force_stencil == 1 ? 3 : 1; }
+int32_t lbm_kernels_per_step(const lbm_ctx* c) {
+  return c && (c->prm.force_stencil == 1 || c->d3()) ? 3 : 1;
+}
 
 }  // extern "C"
 
@@ -801,6 +921,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
   if (p->force_stencil != 0) return bfail(b, LBM_EINVAL, "batches use the central force stencil");
+  if (p->nz > 1) return bfail(b, LBM_EINVAL, "batches hold 2-D lattices");
   int idx = -1;
   for (int i = 0; i < b->max_slots; ++i)
     if (b->slots[i].status == LBM_SLOT_FREE) {

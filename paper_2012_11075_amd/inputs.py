@@ -228,6 +228,25 @@ def request_stream(n: int, rate_hz: float, seed: int = 5, side_lo: int = 64,
     return out
 
 
+def droplet3_density(nx: int, ny: int, nz: int, ph: Physics, radius: float, width: float,
+                     noise: float = 0.0, seed: int = 0) -> np.ndarray:
+    """3-D droplet: the radial tanh profile of Eq. (38) about the node
+    (nx//2, ny//2, nz//2), shape (nz, ny, nx), with an optional
+    multiplicative perturbation (1 + noise r), r ~ U[-1, 1] (PCG64, seeded)."""
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - nx // 2) ** 2 + (y - ny // 2) ** 2 + (z - nz // 2) ** 2)
+    rho = 0.5 * (ph.rho_l + ph.rho_v) - 0.5 * (ph.rho_l - ph.rho_v) * np.tanh(2.0 * (r - radius) / width)
+    if noise:
+        rho = rho * (1.0 + noise * np.random.default_rng(seed).uniform(-1.0, 1.0, (nz, ny, nx)))
+    return np.ascontiguousarray(rho)
+
+
+# 3-D throughput lattice: 256^3 D3Q19 droplet of radius 64, the free-energy
+# constants of Sec. IV at density ratio 10, tau 1 (a finite, relaxing state).
+PHYS3 = Physics(tau=1.0, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=0.1)
+DROPLET3_SIDE, DROPLET3_RADIUS = 256, 64.0
+
+
 def with_size(p: Problem, nx: int, ny: int, **kw) -> Problem:
     """The same problem on another lattice (interfaces scaled with the side)."""
     sx = nx / p.nx

@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("rho_l", ctypes.c_double),
                 ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_all", ctypes.c_int32),
-                ("force_stencil", ctypes.c_int32)]
+                ("force_stencil", ctypes.c_int32), ("nz", ctypes.c_int32)]
 
 
 class Observation(ctypes.Structure):
@@ -78,6 +78,8 @@ def load():
         "lbm_init": (st, [_VP, _D, _D, _D, st]),
         "lbm_step": (st, [_VP, i64, st]),
         "lbm_observe": (st, [_VP, _D, _D, _D, _D, O]),
+        "lbm_init3d": (st, [_VP, _D, _D, _D, _D, st]),
+        "lbm_observe3d": (st, [_VP, _D, _D, _D, _D, _D, O]),
         "lbm_get_populations": (st, [_VP, _D]),
         "lbm_set_populations": (st, [_VP, _D, st, i64]),
         "lbm_set_tile": (st, [_VP, i32, i32, i32]),
@@ -122,15 +124,16 @@ def _scheme(s) -> int:
 
 
 def make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                rho_ref=None, shift_all=False, force_stencil=0) -> Params:
+                rho_ref=None, shift_all=False, force_stencil=0, nz=0) -> Params:
     """force_stencil: 0 the central gradients of Sec. II in the force, 1 the
-    fourth-order ones (FP64 single lattices only)."""
+    fourth-order ones (FP64 single lattices only).  nz > 1: a 3-D D3Q19
+    lattice (FP64 single lattices)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     if rho_ref is None:
         rho_ref = 0.5 * (rho_l + rho_v)
     return Params(int(nx), int(ny), float(tau), float(beta), float(kappa), float(rho_l),
                   float(rho_v), float(rho0), float(rho_ref), prec, int(bool(shift_all)),
-                  int(force_stencil))
+                  int(force_stencil), int(nz))
 
 
 def stream_handle(stream=None) -> int:
@@ -143,12 +146,17 @@ class Solver:
     """One periodic lattice on the current HIP device."""
 
     def __init__(self, nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                 rho_ref=None, shift_all=False, stream=None, force_stencil=0):
+                 rho_ref=None, shift_all=False, stream=None, force_stencil=0, nz=0):
         import torch
         self.lib = load()
         self.params = make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0, precision,
-                                  rho_ref, shift_all, force_stencil)
+                                  rho_ref, shift_all, force_stencil, nz)
         self.nx, self.ny = int(nx), int(ny)
+        self.nz = int(nz) if int(nz) > 1 else 0
+        # field and population shapes: (ny, nx) and (9, ny, nx) in 2-D,
+        # (nz, ny, nx) and (19, nz, ny, nx) in 3-D
+        self.shape = (self.nz, self.ny, self.nx) if self.nz else (self.ny, self.nx)
+        self.q = 19 if self.nz else 9
         nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise LbmError(-1, "invalid parameters")
@@ -175,24 +183,37 @@ class Solver:
                 raise NonFiniteState(status, msg)
             raise LbmError(status, msg)
 
-    def init(self, rho, ux=None, uy=None, scheme="well_balanced"):
+    def init(self, rho, ux=None, uy=None, scheme="well_balanced", uz=None):
         rho = np.ascontiguousarray(rho, dtype=np.float64)
-        assert rho.shape == (self.ny, self.nx)
+        assert rho.shape == self.shape
+        comps = [ux, uy, uz] if self.nz else [ux, uy]
         if ux is not None:
-            ux = np.ascontiguousarray(np.broadcast_to(ux, rho.shape), dtype=np.float64)
-            uy = np.ascontiguousarray(np.broadcast_to(uy, rho.shape), dtype=np.float64)
-        self._check(self.lib.lbm_init(self.ctx, _dptr(rho), _dptr(ux), _dptr(uy), _scheme(scheme)))
+            comps = [np.ascontiguousarray(np.broadcast_to(a, rho.shape), dtype=np.float64)
+                     for a in comps]
+        else:
+            comps = [None] * len(comps)
+        if self.nz:
+            self._check(self.lib.lbm_init3d(self.ctx, _dptr(rho), *[_dptr(a) for a in comps],
+                                            _scheme(scheme)))
+        else:
+            self._check(self.lib.lbm_init(self.ctx, _dptr(rho), *[_dptr(a) for a in comps],
+                                          _scheme(scheme)))
         return self
 
     def step(self, n=1, scheme="well_balanced"):
         self._check(self.lib.lbm_step(self.ctx, int(n), _scheme(scheme)))
         return self
 
-    def observe(self, fields=("rho", "ux", "uy", "mu"), raise_nonfinite=True) -> dict:
-        out = {k: np.empty((self.ny, self.nx)) for k in fields}
+    def observe(self, fields=("rho", "ux", "uy", "uz", "mu"), raise_nonfinite=True) -> dict:
+        out = {k: np.empty(self.shape) for k in fields if k != "uz" or self.nz}
         obs = Observation()
-        st = self.lib.lbm_observe(self.ctx, _dptr(out.get("rho")), _dptr(out.get("ux")),
-                                  _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(obs))
+        if self.nz:
+            st = self.lib.lbm_observe3d(self.ctx, _dptr(out.get("rho")), _dptr(out.get("ux")),
+                                        _dptr(out.get("uy")), _dptr(out.get("uz")),
+                                        _dptr(out.get("mu")), ctypes.byref(obs))
+        else:
+            st = self.lib.lbm_observe(self.ctx, _dptr(out.get("rho")), _dptr(out.get("ux")),
+                                      _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(obs))
         if st != -4 or raise_nonfinite:
             self._check(st)
         out.update(step=obs.step, max_u=obs.max_u, mass=obs.mass,
@@ -200,14 +221,14 @@ class Solver:
         return out
 
     def get_populations(self) -> np.ndarray:
-        """Populations as (9, ny, nx) doubles (unshifted)."""
-        f = np.empty((9, self.ny, self.nx))
+        """Populations as (9, ny, nx) doubles (unshifted); 3-D: (19, nz, ny, nx)."""
+        f = np.empty((self.q,) + self.shape)
         self._check(self.lib.lbm_get_populations(self.ctx, _dptr(f)))
         return f
 
     def set_populations(self, f: np.ndarray, scheme="well_balanced", step=0):
         f = np.ascontiguousarray(f, dtype=np.float64)
-        assert f.shape == (9, self.ny, self.nx)
+        assert f.shape == (self.q,) + self.shape
         self._check(self.lib.lbm_set_populations(self.ctx, _dptr(f), _scheme(scheme), int(step)))
         return self
 

@@ -32,6 +32,8 @@ def main():
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--force-stencil", type=int, default=0,
                     help="1: the fourth-order force-stencil variant (FP64, three kernels per step)")
+    ap.add_argument("--d3", type=int, default=0,
+                    help="profile the 3-D (D3Q19) step on an N^3 droplet instead")
     ap.add_argument("--batch", type=int, default=0,
                     help="profile the batched launch over this many uneven instances instead")
     args = ap.parse_args()
@@ -41,6 +43,19 @@ def main():
     if args.batch:
         run_batch(args, torch, I, lbm, tune)
         calibrate(args, torch)
+        return
+    if args.d3:
+        n, ph = args.d3, I.PHYS3
+        rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
+                                 I.equilibrium_width(ph), 1e-3, seed=13)
+        s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n)
+        s.init(rho, scheme=args.scheme)
+        print("profile_step: D3Q19 %d^3 %s" % (n, args.scheme), flush=True)
+        s.step(args.steps, args.scheme)
+        torch.cuda.synchronize()
+        print("profile_step: %d steps done" % args.steps, flush=True)
+        calibrate(args, torch)
+        s.close()
         return
     prob = I.PROBLEMS[args.problem]
     s = lbm.Solver.for_problem(prob, precision=args.precision, force_stencil=args.force_stencil)
