@@ -179,9 +179,10 @@ int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
 
 /* ------------------------------------------------------------------ batch */
 /* Many independent lattices of uneven size advanced together: each step is
- * one persistent launch per group of slots that share precision, scheme and
- * block width, reading a device-resident slot table (HIP-graph replays stay
- * valid when slots come and go).  Each slot is a complete single-instance
+ * one launch per group of slots that share precision, scheme, block width
+ * and prefetch depth, with one block per tile of the group's slots, reading
+ * a device-resident slot table (captured step sequences are re-captured
+ * when the groups or their tile counts change).  Each slot is a complete single-instance
  * state (same kernels, same arithmetic), so a lattice gives bit-identical
  * populations alone and in a batch.  The caller owns the device arena; the
  * library places slot workspaces and the tables inside it. */

@@ -660,7 +660,6 @@ struct lbm_batch {
   hipStream_t stream = nullptr;
   int max_slots = 0;
   size_t tab_stride = 0;   // bytes per group table
-  size_t ctr_off = 0;      // work queues, kQueueInts ints per group
   size_t part_off = 0;     // partials region
   size_t part_cap = 0;     // tiles it can hold
   size_t heap_off = 0;     // start of the slot heap
@@ -686,12 +685,11 @@ struct lbm_batch {
   int graph_steps = 0;
   hipGraphExec_t graph = nullptr;
   uint64_t graph_mask = 0;
-  int grid[kGroups][2] = {};  // residency of step / observe launches
+  int tiles_of[kGroups] = {};     // work items (tiles) of each group, as uploaded
+  int graph_tiles[kGroups] = {};  // the same when the graph was captured
   std::string err;
 
   lbmk::BatchTable* dev_tab(int g) const { return (lbmk::BatchTable*)(arena + g * tab_stride); }
-  int* counters() const { return (int*)(arena + ctr_off); }
-  int* queues(int g) const { return counters() + g * lbmk::kQueueInts; }
   double* partials() const { return (double*)(arena + part_off); }
 };
 
@@ -789,6 +787,7 @@ lbm_status upload_tables(lbm_batch* b) {
     tab->nslots = n;
     tab->total_tiles = tiles;
     if (n > 0) active |= 1ull << g;
+    b->tiles_of[g] = tiles;
     part += tiles;
     if (part > b->part_cap) return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
     const size_t used = sizeof(lbmk::BatchTable) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot);
@@ -803,13 +802,12 @@ lbm_status upload_tables(lbm_batch* b) {
 
 lbm_status batch_launches(lbm_batch* b, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
-    BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups * lbmk::kQueueInts, s));
     for (int g = 0; g < kGroups; ++g) {
       if (!(b->active_mask >> g & 1)) continue;
       int storage, scheme, block, depth;
       group_decode(g, &storage, &scheme, &block, &depth);
       BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g),
-                                 b->queues(g), b->grid[g][0], j & 1, s));
+                                 b->tiles_of[g], j & 1, s));
     }
   }
   return LBM_OK;
@@ -823,7 +821,10 @@ void drop_batch_graph(lbm_batch* b) {
 }
 
 lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
-  if (b->graph && b->graph_mask == b->active_mask) {
+  // a captured launch holds its group's grid (one block per tile), so the
+  // graph is re-captured when the launched groups or their tile counts change
+  if (b->graph && b->graph_mask == b->active_mask &&
+      std::equal(b->tiles_of, b->tiles_of + kGroups, b->graph_tiles)) {
     *out = b->graph;
     return LBM_OK;
   }
@@ -852,6 +853,7 @@ lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
     return bfail(b, LBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
   b->graph_mask = b->active_mask;
+  std::copy(b->tiles_of, b->tiles_of + kGroups, b->graph_tiles);
   *out = b->graph;
   return LBM_OK;
 }
@@ -873,8 +875,7 @@ size_t lbm_batch_slot_bytes(const lbm_params* p) {
 size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  return kGroups * stride + align_up(kGroups * lbmk::kQueueInts * sizeof(int), ALIGN) +
-         align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+  return kGroups * stride + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
 }
 
 lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
@@ -892,23 +893,12 @@ lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* 
   b->stream = (hipStream_t)stream;
   b->max_slots = max_slots;
   b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  b->ctr_off = kGroups * b->tab_stride;
-  b->part_off = b->ctr_off + align_up(kGroups * lbmk::kQueueInts * sizeof(int), ALIGN);
+  b->part_off = kGroups * b->tab_stride;
   b->part_cap = part_capacity(bytes);
   b->heap_off = over;
   b->slots.resize(max_slots);
   b->free_ranges.push_back(Range{b->heap_off, bytes - b->heap_off});
   b->host_tab.assign(kGroups, std::vector<char>(lbmk::batch_table_bytes(max_slots), 0));
-  for (int g = 0; g < kGroups; ++g) {
-    int storage, scheme, block, depth;
-    group_decode(g, &storage, &scheme, &block, &depth);
-    b->grid[g][0] = lbmk::batch_grid(storage, scheme, block, depth, false);
-    b->grid[g][1] = lbmk::batch_grid(storage, scheme, block, 1, true);
-    if (b->grid[g][0] <= 0 || b->grid[g][1] <= 0) {
-      delete b;
-      return bfail(nullptr, LBM_EHIP, "could not size the batched launches (no device?)");
-    }
-  }
   *out = b;
   return LBM_OK;
 }
@@ -1022,13 +1012,12 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (const auto& s : b->slots)
     if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
   if (total == 0) return LBM_OK;
-  BHIP(b, lbmk::launch_reset_counters(b->counters(), kGroups * lbmk::kQueueInts, b->stream));
   for (int g = 0; g < kGroups; ++g) {
     if (!(b->active_mask >> g & 1)) continue;
     int storage, scheme, block, depth;
     group_decode(g, &storage, &scheme, &block, &depth);
     BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g),
-                               b->queues(g), b->grid[g][1], 0, b->stream));
+                               b->tiles_of[g], 0, b->stream));
   }
   std::vector<double> part(total * 4);
   BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),

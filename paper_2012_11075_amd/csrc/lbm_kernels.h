@@ -90,11 +90,6 @@ inline size_t batch_table_bytes(int max_slots) {
   return sizeof(BatchTable) + (size_t)(max_slots > 1 ? max_slots - 1 : 0) * sizeof(BatchSlot);
 }
 
-// Work queues of one batched launch: kQueues device ints (one per XCD),
-// kQueueStride ints apart so that each sits on its own 64-byte line.
-constexpr int kQueues = 8;
-constexpr int kQueueStride = 16;
-constexpr int kQueueInts = kQueues * kQueueStride;
 enum Storage { FP64 = 0, FP32 = 1 };
 
 // One step: populations fin -> fout (ping-pong buffers).
@@ -122,12 +117,10 @@ hipError_t launch_unpack(int storage, const Geometry& g, const double* shift, co
 hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, void* f,
                           hipStream_t s);
 
-// Persistent batched launch of one group (one precision, scheme, block width
-// and depth) over the device table `tab`; observe = write per-tile partials
-// instead of stepping.  `queues` (kQueueInts device ints, zero at launch)
-// hand out work items; `grid` = batch_grid(...) blocks.
+// Batched step (or observe) of one launch group: one block per tile of the
+// table's `tiles` work items (the group's total_tiles).
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int* queues, int grid, int parity, hipStream_t s);
+                        const BatchTable* tab, int tiles, int parity, hipStream_t s);
 
 // Force-stencil variant (FP64): one step in three launches (density into
 // `rho`, chemical potential into `mu`, collide-stream with fourth-order
@@ -156,12 +149,6 @@ hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, cons
 hipError_t launch_observe3(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
                            double* rho, double* mu, const ObserveOut3& o, hipStream_t s);
 int blocks3(const Geometry3& g);
-
-// Set n device ints to zero (the work queues, before each batched step).
-hipError_t launch_reset_counters(int* c, int n, hipStream_t s);
-
-// Blocks of a batched launch that fit on the device at once.
-int batch_grid(int storage, int scheme, int block, int depth, bool observe);
 
 // Block widths the kernels are instantiated for.
 bool block_width_supported(int block);

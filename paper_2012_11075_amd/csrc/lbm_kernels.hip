@@ -389,88 +389,41 @@ __global__ void __launch_bounds__(BW)
                                         (Global<T>*)fout, obs);
 }
 
-// Many lattices in one persistent launch: the grid is sized to residency and
-// blocks take work items (one tile of one lattice) from queues in device
-// memory until the concatenated tile list of the table is exhausted, so
-// uneven lattices balance across the device.  The list is cut into eight
-// contiguous ranges, one queue each; block b starts on queue b mod 8, the XCD
-// the hardware places it on, so horizontally adjacent tiles (consecutive
-// items) run together on one XCD and share their halo lines in its L2.  A
-// block whose queue is empty moves on to the next queues in turn, which
-// balances the tail.  Every grab either returns an item of a finite range or
-// moves the block to its next queue, so each block leaves after at most
-// eight empty grabs and each item is taken exactly once.  The table and the
-// counters live in device memory, so a captured launch stays valid when
-// slots are admitted or released; `parity` selects which of each slot's two
-// buffers is read.
+// Many lattices in one launch: one block per work item (one tile of one
+// lattice) of the table's concatenated tile list, so the hardware dispatcher
+// balances uneven lattices as blocks finish.  Items are mapped XCD-aware as
+// in the single-lattice launch (blocks b, b+8, ... of one XCD walk a
+// contiguous range of the list), so horizontally adjacent tiles run together
+// on one XCD and share their halo lines in its L2.  The table lives in
+// device memory; `parity` selects which of each slot's two buffers is read.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
-__global__ void __launch_bounds__(BW)
-    march_batch(const BatchTable* __restrict__ tab, int* __restrict__ queues, int parity) {
-  __shared__ int item_s;
+__global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__ tab, int parity) {
   const int total = tab->total_tiles;
   const int ns = tab->nslots;
-  const int q8 = total >> 3, r8 = total & 7;
-  const int home = blockIdx.x & 7;
-  int k = 0;
-  while (k < kQueues) {
-    // Queue index and grab result are made wave-uniform explicitly, so the
-    // loop control stays scalar and the compiler combines the wave's atomic
-    // into one memory operation.  All lanes of the first wave join the
-    // atomic (lane 0 adds 1, the others 0) and read lane 0's result, without
-    // a lane-0-only branch: such a branch plus an LDS broadcast let the
-    // compiler split a one-wave block's loop into a lane-0 path and an inner
-    // loop in which the other lanes re-read the broadcast slot without a new
-    // item, and spin.
-    const int q = __builtin_amdgcn_readfirstlane((home + k) & 7);
-    int* const qp = queues + q * kQueueStride;
-    int v;
-    if (BW == 64) {
-      v = __builtin_amdgcn_readfirstlane(atomicAdd(qp, threadIdx.x == 0 ? 1 : 0));
-    } else {
-      if (threadIdx.x < 64) {
-        const int a = __builtin_amdgcn_readfirstlane(atomicAdd(qp, threadIdx.x == 0 ? 1 : 0));
-        if (threadIdx.x == 0) item_s = a;
-      }
-      __syncthreads();  // publishes item_s; the previous item's LDS reads are done
-      v = __builtin_amdgcn_readfirstlane(item_s);
-      __syncthreads();  // every wave has read item_s before it is replaced
-    }
-    if (v >= q8 + (q < r8 ? 1 : 0)) {
-      ++k;
-      continue;
-    }
-    const int item = q * q8 + min(q, r8) + v;
-    // slot of this item: last slot whose first tile <= item (uniform search)
-    int lo = 0, hi = ns - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tab->slot[mid].tile0 <= item)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    // The slot's record is copied into locals once per item: read through a
-    // reference into the table, its fields would be re-loaded after every
-    // population store (the compiler cannot rule out that the stores alias
-    // the table), and each scalar re-load waits on outstanding LDS traffic.
-    const BatchSlot* sp = &tab->slot[lo];
-    const Geometry g = sp->g;
-    const Physics ph = sp->ph;
-    const Tiling tl = sp->tl;
-    const int which = sp->cur ^ parity;
-    const Global<T>* fin = (const Global<T>*)(const T*)sp->buf[which];
-    Global<T>* fout = (Global<T>*)(T*)sp->buf[which ^ 1];
-    const ObserveOut o{nullptr, nullptr, nullptr, nullptr, sp->partials};
-    const int tile = item - sp->tile0;
-    march_tile<T, SCHEME, BW, D, OBSERVE>(g, ph, tl, tile, fin, fout, o);
+  const int item = xcd_tile(blockIdx.x, total);
+  if (item >= total) return;
+  // slot of this item: last slot whose first tile <= item (uniform search)
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab->slot[mid].tile0 <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-}
-
-// Work queues of the batched launches start at zero for every launch (a
-// kernel rather than a memset, so that captured graphs replay it reliably).
-__global__ void reset_counters(int* __restrict__ c, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) c[i] = 0;
+  // The slot's record is copied into locals: read through a reference into
+  // the table, its fields would be re-loaded after every population store
+  // (the compiler cannot rule out that the stores alias the table), and each
+  // scalar re-load waits on outstanding LDS traffic.
+  const BatchSlot* sp = &tab->slot[lo];
+  const Geometry g = sp->g;
+  const Physics ph = sp->ph;
+  const Tiling tl = sp->tl;
+  const int which = sp->cur ^ parity;
+  const Global<T>* fin = (const Global<T>*)(const T*)sp->buf[which];
+  Global<T>* fout = (Global<T>*)(T*)sp->buf[which ^ 1];
+  const ObserveOut o{nullptr, nullptr, nullptr, nullptr, sp->partials};
+  march_tile<T, SCHEME, BW, D, OBSERVE>(g, ph, tl, item - sp->tile0, fin, fout, o);
 }
 
 // Offset, within a plane, of the slot the next pull reads population q of
@@ -1095,28 +1048,13 @@ const void* batch_kernel(int storage, int scheme, int block, int depth, bool obs
 
 }  // namespace
 
-int batch_grid(int storage, int scheme, int block, int depth, bool observe) {
-  const void* fn = batch_kernel(storage, scheme, block, depth, observe);
-  if (!fn) return 0;
-  int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, 0) != hipSuccess) return 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  return per_cu * cus;
-}
-
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
-                        const BatchTable* tab, int* queues, int grid, int parity, hipStream_t s) {
+                        const BatchTable* tab, int tiles, int parity, hipStream_t s) {
   const void* fn = batch_kernel(storage, scheme, block, depth, observe);
-  if (!fn || grid <= 0) return hipErrorInvalidValue;
-  void* args[] = {(void*)&tab, (void*)&queues, (void*)&parity};
+  if (!fn || tiles <= 0) return hipErrorInvalidValue;
+  void* args[] = {(void*)&tab, (void*)&parity};
+  const int grid = tiles;
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, s);
-}
-
-hipError_t launch_reset_counters(int* c, int n, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counters, dim3((n + 63) / 64), dim3(64), 0, s, c, n);
-  return hipGetLastError();
 }
 
 hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics& ph,

@@ -263,7 +263,7 @@ SLOT_STATUS = {0: "free", 1: "active", 2: "converged", 3: "capped", 4: "diverged
 
 class Batch:
     """Many independent lattices in one device arena, advanced together by
-    batched persistent launches (see the lbm_batch_* calls of lbm.h)."""
+    batched launches, one per group of slots (see the lbm_batch_* calls of lbm.h)."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 1024, stream=None):
         import torch

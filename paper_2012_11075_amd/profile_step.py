@@ -75,7 +75,7 @@ def main():
 def run_batch(args, torch, I, lbm, tune):
     """The batched workload: `args.batch` uneven instances (side 32..512)
     in one arena, tuned tiles, `args.steps` steps without graphs (one
-    counter reset and one persistent launch per step)."""
+    launch per group and step)."""
     probs = I.batch_instances(args.batch)
     prms = [lbm.make_params(p.nx, p.ny, p.physics.tau, p.physics.beta, p.physics.kappa,
                             p.physics.rho_l, p.physics.rho_v, precision=args.precision) for p in probs]

@@ -72,7 +72,7 @@ BATCH_TILES = [(64, 8, 1), (128, 16, 2), (256, 32, 3), (64, 33, 3), (128, 5, 1),
 
 def test_batch_tiles_bit_exact(lbm):
     """Slots of one batch on every batched block width and depth (several
-    launch groups at once, each on its work queues) give the populations of
+    launch groups at once) give the populations of
     the lattice run alone."""
     cases = mix_cases()
     steps = 40
