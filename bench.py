@@ -395,7 +395,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the step on a single device "
+        print("bench.py measures one GPU: the step runs on a single device "
               "(multi-GPU decomposition is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     from paper_2012_11075_amd import inputs as I

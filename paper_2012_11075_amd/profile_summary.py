@@ -11,7 +11,7 @@ traffic (an elementwise kernel that reads and writes ``copy_mib`` MiB).  It
 writes ``<out>.json`` (read by bench.py together with the kernel source hash
 the counters were taken on) and ``<out>.md``.
 
-    python -m paper_2012_11075_amd.profile_summary --root gpurun_out/prof \
+    python -m paper_2012_11075_amd.profile_summary --root <rocprofv3 output dir> \
         --out profiles/step_droplet_4096 --copy-mib 1024 --nodes 16777216 \
         --command-kt "..." --command-pmc "..."
 """

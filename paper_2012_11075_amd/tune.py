@@ -115,7 +115,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
     full batch under every candidate for that bucket's lattices (the others
     fixed) and keep the fastest.  Starting from one shared tile matters: a
     bucket moved alone to another block width or depth forms a second group,
-    launched after the first, so single-bucket moves are judged against a
+    launched after the first, so single-bucket moves are compared against a
     one-group start.  Returns {bucket: (block, rows, depth)}, the final ms
     per step and the uniform sweep [(ms, tile), ...]."""
     import torch
