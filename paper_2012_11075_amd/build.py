@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "liblbm.so")
 CEILING = os.path.join(LIB_DIR, "hbm_ceiling")
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_kernels3d.hip", "lbm_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "lbm.h"
-#include "lbm_kernels.h"
+#include "lbm_kernels3d.h"
 
 using lbmk::Q;
 
