@@ -294,15 +294,13 @@ def time_stencil4(prob, steps, warmup, scheme="standard"):
                         % (prob.name, scheme, steps)}
 
 
-D3_BYTES = 496         # FP64 bytes per node of the three-pass 3-D step
-D3_FUSED_BYTES = 304   # 19 populations read and written once
+D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
 
 
-def time_d3q19(steps, warmup, side=None):
-    """The 3-D (D3Q19) WB step on a side^3 droplet (FP64), three passes per
-    step: density (19 reads + 1 write), chemical potential (1 + 1),
-    collide-stream (19 + 2 reads, 19 writes) = 496 algorithmic bytes per
-    node (a single fused pass would need 304)."""
+def time_d3q19(steps, warmup, side=None, tile=None):
+    """The 3-D (D3Q19) WB step on a side^3 droplet (FP64): one fused pass
+    per step, 19 populations read and written = 304 algorithmic bytes per
+    node.  `tile` (block threads, planes per chunk) overrides the default."""
     import torch
     from paper_2012_11075_amd import inputs as I
     from paper_2012_11075_amd import lbm
@@ -311,6 +309,8 @@ def time_d3q19(steps, warmup, side=None):
     rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
                              I.equilibrium_width(ph), 1e-3, seed=13)
     s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n)
+    if tile:
+        s.set_tile(*tile)
     s.init(rho, scheme="well_balanced")
     del rho
     s.step(warmup, "well_balanced")
@@ -324,13 +324,15 @@ def time_d3q19(steps, warmup, side=None):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     ob = s.observe(fields=(), raise_nonfinite=False)
+    kps = s.lib.lbm_kernels_per_step(s.ctx)
+    used = s.get_tile()
     s.close()
     del s
     torch.cuda.empty_cache()
     nodes = n ** 3
     gbs = D3_BYTES * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
-            "kernels_per_step": 3, "bytes_per_update": D3_BYTES, "fused_bytes_per_update": D3_FUSED_BYTES,
+            "kernels_per_step": kps, "bytes_per_update": D3_BYTES, "tile": list(used),
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "workload": "D3Q19 droplet %d^3, R=%g, rho_l=1, rho_v=0.1, beta=0.01, kappa=0.0128, tau=1, "

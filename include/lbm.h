@@ -91,7 +91,9 @@ typedef struct {
                           * (Eqs. 24 and 26 hold for general dimension; here
                           * D = 3).  3-D lattices are FP64 with the central
                           * force stencil, single lattices only, ny and
-                          * nz <= 65535; three kernels per step.  Fields are
+                          * nz <= 65535, a z-plane of populations
+                          * (19 * ny * nx * 8 bytes, nx rounded up to 32)
+                          * below 4 GiB; one kernel per step.  Fields are
                           * then double[nz][ny][nx]. */
 } lbm_params;
 
@@ -160,8 +162,10 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme,
 /* Tile shape of the step kernel: block width in threads (128, 192, 256, 320
  * or 512; the block computes block_width output columns), output rows
  * per block (>= 4) and prefetch depth (rows of populations each thread keeps
- * in flight, 1..3).  Any valid shape gives bit-identical populations.  0
- * keeps the current value.  lbm_get_tile reports the shape in use (any
+ * in flight, 1..3).  3-D lattices (nz > 1): block width 256 or 512 threads
+ * (tiles of 32 x 8 or 32 x 16 nodes), rows = z planes each block marches
+ * through (>= 1), depth 1.  Any valid shape gives bit-identical populations.
+ * 0 keeps the current value.  lbm_get_tile reports the shape in use (any
  * output pointer may be NULL). */
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t block_width, int32_t rows, int32_t depth);
 lbm_status lbm_get_tile(const lbm_ctx* ctx, int32_t* block_width, int32_t* rows, int32_t* depth);

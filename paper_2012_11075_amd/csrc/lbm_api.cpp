@@ -66,6 +66,11 @@ bool valid_params(const lbm_params* p, std::string* why) {
     if (p->precision != LBM_FP64) return *why = "3-D lattices are FP64 only", false;
     if (p->force_stencil != 0) return *why = "3-D lattices use the central force stencil", false;
     if (p->ny > 65535 || p->nz > 65535) return *why = "3-D lattices need ny, nz <= 65535", false;
+    // the fused step addresses one z-plane of populations with 32-bit offsets
+    const long long px = ((long long)p->nx + 31) / 32 * 32;
+    if ((long long)p->ny * lbmk::Q3 * px * 8 > 0xffffffffLL)
+      return *why = "3-D lattices need a z-plane of populations (19 * ny * nx * 8 bytes) below 4 GiB",
+             false;
   }
   return true;
 }
@@ -190,6 +195,7 @@ struct lbm_ctx {
   lbm_params prm{};
   Layout L{};
   lbmk::Tiling tl{};
+  lbmk::Tiling3 tl3{};  // fused 3-D step (nz > 1)
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   int cur = 0;           // 0: state in buffer A, 1: in buffer B
@@ -244,9 +250,8 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   const lbmk::Physics3 ph3 = make_physics3(c->prm);
   for (int64_t k = 0; k < n; ++k) {
     if (c->d3()) {
-      // rho and mu of the step go through the staging fields 0 and 4
-      HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->buf(c->cur), c->buf(1 - c->cur),
-                                   c->staging(), c->staging() + 4 * c->nodes(), s));
+      HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
+                                   c->buf(1 - c->cur), s));
     } else if (c->prm.force_stencil == 1) {
       // rho and mu of the step go through the staging fields 0 and 3
       HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->buf(c->cur), c->buf(1 - c->cur),
@@ -335,12 +340,19 @@ lbm_status lbm_create(const lbm_params* p, void* ws, size_t bytes, void* stream,
   if (bytes < L.total)
     return fail(nullptr, LBM_ENOSPACE,
                 "workspace too small: need " + std::to_string(L.total) + " bytes");
+  lbmk::Tiling3 t3{};
+  if (L.d3) {
+    t3 = lbmk::make_tiling3(L.g3, 8, 0, 1);
+    if (lbmk::blocks_of(t3) > 0x7fffffffLL)
+      return fail(nullptr, LBM_EINVAL, "3-D lattice too large for one launch");
+  }
   lbm_ctx* c = new lbm_ctx();
   c->prm = *p;
   c->L = L;
   c->ws = (char*)ws;
   c->stream = (hipStream_t)stream;
   c->tl = default_tiling(L.g);
+  c->tl3 = t3;
   *out = c;
   return LBM_OK;
 }
@@ -571,7 +583,20 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, i
 
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
-  if (c->d3()) return fail(c, LBM_EINVAL, "3-D lattices have no tile choice");
+  if (c->d3()) {
+    // fused 3-D step: block = 32 x ty threads, rows = planes per chunk,
+    // depth = planes of populations in flight per thread
+    const int ty = block == 0 ? c->tl3.ty : (block % lbmk::M3X ? 0 : block / lbmk::M3X);
+    const int d = depth == 0 ? c->tl3.depth : depth;
+    if (!lbmk::tiling3_supported(ty, d))
+      return fail(c, LBM_EINVAL, "3-D tiles: block 256 with depth 1..3 or block 512 with depth 1..2");
+    if (rows < 0) return fail(c, LBM_EINVAL, "rows (planes per chunk) must be >= 1");
+    const lbmk::Tiling3 t = lbmk::make_tiling3(c->L.g3, ty, rows == 0 ? c->tl3.zc : rows, d);
+    if (lbmk::blocks_of(t) > 0x7fffffffLL) return fail(c, LBM_EINVAL, "too many blocks");
+    drop_graphs(c);
+    c->tl3 = t;
+    return LBM_OK;
+  }
   if (block == 0) block = c->tl.block;
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
@@ -589,9 +614,10 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
 
 lbm_status lbm_get_tile(const lbm_ctx* c, int32_t* block, int32_t* rows, int32_t* depth) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
-  if (block) *block = c->tl.block;
-  if (rows) *rows = c->tl.rows;
-  if (depth) *depth = c->tl.depth;
+  const bool d3 = c->d3();
+  if (block) *block = d3 ? lbmk::M3X * c->tl3.ty : c->tl.block;
+  if (rows) *rows = d3 ? c->tl3.zc : c->tl.rows;
+  if (depth) *depth = d3 ? c->tl3.depth : c->tl.depth;
   return LBM_OK;
 }
 
@@ -629,7 +655,7 @@ const char* lbm_last_error(const lbm_ctx* c) {
 }
 
 int32_t lbm_kernels_per_step(const lbm_ctx* c) {
-  return c && (c->prm.force_stencil == 1 || c->d3()) ? 3 : 1;
+  return c && c->prm.force_stencil == 1 ? 3 : 1;
 }
 
 }  // extern "C"

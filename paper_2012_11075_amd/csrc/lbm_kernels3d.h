@@ -27,10 +27,26 @@ struct ObserveOut3 {
   double *rho, *ux, *uy, *uz, *mu, *partials;
 };
 
+// Tiling of the fused step: blocks of M3X x ty threads, one node each, march
+// along z through chunks of zc planes (tiles_x * tiles_y * chunks blocks),
+// each thread with `depth` planes of populations in flight (the plane being
+// summed and depth - 1 ahead).
+constexpr int M3X = 32;
+struct Tiling3 {
+  int ty, zc, depth;
+  int tiles_x, tiles_y, chunks;
+};
+// ty: 8 (depth 1..3) or 16 (depth 1..2); zc <= 0 picks the chunk length for
+// about 1024 blocks.
+Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth);
+bool tiling3_supported(int ty, int depth);
+long long blocks_of(const Tiling3& t);
+
 // Three dimensions (D3Q19, FP64): init from dense fields (u may be null),
 // pack/unpack m populations from q0 through a dense staging area, one step
-// (density into `rho`, chemical potential into `mu`, collide-stream), and
-// the observe pass (partials: one per block of blocks3(g)).
+// (one fused pass fin -> fout), and the observe pass (density into `rho`,
+// chemical potential into `mu`, fields and partials: one per block of
+// blocks3(g)).
 hipError_t launch_init3(int scheme, const Geometry3& g, const Physics3& ph, const double* rho,
                         const double* ux, const double* uy, const double* uz, void* f,
                         hipStream_t s);
@@ -38,8 +54,8 @@ hipError_t launch_pack3(const Geometry3& g, const double* dense, int q0, int m, 
                         hipStream_t s);
 hipError_t launch_unpack3(const Geometry3& g, const void* f, int q0, int m, double* dense,
                           hipStream_t s);
-hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const void* fin,
-                        void* fout, double* rho, double* mu, hipStream_t s);
+hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const Tiling3& t,
+                        const void* fin, void* fout, hipStream_t s);
 hipError_t launch_observe3(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
                            double* rho, double* mu, const ObserveOut3& o, hipStream_t s);
 int blocks3(const Geometry3& g);

@@ -3,10 +3,27 @@
 //
 // Velocities: rest, the 6 axis directions (weight 1/18), the 12 edge
 // directions (weight 1/36).  Gradient (1/cs2) sum w_i c_i phi(x+c_i) and
-// Laplacian (2/cs2) sum w_i [phi(x+c_i) - phi(x)], as in 2-D.  FP64, three
-// passes per step like the force-stencil variant: density, chemical
-// potential, collide-stream on LDS tiles of rho and mu with a 1-node halo.
+// Laplacian (2/cs2) sum w_i [phi(x+c_i) - phi(x)], as in 2-D.  FP64.
+//
+// Step (one HBM pass, `march3`).  A block of 32 x TY threads owns a 32 x TY
+// column of nodes and marches along z through a chunk of planes.  Each
+// plane's populations are loaded once: a thread pulls the 19 populations of
+// its own node and keeps them in registers for the two planes until that
+// node's update; the 2-node ring of halo nodes around the tile, whose
+// populations are needed for rho only, is spread over the waves (one node
+// per lane).  rho of a plane goes to a 5-plane LDS ring, mu of the plane
+// before to a 3-plane ring, and the node two planes back is collided and
+// written.  Odd chunks march towards -z, so adjacent chunks read the planes
+// they share at about the same time.  Every stencil sum is grouped
+// symmetrically in z, so the direction of the march changes no bit of the
+// result.
+//
+// Observe (three passes, off the stepping path): density, chemical
+// potential, and fields and reductions on LDS tiles of rho and mu with a
+// 1-node halo, through the same device functions as the step.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "lbm_kernels3d.h"
 
@@ -45,11 +62,14 @@ __device__ __forceinline__ double mu0_3(double r, const Physics3& p) {
 
 // Equilibrium (Eq. 3 / Eq. 24) and forcing term (Eq. 5 / Eq. 26 with D = 3:
 // the last term's coefficient (|c|^2/cs2 - 3)/2 is -3/2, 0, 3/2 for the
-// rest, axis and edge directions), then BGK.
-template <int SCHEME>
-__device__ __forceinline__ void collide3(double (&f)[Q3], double rho, double ux, double uy,
+// rest, axis and edge directions), then BGK; emit(i, f*_i) receives each
+// post-collision population as soon as it is known.  A scheduling barrier
+// after every G directions keeps the compiler from computing all 19 at once
+// (each result then dies at its store instead of holding a register).
+template <int SCHEME, int G, typename E>
+__device__ __forceinline__ void collide3(const double (&f)[Q3], double rho, double ux, double uy,
                                          double uz, double Fx, double Fy, double Fz, double grx,
-                                         double gry, double grz, const Physics3& p) {
+                                         double gry, double grz, const Physics3& p, E&& emit) {
   const double u15 = 1.5 * (ux * ux + uy * uy + uz * uz);
   double Gx = Fx, Gy = Fy, Gz = Fz;
   if (SCHEME == WELL_BALANCED) {
@@ -77,7 +97,287 @@ __device__ __forceinline__ void collide3(double (&f)[Q3], double rho, double ux,
       const double k = i == 0 ? -1.5 : (i < 7 ? 0.0 : 1.5);
       Fi = w * (3.0 * cF + 9.0 * cu * cG - uG3 + k * ugr);
     }
-    f[i] = f[i] - p.omega * (f[i] - feq) + p.fpre * Fi;
+    emit(i, f[i] - p.omega * (f[i] - feq) + p.fpre * Fi);
+    if (G > 0 && i % G == G - 1) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// rho = sum_i f_i in a fixed order (every kernel sums a node the same way).
+__device__ __forceinline__ double sum19(const double (&f)[Q3]) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) s += f[i];
+  return s;
+}
+
+// 19-point Laplacian (2/cs2) sum_i w_i [phi(x + c_i) - phi(x)] from
+// at(dx, dy, dz) = phi(x + (dx, dy, dz)); the sums pair +z with -z.
+template <typename A>
+__device__ __forceinline__ double lap19(const A& at, double c) {
+  const double ax = ((at(1, 0, 0) + at(-1, 0, 0)) + (at(0, 1, 0) + at(0, -1, 0))) +
+                    (at(0, 0, 1) + at(0, 0, -1));
+  const double xy = (at(1, 1, 0) + at(-1, -1, 0)) + (at(1, -1, 0) + at(-1, 1, 0));
+  const double xz = (at(1, 0, 1) + at(1, 0, -1)) + (at(-1, 0, -1) + at(-1, 0, 1));
+  const double yz = (at(0, 1, 1) + at(0, 1, -1)) + (at(0, -1, -1) + at(0, -1, 1));
+  return (2.0 * ax + ((xy + xz) + yz) - 24.0 * c) * (1.0 / 6.0);
+}
+
+// Isotropic central gradient (1/cs2) sum_i w_i c_i phi(x + c_i) at row j,
+// column i of the LDS plane a0, with am and ap the planes at z - 1 and z + 1.
+// Swapping am and ap negates gz exactly and leaves gx, gy unchanged.
+template <int W>
+__device__ __forceinline__ void grad3p(const double (*am)[W], const double (*a0)[W],
+                                       const double (*ap)[W], int j, int i, double& gx,
+                                       double& gy, double& gz) {
+  gx = (a0[j][i + 1] - a0[j][i - 1]) * (1.0 / 6.0) +
+       (((a0[j + 1][i + 1] - a0[j + 1][i - 1]) + (a0[j - 1][i + 1] - a0[j - 1][i - 1])) +
+        ((ap[j][i + 1] - ap[j][i - 1]) + (am[j][i + 1] - am[j][i - 1]))) *
+           (1.0 / 12.0);
+  gy = (a0[j + 1][i] - a0[j - 1][i]) * (1.0 / 6.0) +
+       (((a0[j + 1][i + 1] - a0[j - 1][i + 1]) + (a0[j + 1][i - 1] - a0[j - 1][i - 1])) +
+        ((ap[j + 1][i] - ap[j - 1][i]) + (am[j + 1][i] - am[j - 1][i]))) *
+           (1.0 / 12.0);
+  gz = (ap[j][i] - am[j][i]) * (1.0 / 6.0) +
+       (((ap[j][i + 1] - am[j][i + 1]) + (ap[j][i - 1] - am[j][i - 1])) +
+        ((ap[j + 1][i] - am[j + 1][i]) + (ap[j - 1][i] - am[j - 1][i]))) *
+           (1.0 / 12.0);
+}
+
+// Force (F = -rho grad mu for WB, Eq. 25; plus grad(rho)/3 for the standard
+// scheme, Eq. 6) and the half-force velocity of Eq. (4).
+template <int SCHEME>
+__device__ __forceinline__ void force_velocity3(const double (&f)[Q3], double r, double grx,
+                                                double gry, double grz, double gmx, double gmy,
+                                                double gmz, double& Fx, double& Fy, double& Fz,
+                                                double& ux, double& uy, double& uz) {
+  Fx = -r * gmx;
+  Fy = -r * gmy;
+  Fz = -r * gmz;
+  if (SCHEME == STANDARD) {
+    Fx += grx * (1.0 / 3.0);
+    Fy += gry * (1.0 / 3.0);
+    Fz += grz * (1.0 / 3.0);
+  }
+  double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q3; ++i) {
+    int cx, cy, cz;
+    c3(i, cx, cy, cz);
+    if (cx) jx += cx > 0 ? f[i] : -f[i];
+    if (cy) jy += cy > 0 ? f[i] : -f[i];
+    if (cz) jz += cz > 0 ? f[i] : -f[i];
+  }
+  const double inv = 1.0 / r;
+  ux = (jx + 0.5 * Fx) * inv;
+  uy = (jy + 0.5 * Fy) * inv;
+  uz = (jz + 0.5 * Fz) * inv;
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Blocks b, b+8, ... run on one XCD; give each XCD a contiguous range of
+// work items, so neighbouring tiles share their halo lines in its L2.
+__device__ __forceinline__ int xcd_item(int b, int nb) {
+  const int xcd = b & 7, l = b >> 3, q8 = nb >> 3, r8 = nb & 7;
+  return xcd * q8 + min(xcd, r8) + l;
+}
+
+// Buffer addressing for the fused step.  Each z-plane of populations is
+// below 4 GiB (the library checks), so a plane is one buffer resource (in
+// scalar registers), a node's position in it a 32-bit per-lane byte offset
+// and the population's offset q * plane a scalar offset: no 64-bit per-lane
+// address arithmetic, which would otherwise take a large share of the
+// registers.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RSRC_WORD3 = 0x00020000;  // raw 32-bit data, no swizzle (gfx9 family)
+constexpr int CPOL_NT = 2;              // non-temporal
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_buffer(const double* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)bytes, RSRC_WORD3);
+}
+
+// Pull sources of one node (x, y) within a z-plane: byte offset of the node
+// (x - c_x, y - c_y), periodic, at index [c_y + 1][c_x + 1].
+struct Pull3 {
+  unsigned off[3][3];
+};
+
+__device__ __forceinline__ Pull3 pull_of(const Geometry3& g, int x, int y) {
+  Pull3 s;
+#pragma unroll
+  for (int cy = -1; cy <= 1; ++cy) {
+    const long long row = (long long)wrapi(y - cy, g.ny) * g.pitch;
+#pragma unroll
+    for (int cx = -1; cx <= 1; ++cx)
+      s.off[cy + 1][cx + 1] = (unsigned)((row + wrapi(x - cx, g.nx)) * (long long)sizeof(double));
+  }
+  return s;
+}
+
+// The 19 pulled populations of node s on a plane; b[c_z + 1] is the plane
+// z - c_z, pb the bytes between populations.
+__device__ __forceinline__ void load19(const __amdgpu_buffer_rsrc_t (&b)[3], unsigned pb,
+                                       const Pull3& s, double (&f)[Q3]) {
+#pragma unroll
+  for (int q = 0; q < Q3; ++q) {
+    int cx, cy, cz;
+    c3(q, cx, cy, cz);
+    f[q] = __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(b[cz + 1], s.off[cy + 1][cx + 1], q * pb, 0));
+  }
+}
+
+// Fused step: one block per (32 x TY column, chunk of tl.zc planes).  D:
+// planes of populations loaded ahead of the plane being summed (0 = none).
+constexpr int CG = 3;  // directions per scheduling region of the collision
+template <int SCHEME, int TY, int D>
+__global__ void __launch_bounds__(M3X * TY)
+    march3(Geometry3 g, Physics3 p, Tiling3 tl, const double* __restrict__ fin,
+           double* __restrict__ fout) {
+  constexpr int NT = M3X * TY;
+  constexpr int RX = M3X + 4, RY = TY + 4;  // rho region: tile and a 2-node halo
+  constexpr int MX = M3X + 2, MY = TY + 2;  // mu region: tile and a 1-node halo
+  constexpr int NH = RX * RY - NT;          // halo nodes of the rho region
+  constexpr int NW = NT / 64, HPW = (NH + NW - 1) / NW;
+  static_assert(HPW <= 64, "one halo node per lane");
+  // Populations of planes k-1 .. k+D in a register ring, of plane k-2 in LDS
+  // (each thread its own column); halo of planes k .. k+D-1.
+  constexpr int RP = 2 + D, RH = D > 0 ? D : 1;
+  constexpr int U = (RP % RH == 0) ? RP : RP * RH;  // unroll: slots are compile-time
+  __shared__ double pk[Q3][NT];
+  __shared__ double rs[5][RY][RX];  // region (i, j) is lattice (x0 - 2 + i, y0 - 2 + j)
+  __shared__ double ms[3][MY][MX];  // region (i, j) is lattice (x0 - 1 + i, y0 - 1 + j)
+  const int t = threadIdx.x;
+  const int per_plane = tl.tiles_x * tl.tiles_y;
+  const int item = xcd_item(blockIdx.x, per_plane * tl.chunks);
+  const int chunk = item / per_plane;
+  const int rem = item - chunk * per_plane;
+  const int by = rem / tl.tiles_x, bx = rem - by * tl.tiles_x;
+  const int x0 = bx * M3X, y0 = by * TY, z0 = chunk * tl.zc;
+  const int Z = min(tl.zc, g.nz - z0);
+  const int K = Z + 4;  // planes z0-2 .. z0+Z+1
+  const bool up = (chunk & 1) != 0;
+  // plane index k of the march -> lattice plane
+  auto plane_of = [&](int k) { return wrapi(up ? z0 + Z + 1 - k : z0 - 2 + k, g.nz); };
+
+  const int tx = t % M3X, ty = t / M3X;
+  const bool own = x0 + tx < g.nx && y0 + ty < g.ny;
+  const Pull3 si = pull_of(g, x0 + tx, y0 + ty);
+  // Halo node of this lane: wave w takes halo nodes w*HPW .. w*HPW+HPW-1,
+  // numbered along the two rows above the tile, the side columns, then the
+  // two rows below.
+  const int h = (t >> 6) * HPW + (t & 63);
+  const bool hl = (t & 63) < HPW && h < NH;
+  int hi = 0, hj = 0;
+  if (hl) {
+    if (h < 2 * RX) {
+      hj = h / RX;
+      hi = h - hj * RX;
+    } else if (h < 2 * RX + 4 * TY) {
+      const int e = h - 2 * RX, c = e & 3;
+      hj = 2 + (e >> 2);
+      hi = c < 2 ? c : RX - 4 + c;
+    } else {
+      const int e = h - 2 * RX - 4 * TY;
+      hj = TY + 2 + e / RX;
+      hi = e - (e / RX) * RX;
+    }
+  }
+  const Pull3 sh = pull_of(g, x0 - 2 + hi, y0 - 2 + hj);
+
+  const unsigned pb = (unsigned)(g.plane * (long long)sizeof(double));
+  const unsigned slab_bytes = (unsigned)(g.slab * (long long)sizeof(double));
+  const unsigned own_off =
+      (unsigned)(((long long)(y0 + ty) * g.pitch + (x0 + tx)) * (long long)sizeof(double));
+
+  // Loads of plane k.
+  auto load_plane = [&](int k, double(&Pl)[Q3], double(&Hl)[Q3]) {
+    const int z = plane_of(k);
+    __amdgpu_buffer_rsrc_t b[3];
+#pragma unroll
+    for (int c = -1; c <= 1; ++c)
+      b[c + 1] = plane_buffer(fin + (long long)wrapi(z - c, g.nz) * g.slab, slab_bytes);
+    load19(b, pb, si, Pl);
+    if (hl) load19(b, pb, sh, Hl);
+  };
+
+  // Plane step k: publish rho of plane k (populations in Pk, halo in Hk),
+  // start the loads of plane k+D (into Pn, Hk), mu of plane k-1, update the
+  // nodes of plane k-2 (populations parked in LDS), park plane k-1 (Pm).
+  auto stage = [&](int k, double(&Pk)[Q3], double(&Hk)[Q3], double(&Pn)[Q3],
+                   double(&Pm)[Q3]) {
+    if (D == 0) load_plane(k, Pk, Hk);
+    const int sk = k % 5;
+    rs[sk][ty + 2][tx + 2] = sum19(Pk);
+    if (hl) rs[sk][hj][hi] = sum19(Hk);
+    if (D > 0 && k + D < K) load_plane(k + D, Pn, Hk);
+    __syncthreads();
+    if (k >= 2) {
+      const int sm = (k - 2) % 5, s0 = (k - 1) % 5, mk = (k - 1) % 3;
+      for (int e = t; e < MX * MY; e += NT) {
+        const int mj = e / MX, mi = e - mj * MX;
+        const int i = mi + 1, j = mj + 1;
+        auto at = [&](int dx, int dy, int dz) {
+          return rs[dz < 0 ? sm : (dz > 0 ? sk : s0)][j + dy][i + dx];
+        };
+        const double r0 = rs[s0][j][i];
+        ms[mk][mj][mi] = mu0_3(r0, p) - p.kappa * lap19(at, r0);
+      }
+    }
+    __syncthreads();
+    if (own) {
+      // Gradients first, then plane k-2 out of LDS and plane k-1 in (each
+      // thread its own column), then the collision: the scheduling barriers
+      // keep the phases apart, so their temporaries are not live at once.
+      const int c = k - 2;
+      double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0, r = 1.0;
+      if (k >= 4) {
+        const int sM = (c - 1) % 5, s0 = c % 5, sP = (c + 1) % 5;
+        const int mM = (c - 1) % 3, m0 = c % 3, mP = (c + 1) % 3;
+        grad3p<RX>(rs[sM], rs[s0], rs[sP], ty + 2, tx + 2, grx, gry, grz);
+        grad3p<MX>(ms[mM], ms[m0], ms[mP], ty + 1, tx + 1, gmx, gmy, gmz);
+        r = rs[s0][ty + 2][tx + 2];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      double f[Q3];
+      if (k >= 4) {
+#pragma unroll
+        for (int q = 0; q < Q3; ++q) f[q] = pk[q][t];
+      }
+      if (k >= 3) {
+#pragma unroll
+        for (int q = 0; q < Q3; ++q) pk[q][t] = Pm[q];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (k >= 4) {
+        if (up) {  // plane k-1 of the march lies at +z
+          grz = -grz;
+          gmz = -gmz;
+        }
+        double Fx, Fy, Fz, ux, uy, uz;
+        force_velocity3<SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
+        const __amdgpu_buffer_rsrc_t o =
+            plane_buffer(fout + (long long)plane_of(c) * g.slab, slab_bytes);
+        collide3<SCHEME, CG>(f, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p,
+                             [&](int q, double v) {
+                               __builtin_amdgcn_raw_buffer_store_b64(
+                                   __builtin_bit_cast(u32x2, v), o, own_off, q * pb, CPOL_NT);
+                             });
+      }
+    }
+  };
+
+  double P[RP][Q3], H[RH][Q3];
+#pragma unroll
+  for (int k = 0; k < D; ++k) load_plane(k, P[k], H[k % RH]);
+  for (int k0 = 0; k0 < K; k0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < K)
+        stage(k0 + u, P[u % RP], H[u % RH], P[(u + D) % RP], P[(u + RP - 1) % RP]);
   }
 }
 
@@ -85,10 +385,10 @@ __global__ void __launch_bounds__(256)
     density3(Geometry3 g, const Global<double>* __restrict__ fin, double* __restrict__ rho) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
-  double s = 0.0;
+  double f[Q3];
 #pragma unroll
-  for (int i = 0; i < Q3; ++i) s += fin[(long long)i * g.plane + src3(g, i, x, y, z)];
-  rho[((long long)z * g.ny + y) * g.nx + x] = s;
+  for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
+  rho[((long long)z * g.ny + y) * g.nx + x] = sum19(f);
 }
 
 __global__ void __launch_bounds__(256)
@@ -96,51 +396,22 @@ __global__ void __launch_bounds__(256)
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
   auto at = [&](int dx, int dy, int dz) {
-    int a = x + dx, b = y + dy, c = z + dz;
-    a = a < 0 ? a + g.nx : (a >= g.nx ? a - g.nx : a);
-    b = b < 0 ? b + g.ny : (b >= g.ny ? b - g.ny : b);
-    c = c < 0 ? c + g.nz : (c >= g.nz ? c - g.nz : c);
+    const int a = wrapi(x + dx, g.nx), b = wrapi(y + dy, g.ny), c = wrapi(z + dz, g.nz);
     return rho[((long long)c * g.ny + b) * g.nx + a];
   };
   const double c = at(0, 0, 0);
-  double ax = 0.0, ed = 0.0;
-#pragma unroll
-  for (int i = 1; i < Q3; ++i) {
-    int cx, cy, cz;
-    c3(i, cx, cy, cz);
-    if (i < 7)
-      ax += at(cx, cy, cz);
-    else
-      ed += at(cx, cy, cz);
-  }
-  const double lap = (2.0 * ax + ed - 24.0 * c) * (1.0 / 6.0);
-  mu[((long long)z * g.ny + y) * g.nx + x] = mu0_3(c, p) - p.kappa * lap;
+  mu[((long long)z * g.ny + y) * g.nx + x] = mu0_3(c, p) - p.kappa * lap19(at, c);
 }
 
-constexpr int T3X = 32, T3Y = 4, T3Z = 2;  // collide-stream block (threads)
+constexpr int T3X = 32, T3Y = 4, T3Z = 2;  // observe block (threads)
 
-// Isotropic central gradient of an LDS tile at tile point (k, j, i).
-__device__ __forceinline__ void grad3(const double (&a)[T3Z + 2][T3Y + 2][T3X + 2], int k, int j,
-                                      int i, double& gx, double& gy, double& gz) {
-  gx = (a[k][j][i + 1] - a[k][j][i - 1]) * (1.0 / 6.0) +
-       ((a[k][j + 1][i + 1] - a[k][j + 1][i - 1]) + (a[k][j - 1][i + 1] - a[k][j - 1][i - 1]) +
-        (a[k + 1][j][i + 1] - a[k + 1][j][i - 1]) + (a[k - 1][j][i + 1] - a[k - 1][j][i - 1])) *
-           (1.0 / 12.0);
-  gy = (a[k][j + 1][i] - a[k][j - 1][i]) * (1.0 / 6.0) +
-       ((a[k][j + 1][i + 1] - a[k][j - 1][i + 1]) + (a[k][j + 1][i - 1] - a[k][j - 1][i - 1]) +
-        (a[k + 1][j + 1][i] - a[k + 1][j - 1][i]) + (a[k - 1][j + 1][i] - a[k - 1][j - 1][i])) *
-           (1.0 / 12.0);
-  gz = (a[k + 1][j][i] - a[k - 1][j][i]) * (1.0 / 6.0) +
-       ((a[k + 1][j][i + 1] - a[k - 1][j][i + 1]) + (a[k + 1][j][i - 1] - a[k - 1][j][i - 1]) +
-        (a[k + 1][j + 1][i] - a[k - 1][j + 1][i]) + (a[k + 1][j - 1][i] - a[k - 1][j - 1][i])) *
-           (1.0 / 12.0);
-}
-
-template <int SCHEME, bool OBSERVE>
+// Fields and per-block partials (max|u|, mass, kinetic energy, non-finite
+// flag) of the state f, from dense rho and mu.
+template <int SCHEME>
 __global__ void __launch_bounds__(T3X * T3Y * T3Z)
-    collide3_kernel(Geometry3 g, Physics3 p, const Global<double>* __restrict__ fin,
-                    Global<double>* __restrict__ fout, const double* __restrict__ rho,
-                    const double* __restrict__ mu, ObserveOut3 obs) {
+    observe3_kernel(Geometry3 g, const Global<double>* __restrict__ fin,
+                    const double* __restrict__ rho, const double* __restrict__ mu,
+                    ObserveOut3 obs) {
   __shared__ double rt[T3Z + 2][T3Y + 2][T3X + 2];
   __shared__ double mt[T3Z + 2][T3Y + 2][T3X + 2];
   const int tid = threadIdx.x;
@@ -149,10 +420,8 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
   constexpr int TILE = (T3Z + 2) * (T3Y + 2) * (T3X + 2);
   for (int e = tid; e < TILE; e += T3X * T3Y * T3Z) {
     const int i = e % (T3X + 2), j = (e / (T3X + 2)) % (T3Y + 2), k = e / ((T3X + 2) * (T3Y + 2));
-    int xx = (x0 + i - 1) % g.nx, yy = (y0 + j - 1) % g.ny, zz = (z0 + k - 1) % g.nz;
-    xx = xx < 0 ? xx + g.nx : xx;
-    yy = yy < 0 ? yy + g.ny : yy;
-    zz = zz < 0 ? zz + g.nz : zz;
+    const int xx = wrapi(x0 + i - 1, g.nx), yy = wrapi(y0 + j - 1, g.ny),
+              zz = wrapi(z0 + k - 1, g.nz);
     const long long o = ((long long)zz * g.ny + yy) * g.nx + xx;
     rt[k][j][i] = rho[o];
     mt[k][j][i] = mu[o];
@@ -166,44 +435,22 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
     for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
     const double r = rt[tz + 1][ty + 1][tx + 1];
     double grx, gry, grz, gmx, gmy, gmz;
-    grad3(rt, tz + 1, ty + 1, tx + 1, grx, gry, grz);
-    grad3(mt, tz + 1, ty + 1, tx + 1, gmx, gmy, gmz);
-    double Fx = -r * gmx, Fy = -r * gmy, Fz = -r * gmz;
-    if (SCHEME == STANDARD) {
-      Fx += grx * (1.0 / 3.0);
-      Fy += gry * (1.0 / 3.0);
-      Fz += grz * (1.0 / 3.0);
-    }
-    double jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q3; ++i) {
-      int cx, cy, cz;
-      c3(i, cx, cy, cz);
-      jx += cx * f[i];
-      jy += cy * f[i];
-      jz += cz * f[i];
-    }
-    const double inv = 1.0 / r;
-    const double ux = (jx + 0.5 * Fx) * inv, uy = (jy + 0.5 * Fy) * inv, uz = (jz + 0.5 * Fz) * inv;
-    if (!OBSERVE) {
-      collide3<SCHEME>(f, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p);
-      Global<double>* dst = fout + (long long)z * g.slab + (long long)y * g.pitch + x;
-#pragma unroll
-      for (int i = 0; i < Q3; ++i) __builtin_nontemporal_store(f[i], dst + (long long)i * g.plane);
-    } else {
-      const long long o = ((long long)z * g.ny + y) * g.nx + x;
-      if (obs.ux) obs.ux[o] = ux;
-      if (obs.uy) obs.uy[o] = uy;
-      if (obs.uz) obs.uz[o] = uz;
-      const double u2 = ux * ux + uy * uy + uz * uz;
-      const double um = sqrt(u2);
-      if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
-      umax = um;
-      mass = r;
-      ekin = 0.5 * r * u2;
-    }
+    grad3p<T3X + 2>(rt[tz], rt[tz + 1], rt[tz + 2], ty + 1, tx + 1, grx, gry, grz);
+    grad3p<T3X + 2>(mt[tz], mt[tz + 1], mt[tz + 2], ty + 1, tx + 1, gmx, gmy, gmz);
+    double Fx, Fy, Fz, ux, uy, uz;
+    force_velocity3<SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
+    const long long o = ((long long)z * g.ny + y) * g.nx + x;
+    if (obs.ux) obs.ux[o] = ux;
+    if (obs.uy) obs.uy[o] = uy;
+    if (obs.uz) obs.uz[o] = uz;
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    const double um = sqrt(u2);
+    if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
+    umax = um;
+    mass = r;
+    ekin = 0.5 * r * u2;
   }
-  if (OBSERVE && obs.partials) {
+  if (obs.partials) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       umax = fmax(umax, __shfl_xor(umax, off));
@@ -322,36 +569,83 @@ hipError_t launch_unpack3(const Geometry3& g, const void* f, int q0, int m, doub
   return hipGetLastError();
 }
 
+Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth) {
+  Tiling3 t{};
+  t.ty = ty;
+  t.depth = depth;
+  t.tiles_x = (g.nx + M3X - 1) / M3X;
+  t.tiles_y = (g.ny + ty - 1) / ty;
+  if (zc <= 0) {
+    // about 1024 blocks (four per CU), chunks of at least 16 planes
+    const long long per = (long long)t.tiles_x * t.tiles_y;
+    long long ch = (1024 + per - 1) / per;
+    ch = std::max(1LL, std::min(ch, (long long)(g.nz + 15) / 16));
+    zc = (int)((g.nz + ch - 1) / ch);
+  }
+  t.zc = std::min(zc, g.nz);
+  t.chunks = (g.nz + t.zc - 1) / t.zc;
+  return t;
+}
+
+bool tiling3_supported(int ty, int depth) {
+  return (ty == 8 && depth >= 1 && depth <= 3) || (ty == 16 && depth >= 1 && depth <= 2);
+}
+
+long long blocks_of(const Tiling3& t) { return (long long)t.tiles_x * t.tiles_y * t.chunks; }
+
 namespace {
 
-template <bool OBS>
-hipError_t launch3(int scheme, const Geometry3& g, const Physics3& ph, const void* fin, void* fout,
-                   double* rho, double* mu, const ObserveOut3& o, hipStream_t s) {
-  const auto* in = (const Global<double>*)(const double*)fin;
-  auto* out = (Global<double>*)(double*)fout;
-  hipLaunchKernelGGL(density3, grid_rows3(g), dim3(256), 0, s, g, in, rho);
-  hipLaunchKernelGGL(potential3, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
-  const dim3 gc((g.nx + T3X - 1) / T3X, (g.ny + T3Y - 1) / T3Y, (g.nz + T3Z - 1) / T3Z);
-  if (scheme == STANDARD)
-    hipLaunchKernelGGL((collide3_kernel<STANDARD, OBS>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, ph,
-                       in, out, (const double*)rho, (const double*)mu, o);
+template <int SCHEME, int TY, int D>
+void launch_m3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const double* in,
+               double* out, long long nb, hipStream_t s) {
+  hipLaunchKernelGGL((march3<SCHEME, TY, D>), dim3((unsigned)nb), dim3(M3X * TY), 0, s, g, ph, t,
+                     in, out);
+}
+
+template <int SCHEME>
+hipError_t launch_march3(const Geometry3& g, const Physics3& ph, const Tiling3& t,
+                         const double* in, double* out, hipStream_t s) {
+  const long long nb = blocks_of(t);
+  if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (t.ty == 8 && t.depth == 1)
+    launch_m3<SCHEME, 8, 0>(g, ph, t, in, out, nb, s);
+  else if (t.ty == 8 && t.depth == 2)
+    launch_m3<SCHEME, 8, 1>(g, ph, t, in, out, nb, s);
+  else if (t.ty == 8 && t.depth == 3)
+    launch_m3<SCHEME, 8, 2>(g, ph, t, in, out, nb, s);
+  else if (t.ty == 16 && t.depth == 1)
+    launch_m3<SCHEME, 16, 0>(g, ph, t, in, out, nb, s);
+  else if (t.ty == 16 && t.depth == 2)
+    launch_m3<SCHEME, 16, 1>(g, ph, t, in, out, nb, s);
   else
-    hipLaunchKernelGGL((collide3_kernel<WELL_BALANCED, OBS>), gc, dim3(T3X * T3Y * T3Z), 0, s, g,
-                       ph, in, out, (const double*)rho, (const double*)mu, o);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const void* fin,
-                        void* fout, double* rho, double* mu, hipStream_t s) {
-  const ObserveOut3 none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  return launch3<false>(scheme, g, ph, fin, fout, rho, mu, none, s);
+hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const Tiling3& t,
+                        const void* fin, void* fout, hipStream_t s) {
+  if (g.slab * (long long)sizeof(double) > 0xffffffffLL) return hipErrorInvalidValue;
+  const auto* in = (const double*)fin;
+  auto* out = (double*)fout;
+  return scheme == STANDARD ? launch_march3<STANDARD>(g, ph, t, in, out, s)
+                            : launch_march3<WELL_BALANCED>(g, ph, t, in, out, s);
 }
 
 hipError_t launch_observe3(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
                            double* rho, double* mu, const ObserveOut3& o, hipStream_t s) {
-  return launch3<true>(scheme, g, ph, f, nullptr, rho, mu, o, s);
+  const auto* in = (const Global<double>*)(const double*)f;
+  hipLaunchKernelGGL(density3, grid_rows3(g), dim3(256), 0, s, g, in, rho);
+  hipLaunchKernelGGL(potential3, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
+  const dim3 gc((g.nx + T3X - 1) / T3X, (g.ny + T3Y - 1) / T3Y, (g.nz + T3Z - 1) / T3Z);
+  if (scheme == STANDARD)
+    hipLaunchKernelGGL(observe3_kernel<STANDARD>, gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
+                       (const double*)rho, (const double*)mu, o);
+  else
+    hipLaunchKernelGGL(observe3_kernel<WELL_BALANCED>, gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
+                       (const double*)rho, (const double*)mu, o);
+  return hipGetLastError();
 }
 
 }  // namespace lbmk

@@ -42,8 +42,13 @@ def test_workspace_bytes_rejects_bad_params(lib):
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=-1),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=8, precision="fp32s"),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=8, force_stencil=1),
-                P(2048, 2048, 1.0, 0.1, 0.02, 1, 0.1, nz=1024)]:
+                P(2048, 2048, 1.0, 0.1, 0.02, 1, 0.1, nz=1024),
+                # a z-plane of 19 * 4096 * 8192 * 8 bytes is over 4 GiB
+                P(8192, 4096, 1.0, 0.1, 0.02, 1, 0.1, nz=2)]:
         assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    # the largest z-plane: 19 * 4096 * 6880 * 8 bytes, just below 4 GiB
+    assert lib.lbm_workspace_bytes(ctypes.byref(P(6880, 4096, 1.0, 0.1, 0.02, 1, 0.1, nz=2))) > 0
+    assert lib.lbm_workspace_bytes(ctypes.byref(P(6912, 4096, 1.0, 0.1, 0.02, 1, 0.1, nz=2))) == 0
     # a 3-D (D3Q19) lattice: two copies of 19 populations + 5 fields of staging
     p3 = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, nz=40)
     n3 = lib.lbm_workspace_bytes(ctypes.byref(p3))
