@@ -260,17 +260,19 @@ def finite_state(steps, warmup):
     return res
 
 
-STENCIL4_BYTES = 256   # FP64 bytes per node of the three-pass variant step
+STENCIL4_BYTES = 144   # FP64 bytes per node of the variant step: 9 populations read and written
 
 
-def time_stencil4(prob, steps, warmup, scheme="standard"):
+def time_stencil4(prob, steps, warmup, scheme="standard", tile=None):
     """The force-stencil variant (fourth-order gradients in the force, FP64):
-    three passes per step, so 256 algorithmic bytes per node (density: 72
-    read + 8 written; chemical potential: 8 + 8; collide-stream: 9 + 2 fields
-    read, 9 written)."""
+    one fused pass per step, 9 populations read and written = 144
+    algorithmic bytes per node.  `tile` (block, rows, depth) overrides the
+    default."""
     import torch
     from paper_2012_11075_amd import lbm
     s = lbm.Solver.for_problem(prob, force_stencil=1)
+    if tile:
+        s.set_tile(*tile)
     s.init(prob.rho(), scheme=scheme)
     s.step(warmup, scheme)
     torch.cuda.synchronize()
@@ -282,13 +284,16 @@ def time_stencil4(prob, steps, warmup, scheme="standard"):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    kps = s.lib.lbm_kernels_per_step(s.ctx)
+    used = s.get_tile()
     s.close()
     del s
     torch.cuda.empty_cache()
     nodes = prob.nx * prob.ny
     gbs = STENCIL4_BYTES * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
-            "scheme": scheme, "kernels_per_step": 3, "bytes_per_update": STENCIL4_BYTES,
+            "scheme": scheme, "kernels_per_step": kps, "tile": list(used),
+            "bytes_per_update": STENCIL4_BYTES,
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "workload": "%s, %s scheme, fourth-order force stencil, FP64, %d steps"
                         % (prob.name, scheme, steps)}
@@ -401,6 +406,7 @@ def main():
               "(multi-GPU decomposition is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import tune
     prob = I.DROPLET_4096
     ref = copy_reference(prob.nx, prob.ny)
     progress("copy reference %s" % ref)
@@ -454,7 +460,8 @@ def main():
         out["finite_state"] = finite_state(args.steps, args.warmup)
         progress("finite-state companion done")
     if not args.no_stencil4:
-        out["force_stencil4"] = time_stencil4(prob, 200, 5)
+        out["force_stencil4"] = time_stencil4(prob, 200, 5,
+                                              tile=tune.bench_tile(prob.nx, prob.ny, "fp64"))
         progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
     if not args.no_d3:
         out["d3q19"] = time_d3q19(100, 5)

@@ -253,9 +253,8 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
       HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
                                    c->buf(1 - c->cur), s));
     } else if (c->prm.force_stencil == 1) {
-      // rho and mu of the step go through the staging fields 0 and 3
-      HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->buf(c->cur), c->buf(1 - c->cur),
-                                   c->staging(), c->staging() + 3 * c->nodes(), s));
+      HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->tl, c->buf(c->cur), c->buf(1 - c->cur),
+                                   s));
     } else {
       HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
                                   c->buf(1 - c->cur), s));
@@ -603,6 +602,8 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
   if (depth < 1 || depth > 3) return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3");
   if (!lbmk::block_width_supported(block))
     return fail(c, LBM_EINVAL, "unsupported block width " + std::to_string(block));
+  if (c->prm.force_stencil == 1 && !lbmk::stencil4_block_supported(block))
+    return fail(c, LBM_EINVAL, "the force-stencil variant runs on block widths 256 and 512");
   if (rows < MIN_ROWS) return fail(c, LBM_EINVAL, "rows must be >= 4");
   lbmk::Tiling t = make_tiling(c->L.g, block, rows, depth);
   if ((size_t)t.blocks() > c->L.partial_count)
@@ -655,7 +656,7 @@ const char* lbm_last_error(const lbm_ctx* c) {
 }
 
 int32_t lbm_kernels_per_step(const lbm_ctx* c) {
-  return c && c->prm.force_stencil == 1 ? 3 : 1;
+  return 1;
 }
 
 }  // extern "C"

@@ -444,9 +444,10 @@ __device__ __forceinline__ long long src_offset(const Geometry& g, int q, int x,
 // the central gradient's isotropic second-order error (1-D:
 // (-phi_{j+2} + 8 phi_{j+1} - 8 phi_{j-1} + phi_{j-2})/12).  The paper's
 // point is that this shrinks the net force of the standard scheme at
-// equilibrium but cannot remove it.  FP64, three passes per step: density,
-// chemical potential, then collide-stream on LDS tiles of rho and mu with a
-// 2-node halo.  Expanded, the x-derivative's 5 x 5 weights are, for rows
+// equilibrium but cannot remove it.  FP64.  The step is one fused pass
+// (`march4`); the observe pass takes three: density, chemical potential,
+// then fields and reductions on LDS tiles of rho and mu with a 2-node halo.
+// Expanded, the x-derivative's 5 x 5 weights are, for rows
 // dy = 0, +-1, +-2 and columns dx = 1, 2 (odd in dx):
 //   dy = 0:   1/2,    -1/24
 //   dy = +-1: 5/54,   -1/54
@@ -484,34 +485,40 @@ __global__ void __launch_bounds__(256)
 
 constexpr int S4X = 64, S4Y = 4;  // collide-stream tile (threads)
 
-// Fourth-order gradient of a (S4Y+4) x (S4X+4) LDS tile at tile point (i, j).
-__device__ __forceinline__ void grad4(const double (&a)[S4Y + 4][S4X + 4], int i, int j,
-                                      double& gx, double& gy) {
-  auto dx1 = [&](int r) { return a[r][j + 1] - a[r][j - 1]; };
-  auto dx2 = [&](int r) { return a[r][j + 2] - a[r][j - 2]; };
-  auto dy1 = [&](int c) { return a[i + 1][c] - a[i - 1][c]; };
-  auto dy2 = [&](int c) { return a[i + 2][c] - a[i - 2][c]; };
-  gx = 0.5 * dx1(i) - (1.0 / 24.0) * dx2(i) + (5.0 / 54.0) * (dx1(i + 1) + dx1(i - 1)) -
-       (1.0 / 54.0) * (dx2(i + 1) + dx2(i - 1)) - (1.0 / 108.0) * (dx1(i + 2) + dx1(i - 2)) -
-       (1.0 / 432.0) * (dx2(i + 2) + dx2(i - 2));
+// Fourth-order gradient at column j from the five rows y-2 .. y+2 (m2, m1,
+// r0, p1, p2).  Swapping the rows (m2 <-> p2, m1 <-> p1) negates gy exactly
+// and leaves gx unchanged.
+__device__ __forceinline__ void grad4r(const double* m2, const double* m1, const double* r0,
+                                       const double* p1, const double* p2, int j, double& gx,
+                                       double& gy) {
+  auto dx1 = [&](const double* r) { return r[j + 1] - r[j - 1]; };
+  auto dx2 = [&](const double* r) { return r[j + 2] - r[j - 2]; };
+  auto dy1 = [&](int c) { return p1[c] - m1[c]; };
+  auto dy2 = [&](int c) { return p2[c] - m2[c]; };
+  gx = 0.5 * dx1(r0) - (1.0 / 24.0) * dx2(r0) + (5.0 / 54.0) * (dx1(p1) + dx1(m1)) -
+       (1.0 / 54.0) * (dx2(p1) + dx2(m1)) - (1.0 / 108.0) * (dx1(p2) + dx1(m2)) -
+       (1.0 / 432.0) * (dx2(p2) + dx2(m2));
   gy = 0.5 * dy1(j) - (1.0 / 24.0) * dy2(j) + (5.0 / 54.0) * (dy1(j + 1) + dy1(j - 1)) -
        (1.0 / 54.0) * (dy2(j + 1) + dy2(j - 1)) - (1.0 / 108.0) * (dy1(j + 2) + dy1(j - 2)) -
        (1.0 / 432.0) * (dy2(j + 2) + dy2(j - 2));
 }
 
-// Pass 3: force with the fourth-order gradients, velocity, equilibrium,
-// forcing term and BGK of every node; the post-collision populations stay at
-// their node (pull form, as in the fused step).  With OBSERVE it writes the
-// fields and per-block partials (max|u|, mass, kinetic energy, non-finite)
-// instead of stepping.
-template <int SCHEME, bool OBSERVE>
+// The same on a (S4Y+4) x (S4X+4) LDS tile at tile point (i, j).
+__device__ __forceinline__ void grad4(const double (&a)[S4Y + 4][S4X + 4], int i, int j,
+                                      double& gx, double& gy) {
+  grad4r(a[i - 2], a[i - 1], a[i], a[i + 1], a[i + 2], j, gx, gy);
+}
+
+// Pass 3 of the observe pass: force with the fourth-order gradients and
+// velocity of every node; writes the velocity fields and per-block partials
+// (max|u|, mass, kinetic energy, non-finite).
+template <int SCHEME>
 __global__ void __launch_bounds__(S4X * S4Y)
-    collide4(Geometry g, Physics phys, const Global<double>* __restrict__ fin,
-             Global<double>* __restrict__ fout, const double* __restrict__ rho,
-             const double* __restrict__ mu, ObserveOut obs) {
+    observe4_kernel(Geometry g, const Global<double>* __restrict__ fin,
+                    const double* __restrict__ rho, const double* __restrict__ mu,
+                    ObserveOut obs) {
   __shared__ double rt[S4Y + 4][S4X + 4];
   __shared__ double mt[S4Y + 4][S4X + 4];
-  const PhysR<double> p = to_r<double>(phys);
   const int tx = threadIdx.x % S4X, ty = threadIdx.x / S4X;
   const int x0 = blockIdx.x * S4X, y0 = blockIdx.y * S4Y;
   for (int e = threadIdx.x; e < (S4Y + 4) * (S4X + 4); e += S4X * S4Y) {
@@ -541,24 +548,17 @@ __global__ void __launch_bounds__(S4X * S4Y)
     }
     double ux, uy;
     velocity(f, r, Fx, Fy, ux, uy);
-    if (!OBSERVE) {
-      collide<double, SCHEME>(f, r, r, ux, uy, Fx, Fy, grx, gry, p);
-      Global<double>* dst = fout + (long long)y * g.pitch + x;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(f[i], dst + (long long)i * g.plane);
-    } else {
-      const long long o = (long long)y * g.nx + x;
-      if (obs.ux) obs.ux[o] = ux;
-      if (obs.uy) obs.uy[o] = uy;
-      const double u2 = ux * ux + uy * uy;
-      const double um = sqrt(u2);
-      if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
-      umax = um;
-      mass = r;
-      ekin = 0.5 * r * u2;
-    }
+    const long long o = (long long)y * g.nx + x;
+    if (obs.ux) obs.ux[o] = ux;
+    if (obs.uy) obs.uy[o] = uy;
+    const double u2 = ux * ux + uy * uy;
+    const double um = sqrt(u2);
+    if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
+    umax = um;
+    mass = r;
+    ekin = 0.5 * r * u2;
   }
-  if (OBSERVE && obs.partials) {
+  if (obs.partials) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       umax = fmax(umax, __shfl_xor(umax, off));
@@ -588,6 +588,180 @@ __global__ void __launch_bounds__(S4X * S4Y)
       out[1] = m;
       out[2] = e;
       out[3] = z;
+    }
+  }
+}
+
+// Fused step of the force-stencil variant (FP64): one HBM pass per step, as
+// `march`, with the fourth-order gradients.  The gradients reach two nodes
+// and the Laplacian inside mu one more, so the rho ring holds 7 rows
+// (y-3 .. y+3), the mu ring 5, the x-halo is 3 columns on each side (54
+// lanes of wave 0 load one population each), and a row is updated 3 rows
+// after it is loaded (rows k-3 .. k-1 wait in LDS).  Stencil sums pair the
+// rows above and below, so the march direction changes no bit of the result.
+template <int SCHEME, int BW, int D>
+__global__ void __launch_bounds__(BW)
+    march4(Geometry g, Physics phys, Tiling tl, const Global<double>* __restrict__ fin,
+           Global<double>* __restrict__ fout) {
+  using R = double;
+  __shared__ R rs[7][BW + 6];  // column j: lattice column x0 - 3 + j
+  __shared__ R ms[5][BW + 4];  // column m: lattice column x0 - 2 + m
+  __shared__ R fl[3][Q][BW];   // populations of rows k-3 .. k-1, each thread its own column
+  const PhysR<R> p = to_r<R>(phys);
+  const int t = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, tl.strips * tl.chunks);
+  const int chunk = tile / tl.strips;
+  const int strip = tile - chunk * tl.strips;
+  const int x0 = strip * BW;
+  const int x = x0 + t;
+  const bool outc = x < g.nx;
+  const int xc = x % g.nx;
+  const int y0 = chunk * tl.rows;
+  const int H = min(tl.rows, g.ny - y0);
+  const int K = H + 6;
+  // Odd chunks march upward (as in `march`); row index k is lattice row
+  // y0 - 3 + k (down) or y0 + H + 2 - k (up).
+  const bool up = (chunk & 1) != 0;
+  auto wrapy = [&](int y) {
+    y %= g.ny;
+    return y < 0 ? y + g.ny : y;
+  };
+  auto row_of = [&](int k) { return wrapy(up ? y0 + H + 2 - k : y0 - 3 + k); };
+
+  const int xw = (xc == 0) ? g.nx - 1 : xc - 1;
+  const int xe = (xc + 1 == g.nx) ? 0 : xc + 1;
+  auto load_row = [&](int k, R(&dst)[Q]) {
+    const int y = row_of(k);
+    const int yu = (y == 0) ? g.ny - 1 : y - 1;
+    const int yd = (y + 1 == g.ny) ? 0 : y + 1;
+    const long long P = g.plane;
+    const long long r0 = (long long)y * g.pitch, ru = (long long)yu * g.pitch,
+                    rd = (long long)yd * g.pitch;
+    dst[0] = fin[r0 + xc];
+    dst[1] = fin[P + r0 + xw];
+    dst[2] = fin[2 * P + ru + xc];
+    dst[3] = fin[3 * P + r0 + xe];
+    dst[4] = fin[4 * P + rd + xc];
+    dst[5] = fin[5 * P + ru + xw];
+    dst[6] = fin[6 * P + ru + xe];
+    dst[7] = fin[7 * P + rd + xe];
+    dst[8] = fin[8 * P + rd + xw];
+  };
+
+  // Halo columns x0-3 .. x0-1 and x0+BW .. x0+BW+2: lane L < 54 of wave 0
+  // loads population L%9 of halo column L/9; rho is gathered by shuffles and
+  // summed in the interior order.
+  const bool hl = t < 6 * Q;
+  const int hcol = t / Q, hq = t - Q * (t / Q);
+  const int hslot = hcol < 3 ? hcol : BW + hcol;  // rho-ring column of the halo
+  int hsx = 0, hcy = 0;
+  long long hplane = 0;
+  if (hl) {
+    // c_x, c_y of velocity hq (paper numbering), without an indexed array
+    const int cxq = (hq == 1 || hq == 5 || hq == 8) ? 1 : ((hq == 3 || hq == 6 || hq == 7) ? -1 : 0);
+    const int cyq = (hq == 2 || hq == 5 || hq == 6) ? 1 : ((hq == 4 || hq == 7 || hq == 8) ? -1 : 0);
+    int hc = hcol < 3 ? x0 - 3 + hcol : x0 + BW + hcol - 3;
+    hc = ((hc % g.nx) + g.nx) % g.nx;
+    hsx = hc - cxq;
+    hsx = hsx < 0 ? hsx + g.nx : (hsx >= g.nx ? hsx - g.nx : hsx);
+    hcy = cyq;
+    hplane = (long long)hq * g.plane;
+  }
+  auto load_halo = [&](int k, R& dst) {
+    if (hl) dst = fin[hplane + (long long)wrapy(row_of(k) - hcy) * g.pitch + hsx];
+  };
+
+  // One row step: prefetch row k+D; publish rho of row k (`cur`); mu of row
+  // k-1; update the node of row k-3.
+  auto stage = [&](int k, R(&nxt)[Q], R(&cur)[Q], R& hnxt, R& hcur) {
+    load_row(k + D, nxt);  // rows past the chunk are valid (periodic) and unused
+    load_halo(k + D, hnxt);
+    const int sk = k % 7;
+    rs[sk][t + 3] = sum9(cur);
+    if (t < 64) {
+      const int base = (hl ? hcol : 0) * Q;
+      R v[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = __shfl(hcur, base + i);
+      if (hl && hq == 0) rs[sk][hslot] = sum9(v);
+    }
+    const int fk = k % 3;
+    R out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      out[i] = fl[fk][i][t];  // row k-3 (garbage for k < 3, unused)
+      fl[fk][i][t] = cur[i];
+    }
+    __syncthreads();
+    if (k >= 2) {
+      // mu at row index k-1 and mu-ring column m (rho-ring columns m .. m+2)
+      const int a = (k - 2) % 7, c0 = (k - 1) % 7, d = sk, mk = (k - 1) % 5;
+      auto mu_at = [&](int m) {
+        const R r0 = rs[c0][m + 1];
+        const R ax = (rs[c0][m + 2] + rs[c0][m]) + (rs[a][m + 1] + rs[d][m + 1]);
+        const R dg = (rs[a][m + 2] + rs[a][m]) + (rs[d][m + 2] + rs[d][m]);
+        const R lap = ((R)4 * ax + dg - (R)20 * r0) * ((R)1 / (R)6);
+        ms[mk][m] = mu0(r0, p) - p.kappa * lap;
+      };
+      mu_at(t + 2);
+      if (t < 4) mu_at(t < 2 ? t : BW + t);
+    }
+    __syncthreads();
+    if (k >= 6 && k < K && outc) {
+      const int q2 = (k - 5) % 7, q1 = (k - 4) % 7, q0 = (k - 3) % 7, p1 = (k - 2) % 7,
+                p2 = (k - 1) % 7;
+      const int n2 = (k - 5) % 5, n1 = (k - 4) % 5, n0 = (k - 3) % 5, o1 = (k - 2) % 5,
+                o2 = (k - 1) % 5;
+      const R rho = rs[q0][t + 3];
+      R grx, gry, gmx, gmy;
+      grad4r(rs[q2], rs[q1], rs[q0], rs[p1], rs[p2], t + 3, grx, gry);
+      grad4r(ms[n2], ms[n1], ms[n0], ms[o1], ms[o2], t + 2, gmx, gmy);
+      if (up) {
+        gry = -gry;
+        gmy = -gmy;
+      }
+      R Fx = -rho * gmx, Fy = -rho * gmy;
+      if (SCHEME == STANDARD) {
+        Fx += grx * ((R)1 / (R)3);
+        Fy += gry * ((R)1 / (R)3);
+      }
+      R ux, uy;
+      velocity(out, rho, Fx, Fy, ux, uy);
+      collide<R, SCHEME>(out, rho, rho, ux, uy, Fx, Fy, grx, gry, p);
+      Global<double>* dst = fout + (long long)row_of(k - 3) * g.pitch + x;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(out[i], dst + (long long)i * g.plane);
+    }
+  };
+
+  // Row r lives in register set r % (D+1), as in `march`.
+  R s0[Q], s1[Q], s2[Q], s3[Q];
+  R h0 = (R)0, h1 = (R)0, h2 = (R)0, h3 = (R)0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) s0[i] = s1[i] = s2[i] = s3[i] = (R)0;
+  load_row(0, s0);
+  load_halo(0, h0);
+  if (D >= 2) {
+    load_row(1, s1);
+    load_halo(1, h1);
+  }
+  if (D >= 3) {
+    load_row(2, s2);
+    load_halo(2, h2);
+  }
+  for (int k = 0; k < K; k += D + 1) {
+    if (D == 1) {
+      stage(k, s1, s0, h1, h0);
+      stage(k + 1, s0, s1, h0, h1);
+    } else if (D == 2) {
+      stage(k, s2, s0, h2, h0);
+      stage(k + 1, s0, s1, h0, h1);
+      stage(k + 2, s1, s2, h1, h2);
+    } else {
+      stage(k, s3, s0, h3, h0);
+      stage(k + 1, s0, s1, h0, h1);
+      stage(k + 2, s1, s2, h1, h2);
+      stage(k + 3, s2, s3, h2, h3);
     }
   }
 }
@@ -800,35 +974,64 @@ int stencil4_blocks(const Geometry& g) {
 
 namespace {
 
-template <bool OBS>
-hipError_t launch4(int scheme, const Geometry& g, const Physics& ph, const void* fin, void* fout,
-                   double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
+hipError_t launch4_observe(int scheme, const Geometry& g, const Physics& ph, const void* f,
+                           double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
   const dim3 g1((g.nx + 255) / 256, g.ny);
-  const auto* in = (const Global<double>*)(const double*)fin;
-  auto* out = (Global<double>*)(double*)fout;
+  const auto* in = (const Global<double>*)(const double*)f;
   hipLaunchKernelGGL(density4, g1, dim3(256), 0, s, g, in, rho);
   hipLaunchKernelGGL(potential4, g1, dim3(256), 0, s, g, ph, (const double*)rho, mu);
   const dim3 g3((g.nx + S4X - 1) / S4X, (g.ny + S4Y - 1) / S4Y);
   if (scheme == STANDARD)
-    hipLaunchKernelGGL((collide4<STANDARD, OBS>), g3, dim3(S4X * S4Y), 0, s, g, ph, in, out,
+    hipLaunchKernelGGL(observe4_kernel<STANDARD>, g3, dim3(S4X * S4Y), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
-    hipLaunchKernelGGL((collide4<WELL_BALANCED, OBS>), g3, dim3(S4X * S4Y), 0, s, g, ph, in, out,
+    hipLaunchKernelGGL(observe4_kernel<WELL_BALANCED>, g3, dim3(S4X * S4Y), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_step4(int scheme, const Geometry& g, const Physics& ph, const void* fin,
-                        void* fout, double* rho, double* mu, hipStream_t s) {
-  const ObserveOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
-  return launch4<false>(scheme, g, ph, fin, fout, rho, mu, none, s);
+namespace {
+
+template <int SCHEME, int BW>
+hipError_t launch_march4_d(const Geometry& g, const Physics& ph, const Tiling& t,
+                           const Global<double>* in, Global<double>* out, hipStream_t s) {
+  const dim3 grid(t.blocks()), block(BW);
+  if (t.depth == 1)
+    hipLaunchKernelGGL((march4<SCHEME, BW, 1>), grid, block, 0, s, g, ph, t, in, out);
+  else if (t.depth == 2)
+    hipLaunchKernelGGL((march4<SCHEME, BW, 2>), grid, block, 0, s, g, ph, t, in, out);
+  else if (t.depth == 3)
+    hipLaunchKernelGGL((march4<SCHEME, BW, 3>), grid, block, 0, s, g, ph, t, in, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int SCHEME>
+hipError_t launch_march4(const Geometry& g, const Physics& ph, const Tiling& t,
+                         const Global<double>* in, Global<double>* out, hipStream_t s) {
+  if (t.block == 256) return launch_march4_d<SCHEME, 256>(g, ph, t, in, out, s);
+  if (t.block == 512) return launch_march4_d<SCHEME, 512>(g, ph, t, in, out, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool stencil4_block_supported(int block) { return block == 256 || block == 512; }
+
+hipError_t launch_step4(int scheme, const Geometry& g, const Physics& ph, const Tiling& t,
+                        const void* fin, void* fout, hipStream_t s) {
+  const auto* in = (const Global<double>*)(const double*)fin;
+  auto* out = (Global<double>*)(double*)fout;
+  return scheme == STANDARD ? launch_march4<STANDARD>(g, ph, t, in, out, s)
+                            : launch_march4<WELL_BALANCED>(g, ph, t, in, out, s);
 }
 
 hipError_t launch_observe4(int scheme, const Geometry& g, const Physics& ph, const void* f,
                            double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
-  return launch4<true>(scheme, g, ph, f, nullptr, rho, mu, o, s);
+  return launch4_observe(scheme, g, ph, f, rho, mu, o, s);
 }
 
 hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics& ph,

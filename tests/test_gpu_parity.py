@@ -103,8 +103,8 @@ STENCIL4 = [(64, 48, 1000), (37, 53, 200), (1, 7, 200), (7, 1, 200), (2, 2, 200)
 @pytest.mark.parametrize("nx,ny,steps", STENCIL4)
 def test_parity_force_stencil4(orc, lbm, nx, ny, steps, scheme):
     """Force-stencil variant (fourth-order gradients in the force and in
-    Eq. 26; three kernels per step) against the oracle's composition of its
-    own stencils, including lattices smaller than the 5 x 5 stencil."""
+    Eq. 26; one fused kernel per step) against the oracle's composition of
+    its own stencils, including lattices smaller than the 5 x 5 stencil."""
     prob = I.with_size(I.PAPER_DROPLET, nx, ny)
     ph = prob.physics
     print("parity case force_stencil=1", nx, ny, scheme, steps, flush=True)
@@ -115,7 +115,7 @@ def test_parity_force_stencil4(orc, lbm, nx, ny, steps, scheme):
     oo = orc.observe(scheme, p, fo)
     assert np.isfinite(fo).all() and ro.min() > 0
     s = lbm.Solver.for_problem(prob, force_stencil=1)
-    assert s.lib.lbm_kernels_per_step(s.ctx) == 3
+    assert s.lib.lbm_kernels_per_step(s.ctx) == 1
     s.init(rho0, scheme=scheme)
     s.step(steps, scheme)
     fg = to_oracle(s.get_populations())
@@ -131,7 +131,7 @@ def test_parity_force_stencil4(orc, lbm, nx, ny, steps, scheme):
 
 
 def test_force_stencil4_graph_replay_bit_exact(lbm):
-    """The three-kernel step captured in graphs gives the populations of the
+    """The variant's step captured in graphs gives the populations of the
     same steps launched one by one."""
     prob = I.with_size(I.PAPER_DROPLET, 96, 80)
     out = []
@@ -144,6 +144,38 @@ def test_force_stencil4_graph_replay_bit_exact(lbm):
         out.append(s.get_populations())
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+def test_force_stencil4_tilings_bit_identical(orc, lbm, scheme):
+    """Every tiling of the fused variant step (block width 256 or 512, two
+    strips with a ragged one, chunks of 4 to 45 rows marching up and down,
+    1 to 3 rows in flight) gives the same populations bit for bit, and the
+    oracle agrees; other block widths are refused."""
+    prob = I.with_size(I.PAPER_DROPLET, 600, 45)
+    ph = prob.physics
+    steps = 100
+    print("tilings force_stencil=1", scheme, flush=True)
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
+    fo = orc.step(scheme, p, orc.init(scheme, p, prob.rho()), steps)
+    ref = None
+    for tile in [(256, 16, 2), (256, 4, 1), (256, 7, 3), (512, 45, 3), (512, 9, 2), (512, 16, 1)]:
+        s = lbm.Solver.for_problem(prob, force_stencil=1)
+        s.set_tile(*tile)
+        assert s.get_tile() == tile
+        s.init(prob.rho(), scheme=scheme)
+        s.step(steps, scheme)
+        f = s.get_populations()
+        s.close()
+        if ref is None:
+            ref = f
+            assert np.abs(to_oracle(f) - fo).max() <= TOL
+        else:
+            assert np.array_equal(f, ref), tile
+    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    with pytest.raises(lbm.LbmError):
+        s.set_tile(128, 16, 2)
+    s.close()
 
 
 RAGGED = [(37, 53), (1, 7), (7, 1), (1, 1), (2, 2), (300, 5), (5, 300), (253, 3), (505, 9),
