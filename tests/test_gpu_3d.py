@@ -158,3 +158,35 @@ def test_tile_choice_errors_3d(lbm):
             s.set_tile(*args)
     assert s.get_tile()[0] == 256
     s.close()
+
+
+def test_full_grid_sampled_3d(orc, lbm):
+    """The 256^3 droplet of the benchmark in its launch configuration (the
+    default tiling: 32 x 8 tiles, chunks of 64 planes, odd chunks marching
+    towards -z): after 20 steps, one more GPU step against the oracle's step
+    on periodic crops around sampled windows, across tile, chunk and lattice
+    seams (a node's update depends on f within 3 nodes)."""
+    n, ph = 256, I.PHYS3
+    rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
+                             I.equilibrium_width(ph), 1e-3, seed=13)
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    s = solver(lbm, n, n, n, ph)
+    s.init(rho, scheme="well_balanced")
+    del rho
+    s.step(20, "well_balanced")
+    f = s.get_populations()
+    s.step(1, "well_balanced")
+    g = s.get_populations()
+    s.close()
+    rng = np.random.default_rng(5)
+    corners = [(0, 0, 0), (250, 250, 250), (62, 5, 30), (126, 100, 60), (190, 201, 222)]
+    corners += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(6)]
+    W, M = 14, 3
+    for (z0, y0, x0) in corners:
+        zs = np.arange(z0 - M, z0 + W - M) % n
+        ys = np.arange(y0 - M, y0 + W - M) % n
+        xs = np.arange(x0 - M, x0 + W - M) % n
+        crop = to_oracle(f[:, zs][:, :, ys][:, :, :, xs])
+        want = orc.step3("well_balanced", p, crop, 1)[M:-M, M:-M, M:-M]
+        got = to_oracle(g[:, zs[M:-M]][:, :, ys[M:-M]][:, :, :, xs[M:-M]])
+        assert np.abs(got - want).max() <= 1e-12, (z0, y0, x0)

@@ -343,3 +343,41 @@ def test_full_grid_sampled(orc, lbm):
         want = out[M:-M, M:-M]
         got = to_oracle(g[:, ys[M:-M]][:, :, xs[M:-M]])
         assert np.abs(got - want).max() <= 1e-12, (y0, x0)
+
+
+def test_full_grid_sampled_force_stencil4(orc, lbm):
+    """The force-stencil variant on a 4096^2 droplet in its benchmark launch
+    configuration (block 512, 128 rows, depth 3), with the finite-state
+    constants and the WB scheme (at density ratio 100 the standard scheme
+    diverges within a few steps, in the oracle too; the variant's gradients
+    enter the WB step through F, G and u.grad rho): after 20 steps, one
+    more GPU step against
+    the oracle's step on periodic crops around sampled windows, across
+    strip, chunk and lattice seams (a node's update depends on f within 4
+    nodes: pull 1, the Laplacian inside mu 1, the fourth-order gradient 2)."""
+    from paper_2012_11075_amd import tune
+    prob = I.DROPLET_4096_FINITE
+    ph = prob.physics
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
+    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    s.set_tile(*tune.bench_tile(prob.nx, prob.ny, "fp64"))
+    s.init(prob.rho(), scheme="well_balanced")
+    s.step(20, "well_balanced")
+    f = s.get_populations()
+    s.step(1, "well_balanced")
+    g = s.get_populations()
+    m = s.observe(fields=())
+    s.close()
+    assert not m["nonfinite"]
+    rng = np.random.default_rng(11)
+    corners = [(0, 0), (4090, 4090), (125, 509), (253, 1022), (2045, 3580)]
+    corners += [tuple(int(v) for v in rng.integers(0, 4096, 2)) for _ in range(8)]
+    W, M = 24, 4
+    for (y0, x0) in corners:
+        ys = np.arange(y0 - M, y0 + W - M) % 4096
+        xs = np.arange(x0 - M, x0 + W - M) % 4096
+        crop = to_oracle(f[:, ys][:, :, xs])
+        out = orc.step("well_balanced", p, crop, 1)
+        want = out[M:-M, M:-M]
+        got = to_oracle(g[:, ys[M:-M]][:, :, xs[M:-M]])
+        assert np.abs(got - want).max() <= 1e-12, (y0, x0)
