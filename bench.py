@@ -182,7 +182,7 @@ def serve_stream(n_requests=24, rate_hz=None, arena_gb=8.0, k=250):
         rate_hz = 0.7 * 60e9 / (mean_nodes * 50_000)
     reqs = I.request_stream(n_requests, rate_hz)
     ex = BatchExecutor(int(arena_gb * 1e9), max_slots=256, graph_steps=50,
-                       tiles=lambda nx, ny, prec: tune.batch_tile(nx, ny, prec))
+                       tiles=lambda nx, ny, prec: tune.serve_tile(nx, ny, prec))
     srv = Server(ex, k=k)
     t0 = time.perf_counter()
     out = srv.serve(reqs)

@@ -26,7 +26,8 @@
  * Memory and ownership
  *   - The caller owns every host array and the device workspace.  The library
  *     allocates no device memory; it owns only its host-side context structs
- *     (and HIP graph objects), which the destroy calls free.
+ *     and HIP graph objects (a batch also a second stream and two events),
+ *     which the destroy calls free.
  *   - Host field arrays are dense, row-major double[ny][nx] (element (x, y)
  *     at index y*nx + x).  Population arrays are double[9][ny][nx].
  *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
@@ -184,9 +185,12 @@ int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
 /* ------------------------------------------------------------------ batch */
 /* Many independent lattices of uneven size advanced together: each step is
  * one launch per group of slots that share precision, scheme, block width
- * and prefetch depth, with one block per tile of the group's slots, reading
- * a device-resident slot table (captured step sequences are re-captured
- * when the groups or their tile counts change).  Each slot is a complete single-instance
+ * and prefetch depth, and per lane (even and odd slot index), with one block
+ * per tile of those slots, reading a device-resident slot table.  Lane 0
+ * runs on the batch's stream, lane 1 on a second stream of the batch that
+ * forks from it and joins it again within each lbm_batch_run, so one lane's
+ * next step overlaps the end of the other's.  Captured step sequences are
+ * re-captured when the groups or their tile counts change.  Each slot is a complete single-instance
  * state (same kernels, same arithmetic), so a lattice gives bit-identical
  * populations alone and in a batch.  The caller owns the device arena; the
  * library places slot workspaces and the tables inside it. */

@@ -668,6 +668,11 @@ namespace {
 constexpr int kBatchBlocks[3] = {64, 128, 256};
 constexpr int kGroups = 2 * 2 * 3 * 3;  // storage x scheme x block x depth
 static_assert(kGroups <= 64, "group masks are 64-bit");
+// Each group's slots are split into two lanes (even and odd slot index), each
+// with its own table, launched on its own stream: the lanes hold disjoint
+// lattices, so one lane's next step fills the compute units that the other
+// lane's step leaves idle at its end.
+constexpr int kLanes = 2;
 
 int block_index(int block) {
   for (int i = 0; i < 3; ++i)
@@ -705,18 +710,22 @@ struct lbm_batch {
   std::vector<Slot> slots;
   std::vector<Range> free_ranges;  // sorted by offset, coalesced
 
-  std::vector<std::vector<char>> host_tab;  // per group
+  std::vector<std::vector<char>> host_tab;  // per group and lane
   uint64_t group_mask = 0;                  // groups that have ever held a slot
-  uint64_t active_mask = 0;                 // groups with an active slot (launched)
+  uint64_t active_mask[kLanes] = {};        // per lane: groups with an active slot (launched)
   bool dirty = true;
   int graph_steps = 0;
-  hipGraphExec_t graph = nullptr;
-  uint64_t graph_mask = 0;
-  int tiles_of[kGroups] = {};     // work items (tiles) of each group, as uploaded
-  int graph_tiles[kGroups] = {};  // the same when the graph was captured
+  hipGraphExec_t graph[kLanes] = {};
+  uint64_t graph_mask[kLanes] = {};
+  int tiles_of[kLanes][kGroups] = {};     // work items (tiles) of each table, as uploaded
+  int graph_tiles[kLanes][kGroups] = {};  // the same when a lane's graph was captured
+  hipStream_t side = nullptr;             // the second lane's stream
+  hipEvent_t fork = nullptr, join = nullptr;
   std::string err;
 
-  lbmk::BatchTable* dev_tab(int g) const { return (lbmk::BatchTable*)(arena + g * tab_stride); }
+  lbmk::BatchTable* dev_tab(int g, int lane) const {
+    return (lbmk::BatchTable*)(arena + (size_t)(g * kLanes + lane) * tab_stride);
+  }
   double* partials() const { return (double*)(arena + part_off); }
 };
 
@@ -787,75 +796,87 @@ bool alloc_range(lbm_batch* b, size_t size, Range* out) {
 // Rebuild the group tables from the active slots and upload them.
 lbm_status upload_tables(lbm_batch* b) {
   size_t part = 0;
-  uint64_t active = 0;
+  uint64_t active[kLanes] = {};
   for (int g = 0; g < kGroups; ++g) {
     if (!(b->group_mask >> g & 1)) continue;
-    std::vector<char>& h = b->host_tab[g];
-    std::fill(h.begin(), h.end(), 0);
-    auto* tab = (lbmk::BatchTable*)h.data();
-    int n = 0, tiles = 0;
-    for (size_t s = 0; s < b->slots.size(); ++s) {
-      lbm_batch::Slot& sl = b->slots[s];
-      if (sl.status != LBM_SLOT_ACTIVE || group_of(sl.ctx, sl.scheme) != g) continue;
-      lbm_ctx* c = sl.ctx;
-      lbmk::BatchSlot& d = tab->slot[n++];
-      d.g = c->L.g;
-      d.ph = make_physics(c->prm, sl.scheme);
-      d.tl = c->tl;
-      d.buf[0] = c->buf(0);
-      d.buf[1] = c->buf(1);
-      d.cur = c->cur;
-      d.tile0 = tiles;
-      d.partials = b->partials() + 4 * (part + tiles);
-      sl.part_index = part + tiles;
-      sl.tiles = c->tl.blocks();
-      tiles += sl.tiles;
+    for (int lane = 0; lane < kLanes; ++lane) {
+      std::vector<char>& h = b->host_tab[g * kLanes + lane];
+      std::fill(h.begin(), h.end(), 0);
+      auto* tab = (lbmk::BatchTable*)h.data();
+      int n = 0, tiles = 0;
+      for (size_t s = lane; s < b->slots.size(); s += kLanes) {
+        lbm_batch::Slot& sl = b->slots[s];
+        if (sl.status != LBM_SLOT_ACTIVE || group_of(sl.ctx, sl.scheme) != g) continue;
+        lbm_ctx* c = sl.ctx;
+        lbmk::BatchSlot& d = tab->slot[n++];
+        d.g = c->L.g;
+        d.ph = make_physics(c->prm, sl.scheme);
+        d.tl = c->tl;
+        d.buf[0] = c->buf(0);
+        d.buf[1] = c->buf(1);
+        d.cur = c->cur;
+        d.tile0 = tiles;
+        d.partials = b->partials() + 4 * (part + tiles);
+        sl.part_index = part + tiles;
+        sl.tiles = c->tl.blocks();
+        tiles += sl.tiles;
+      }
+      tab->nslots = n;
+      tab->total_tiles = tiles;
+      if (n > 0) active[lane] |= 1ull << g;
+      b->tiles_of[lane][g] = tiles;
+      part += tiles;
+      if (part > b->part_cap)
+        return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
+      const size_t used =
+          sizeof(lbmk::BatchTable) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot);
+      BHIP(b, hipMemcpyAsync(b->dev_tab(g, lane), h.data(), used, hipMemcpyHostToDevice,
+                             b->stream));
     }
-    tab->nslots = n;
-    tab->total_tiles = tiles;
-    if (n > 0) active |= 1ull << g;
-    b->tiles_of[g] = tiles;
-    part += tiles;
-    if (part > b->part_cap) return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
-    const size_t used = sizeof(lbmk::BatchTable) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot);
-    BHIP(b, hipMemcpyAsync(b->dev_tab(g), h.data(), used, hipMemcpyHostToDevice, b->stream));
   }
   // the host copies must stay intact until the uploads have been consumed
   BHIP(b, hipStreamSynchronize(b->stream));
-  b->active_mask = active;
+  std::copy(active, active + kLanes, b->active_mask);
   b->dirty = false;
   return LBM_OK;
 }
 
-lbm_status batch_launches(lbm_batch* b, int steps, hipStream_t s) {
+// `steps` steps of one lane's groups on stream s.
+lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
     for (int g = 0; g < kGroups; ++g) {
-      if (!(b->active_mask >> g & 1)) continue;
+      if (!(b->active_mask[lane] >> g & 1)) continue;
       int storage, scheme, block, depth;
       group_decode(g, &storage, &scheme, &block, &depth);
-      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g),
-                                 b->tiles_of[g], j & 1, s));
+      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g, lane),
+                                 b->tiles_of[lane][g], j & 1, s));
     }
   }
   return LBM_OK;
 }
 
 void drop_batch_graph(lbm_batch* b) {
-  if (b->graph) {
-    (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  for (auto& g : b->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
-lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
-  // a captured launch holds its group's grid (one block per tile), so the
-  // graph is re-captured when the launched groups or their tile counts change
-  if (b->graph && b->graph_mask == b->active_mask &&
-      std::equal(b->tiles_of, b->tiles_of + kGroups, b->graph_tiles)) {
-    *out = b->graph;
+lbm_status batch_graph(lbm_batch* b, int lane, hipGraphExec_t* out) {
+  // a captured launch holds its group's grid (one block per tile), so a
+  // lane's graph is re-captured when its launched groups or their tile
+  // counts change
+  hipGraphExec_t& ge = b->graph[lane];
+  if (ge && b->graph_mask[lane] == b->active_mask[lane] &&
+      std::equal(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane])) {
+    *out = ge;
     return LBM_OK;
   }
-  drop_batch_graph(b);
+  if (ge) {
+    (void)hipGraphExecDestroy(ge);
+    ge = nullptr;
+  }
   hipStream_t cs;
   BHIP(b, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
@@ -863,7 +884,7 @@ lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
     (void)hipStreamDestroy(cs);
     return bfail(b, LBM_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  lbm_status st = batch_launches(b, b->graph_steps, cs);
+  lbm_status st = batch_launches(b, lane, b->graph_steps, cs);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);
@@ -873,15 +894,15 @@ lbm_status batch_graph(lbm_batch* b, hipGraphExec_t* out) {
   }
   if (e != hipSuccess)
     return bfail(b, LBM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    b->graph = nullptr;
+    ge = nullptr;
     return bfail(b, LBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
-  b->graph_mask = b->active_mask;
-  std::copy(b->tiles_of, b->tiles_of + kGroups, b->graph_tiles);
-  *out = b->graph;
+  b->graph_mask[lane] = b->active_mask[lane];
+  std::copy(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane]);
+  *out = ge;
   return LBM_OK;
 }
 
@@ -902,7 +923,8 @@ size_t lbm_batch_slot_bytes(const lbm_params* p) {
 size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  return kGroups * stride + align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+  return kGroups * kLanes * stride +
+         align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
 }
 
 lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
@@ -914,18 +936,32 @@ lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* 
   if (max_slots < 1 || max_slots > 65536) return bfail(nullptr, LBM_EINVAL, "max_slots out of range");
   const size_t over = lbm_batch_overhead_bytes(bytes, max_slots);
   if (bytes <= over) return bfail(nullptr, LBM_ENOSPACE, "arena smaller than the batch tables");
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (join) (void)hipEventDestroy(join);
+    if (fork) (void)hipEventDestroy(fork);
+    if (side) (void)hipStreamDestroy(side);
+    return bfail(nullptr, LBM_EHIP, std::string("batch stream: ") + hipGetErrorString(e));
+  }
   lbm_batch* b = new lbm_batch();
   b->arena = (char*)arena;
   b->bytes = bytes;
   b->stream = (hipStream_t)stream;
+  b->side = side;
+  b->fork = fork;
+  b->join = join;
   b->max_slots = max_slots;
   b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  b->part_off = kGroups * b->tab_stride;
+  b->part_off = kGroups * kLanes * b->tab_stride;
   b->part_cap = part_capacity(bytes);
   b->heap_off = over;
   b->slots.resize(max_slots);
   b->free_ranges.push_back(Range{b->heap_off, bytes - b->heap_off});
-  b->host_tab.assign(kGroups, std::vector<char>(lbmk::batch_table_bytes(max_slots), 0));
+  b->host_tab.assign(kGroups * kLanes, std::vector<char>(lbmk::batch_table_bytes(max_slots), 0));
   *out = b;
   return LBM_OK;
 }
@@ -1007,18 +1043,28 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t k) {
     lbm_status st = upload_tables(b);
     if (st != LBM_OK) return st;
   }
-  int left = k;
-  if (b->graph_steps >= 2) {
-    while (left >= b->graph_steps) {
-      hipGraphExec_t ge;
-      lbm_status st = batch_graph(b, &ge);
-      if (st != LBM_OK) return st;
-      BHIP(b, hipGraphLaunch(ge, b->stream));
-      left -= b->graph_steps;
+  // lane 0 on the caller's stream, lane 1 on the side stream after the work
+  // already queued on the caller's; the caller's stream then waits for both
+  BHIP(b, hipEventRecord(b->fork, b->stream));
+  BHIP(b, hipStreamWaitEvent(b->side, b->fork, 0));
+  for (int lane = 0; lane < kLanes; ++lane) {
+    if (!b->active_mask[lane]) continue;
+    hipStream_t ls = lane == 0 ? b->stream : b->side;
+    int left = k;
+    if (b->graph_steps >= 2) {
+      while (left >= b->graph_steps) {
+        hipGraphExec_t ge;
+        lbm_status st = batch_graph(b, lane, &ge);
+        if (st != LBM_OK) return st;
+        BHIP(b, hipGraphLaunch(ge, ls));
+        left -= b->graph_steps;
+      }
     }
+    lbm_status st = batch_launches(b, lane, left, ls);
+    if (st != LBM_OK) return st;
   }
-  lbm_status st = batch_launches(b, left, b->stream);
-  if (st != LBM_OK) return st;
+  BHIP(b, hipEventRecord(b->join, b->side));
+  BHIP(b, hipStreamWaitEvent(b->stream, b->join, 0));
   for (auto& s : b->slots) {
     if (s.status != LBM_SLOT_ACTIVE) continue;
     s.ctx->step += k;
@@ -1039,13 +1085,14 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (const auto& s : b->slots)
     if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
   if (total == 0) return LBM_OK;
-  for (int g = 0; g < kGroups; ++g) {
-    if (!(b->active_mask >> g & 1)) continue;
-    int storage, scheme, block, depth;
-    group_decode(g, &storage, &scheme, &block, &depth);
-    BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g),
-                               b->tiles_of[g], 0, b->stream));
-  }
+  for (int lane = 0; lane < kLanes; ++lane)
+    for (int g = 0; g < kGroups; ++g) {
+      if (!(b->active_mask[lane] >> g & 1)) continue;
+      int storage, scheme, block, depth;
+      group_decode(g, &storage, &scheme, &block, &depth);
+      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g, lane),
+                                 b->tiles_of[lane][g], 0, b->stream));
+    }
   std::vector<double> part(total * 4);
   BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),
                          hipMemcpyDeviceToHost, b->stream));
@@ -1138,9 +1185,13 @@ lbm_status lbm_batch_release(lbm_batch* b, int32_t slot) {
 lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_OK;
   (void)hipStreamSynchronize(b->stream);
+  (void)hipStreamSynchronize(b->side);
   drop_batch_graph(b);
   for (auto& s : b->slots)
     if (s.ctx) lbm_destroy(s.ctx);
+  (void)hipEventDestroy(b->join);
+  (void)hipEventDestroy(b->fork);
+  (void)hipStreamDestroy(b->side);
   delete b;
   return LBM_OK;
 }
