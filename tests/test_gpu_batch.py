@@ -143,3 +143,28 @@ def test_admission_retirement_and_reuse(lbm):
     b.run(33)
     assert np.array_equal(b.get_populations(s2), alone(lbm, flat, "fp64", "well_balanced", 33))
     b.close()
+
+
+def test_lanes_with_graphs_release_and_admit(lbm):
+    """One launch group with slots in both lanes (even and odd slot index),
+    captured graphs of 8 steps and odd step counts: releasing a slot of one
+    lane and admitting another (that lane's table and graph change, the
+    other's do not) leaves every lattice bit-identical to its run alone."""
+    probs = [I.with_size(I.PAPER_DROPLET, n, n + 3) for n in (40, 57, 33, 64, 29, 48)]
+    extra = I.with_size(I.PAPER_DROPLET, 51, 38)
+    prec, scheme = "fp32s", "well_balanced"
+    need = sum(lbm.Batch.slot_bytes(params_of(lbm, p, prec)) for p in probs + [extra])
+    b = lbm.Batch(need + lbm.Batch.overhead_bytes(need * 2, 16) + (1 << 20), max_slots=16)
+    b.set_graph_steps(8)
+    slots = [b.admit(params_of(lbm, p, prec), p.rho(), scheme) for p in probs]
+    b.run(21)
+    b.release(slots[3])
+    s_new = b.admit(params_of(lbm, extra, prec), extra.rho(), scheme)
+    b.run(13)
+    for k, (p, sl) in enumerate(zip(probs, slots)):
+        if k == 3:
+            continue
+        print("lane test slot", sl, p.nx, p.ny, flush=True)
+        assert np.array_equal(b.get_populations(sl), alone(lbm, p, prec, scheme, 34)), p.name
+    assert np.array_equal(b.get_populations(s_new), alone(lbm, extra, prec, scheme, 13))
+    b.close()
