@@ -263,14 +263,14 @@ def finite_state(steps, warmup):
 STENCIL4_BYTES = 144   # FP64 bytes per node of the variant step: 9 populations read and written
 
 
-def time_stencil4(prob, steps, warmup, scheme="standard", tile=None):
-    """The force-stencil variant (fourth-order gradients in the force, FP64):
-    one fused pass per step, 9 populations read and written = 144
-    algorithmic bytes per node.  `tile` (block, rows, depth) overrides the
-    default."""
+def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="fp64"):
+    """The force-stencil variant (fourth-order gradients in the force): one
+    fused pass per step, 9 populations read and written = 144 (FP64) or 72
+    (FP32-shifted) algorithmic bytes per node.  `tile` (block, rows, depth)
+    overrides the default."""
     import torch
     from paper_2012_11075_amd import lbm
-    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    s = lbm.Solver.for_problem(prob, force_stencil=1, precision=precision)
     if tile:
         s.set_tile(*tile)
     s.init(prob.rho(), scheme=scheme)
@@ -291,14 +291,15 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None):
     del s
     torch.cuda.empty_cache()
     nodes = prob.nx * prob.ny
-    gbs = STENCIL4_BYTES * nodes / (ms / 1e3) / 1e9
+    bpu = STENCIL4_BYTES // 2 if precision == "fp32s" else STENCIL4_BYTES
+    gbs = bpu * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
-            "scheme": scheme, "kernels_per_step": kps, "tile": list(used),
-            "bytes_per_update": STENCIL4_BYTES,
+            "scheme": scheme, "precision": precision, "kernels_per_step": kps, "tile": list(used),
+            "bytes_per_update": bpu,
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "workload": "%s, %s scheme, fourth-order force stencil, FP64, %d steps"
-                        % (prob.name, scheme, steps)}
+            "workload": "%s, %s scheme, fourth-order force stencil, %s, %d steps"
+                        % (prob.name, scheme, precision.upper(), steps)}
 
 
 D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
@@ -465,7 +466,10 @@ def main():
         # on the finite-state droplet: at density ratio 100 the standard
         # scheme diverges within a few steps, so the WB step is timed
         out["force_stencil4"] = time_stencil4(I.DROPLET_4096_FINITE, 200, 5, "well_balanced",
-                                              tile=tune.bench_tile(prob.nx, prob.ny, "fp64"))
+                                              tile=tune.stencil4_tile(prob.nx, prob.ny, "fp64"))
+        out["force_stencil4"]["fp32_shifted"] = time_stencil4(
+            I.DROPLET_4096_FINITE, 200, 5, "well_balanced",
+            tile=tune.stencil4_tile(prob.nx, prob.ny, "fp32s"), precision="fp32s")
         progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
     if not args.no_d3:
         out["d3q19"] = time_d3q19(100, 5)

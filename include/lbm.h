@@ -85,8 +85,8 @@ typedef struct {
                           * isotropic central scheme of Sec. II; 1 the
                           * fourth-order form grad - (1/6) grad(lap), the
                           * higher-order discretisation discussed after
-                          * Eq. (23) (FP64 only, ny <= 65535, not in batches,
-                          * block widths 256 and 512) */
+                          * Eq. (23) (FP64 or FP32-shifted, ny <= 65535, not
+                          * in batches, block widths 256 and 512) */
   int32_t nz;            /* lattice depth: 0 or 1 for the 2-D D2Q9 lattice;
                           * > 1 for the 3-D D3Q19 lattice of the same method
                           * (Eqs. 24 and 26 hold for general dimension; here

@@ -58,8 +58,6 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32_SHIFTED)
     return *why = "unknown precision", false;
   if (p->force_stencil != 0 && p->force_stencil != 1) return *why = "force_stencil must be 0 or 1", false;
-  if (p->force_stencil == 1 && p->precision != LBM_FP64)
-    return *why = "the fourth-order force stencil is FP64 only", false;
   if (p->force_stencil == 1 && p->ny > 65535)
     return *why = "the fourth-order force stencil needs ny <= 65535", false;
   if (p->nz > 1) {
@@ -253,8 +251,8 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
       HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
                                    c->buf(1 - c->cur), s));
     } else if (c->prm.force_stencil == 1) {
-      HIPCHK(c, lbmk::launch_step4(scheme, c->L.g, ph, c->tl, c->buf(c->cur), c->buf(1 - c->cur),
-                                   s));
+      HIPCHK(c, lbmk::launch_step4(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
+                                   c->buf(1 - c->cur), s));
     } else {
       HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
                                   c->buf(1 - c->cur), s));
@@ -469,8 +467,8 @@ lbm_status observe_impl(lbm_ctx* c, double* rho, double* ux, double* uy, double*
     const lbmk::Physics ph = make_physics(c->prm, c->scheme);
     if (c->prm.force_stencil == 1) {
       // the variant always computes rho and mu into staging fields 0 and 3
-      HIPCHK(c, lbmk::launch_observe4(c->scheme, c->L.g, ph, c->state(), st, st_mu, o,
-                                      c->stream));
+      HIPCHK(c, lbmk::launch_observe4(c->storage(), c->scheme, c->L.g, ph, c->state(), st, st_mu,
+                                      o, c->stream));
       nb = lbmk::stencil4_blocks(c->L.g);
     } else {
       HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, ph, c->tl, c->state(), o,

@@ -104,16 +104,17 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
                         const BatchTable* tab, int tiles, int parity, hipStream_t s);
 
-// Force-stencil variant (FP64): one step as one fused launch on the tiling
-// `t` (block width 256 or 512, depth 1..3), and the observe pass of that
-// variant in three launches (density into `rho`, chemical potential into
-// `mu`, velocity into o.ux / o.uy; partials: one per block of
-// stencil4_blocks(g)).  `rho` and `mu` are dense nx*ny doubles.
+// Force-stencil variant (FP64 or FP32-shifted storage): one step as one fused
+// launch on the tiling `t` (block width 256 or 512, depth 1..3), and the
+// observe pass of that variant in three launches (density into `rho`,
+// chemical potential into `mu`, velocity into o.ux / o.uy; partials: one per
+// block of stencil4_blocks(g)).  `rho` and `mu` are dense nx*ny doubles.
 bool stencil4_block_supported(int block);
-hipError_t launch_step4(int scheme, const Geometry& g, const Physics& ph, const Tiling& t,
-                        const void* fin, void* fout, hipStream_t s);
-hipError_t launch_observe4(int scheme, const Geometry& g, const Physics& ph, const void* f,
-                           double* rho, double* mu, const ObserveOut& o, hipStream_t s);
+hipError_t launch_step4(int storage, int scheme, const Geometry& g, const Physics& ph,
+                        const Tiling& t, const void* fin, void* fout, hipStream_t s);
+hipError_t launch_observe4(int storage, int scheme, const Geometry& g, const Physics& ph,
+                           const void* f, double* rho, double* mu, const ObserveOut& o,
+                           hipStream_t s);
 int stencil4_blocks(const Geometry& g);
 
 // Block widths the kernels are instantiated for.

@@ -454,33 +454,41 @@ __device__ __forceinline__ long long src_offset(const Geometry& g, int q, int x,
 //   dy = +-2: -1/108, -1/432
 // and the y-derivative's are their transpose.
 
+// The observe pass computes in the storage type T, as the step does (FP32
+// storage: rho = rho_ref + sum_i g_i, then every stencil in FP32); fields
+// are written as double.
+
 // Pass 1: rho = sum_i f_i of every node (pulled populations, Eq. 4).
+template <typename T>
 __global__ void __launch_bounds__(256)
-    density4(Geometry g, const Global<double>* __restrict__ fin, double* __restrict__ rho) {
+    density4(Geometry g, Physics phys, const Global<T>* __restrict__ fin,
+             double* __restrict__ rho) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
-  double f[Q];
+  T f[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src_offset(g, i, x, y)];
-  rho[(long long)y * g.nx + x] = sum9(f);
+  rho[(long long)y * g.nx + x] = (double)((T)phys.rho_ref + sum9(f));
 }
 
 // Pass 2: mu = mu0(rho) - kappa lap(rho), 9-point isotropic Laplacian.
+template <typename T>
 __global__ void __launch_bounds__(256)
     potential4(Geometry g, Physics phys, const double* __restrict__ rho, double* __restrict__ mu) {
+  using R = T;
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
   if (x >= g.nx) return;
-  const PhysR<double> p = to_r<double>(phys);
+  const PhysR<R> p = to_r<R>(phys);
   const int xw = x == 0 ? g.nx - 1 : x - 1, xe = x + 1 == g.nx ? 0 : x + 1;
   const int ys = y == 0 ? g.ny - 1 : y - 1, yn = y + 1 == g.ny ? 0 : y + 1;
   const double* r0 = rho + (long long)y * g.nx;
   const double* rs = rho + (long long)ys * g.nx;
   const double* rn = rho + (long long)yn * g.nx;
-  const double c = r0[x];
-  const double ax = (r0[xe] + r0[xw]) + (rs[x] + rn[x]);
-  const double dg = (rs[xe] + rs[xw]) + (rn[xe] + rn[xw]);
-  const double lap = (4.0 * ax + dg - 20.0 * c) * (1.0 / 6.0);
-  mu[(long long)y * g.nx + x] = mu0(c, p) - p.kappa * lap;
+  const R c = (R)r0[x];
+  const R ax = ((R)r0[xe] + (R)r0[xw]) + ((R)rs[x] + (R)rn[x]);
+  const R dg = ((R)rs[xe] + (R)rs[xw]) + ((R)rn[xe] + (R)rn[xw]);
+  const R lap = ((R)4 * ax + dg - (R)20 * c) * ((R)1 / (R)6);
+  mu[(long long)y * g.nx + x] = (double)(mu0(c, p) - p.kappa * lap);
 }
 
 constexpr int S4X = 64, S4Y = 4;  // collide-stream tile (threads)
@@ -488,37 +496,33 @@ constexpr int S4X = 64, S4Y = 4;  // collide-stream tile (threads)
 // Fourth-order gradient at column j from the five rows y-2 .. y+2 (m2, m1,
 // r0, p1, p2).  Swapping the rows (m2 <-> p2, m1 <-> p1) negates gy exactly
 // and leaves gx unchanged.
-__device__ __forceinline__ void grad4r(const double* m2, const double* m1, const double* r0,
-                                       const double* p1, const double* p2, int j, double& gx,
-                                       double& gy) {
-  auto dx1 = [&](const double* r) { return r[j + 1] - r[j - 1]; };
-  auto dx2 = [&](const double* r) { return r[j + 2] - r[j - 2]; };
+template <typename R>
+__device__ __forceinline__ void grad4r(const R* m2, const R* m1, const R* r0, const R* p1,
+                                       const R* p2, int j, R& gx, R& gy) {
+  auto dx1 = [&](const R* r) { return r[j + 1] - r[j - 1]; };
+  auto dx2 = [&](const R* r) { return r[j + 2] - r[j - 2]; };
   auto dy1 = [&](int c) { return p1[c] - m1[c]; };
   auto dy2 = [&](int c) { return p2[c] - m2[c]; };
-  gx = 0.5 * dx1(r0) - (1.0 / 24.0) * dx2(r0) + (5.0 / 54.0) * (dx1(p1) + dx1(m1)) -
-       (1.0 / 54.0) * (dx2(p1) + dx2(m1)) - (1.0 / 108.0) * (dx1(p2) + dx1(m2)) -
-       (1.0 / 432.0) * (dx2(p2) + dx2(m2));
-  gy = 0.5 * dy1(j) - (1.0 / 24.0) * dy2(j) + (5.0 / 54.0) * (dy1(j + 1) + dy1(j - 1)) -
-       (1.0 / 54.0) * (dy2(j + 1) + dy2(j - 1)) - (1.0 / 108.0) * (dy1(j + 2) + dy1(j - 2)) -
-       (1.0 / 432.0) * (dy2(j + 2) + dy2(j - 2));
-}
-
-// The same on a (S4Y+4) x (S4X+4) LDS tile at tile point (i, j).
-__device__ __forceinline__ void grad4(const double (&a)[S4Y + 4][S4X + 4], int i, int j,
-                                      double& gx, double& gy) {
-  grad4r(a[i - 2], a[i - 1], a[i], a[i + 1], a[i + 2], j, gx, gy);
+  const R a1 = (R)0.5, a2 = (R)1 / (R)24, b1 = (R)5 / (R)54, b2 = (R)1 / (R)54,
+          c1 = (R)1 / (R)108, c2 = (R)1 / (R)432;
+  gx = a1 * dx1(r0) - a2 * dx2(r0) + b1 * (dx1(p1) + dx1(m1)) - b2 * (dx2(p1) + dx2(m1)) -
+       c1 * (dx1(p2) + dx1(m2)) - c2 * (dx2(p2) + dx2(m2));
+  gy = a1 * dy1(j) - a2 * dy2(j) + b1 * (dy1(j + 1) + dy1(j - 1)) -
+       b2 * (dy2(j + 1) + dy2(j - 1)) - c1 * (dy1(j + 2) + dy1(j - 2)) -
+       c2 * (dy2(j + 2) + dy2(j - 2));
 }
 
 // Pass 3 of the observe pass: force with the fourth-order gradients and
 // velocity of every node; writes the velocity fields and per-block partials
 // (max|u|, mass, kinetic energy, non-finite).
-template <int SCHEME>
+template <typename T, int SCHEME>
 __global__ void __launch_bounds__(S4X * S4Y)
-    observe4_kernel(Geometry g, const Global<double>* __restrict__ fin,
+    observe4_kernel(Geometry g, const Global<T>* __restrict__ fin,
                     const double* __restrict__ rho, const double* __restrict__ mu,
                     ObserveOut obs) {
-  __shared__ double rt[S4Y + 4][S4X + 4];
-  __shared__ double mt[S4Y + 4][S4X + 4];
+  using R = T;
+  __shared__ R rt[S4Y + 4][S4X + 4];
+  __shared__ R mt[S4Y + 4][S4X + 4];
   const int tx = threadIdx.x % S4X, ty = threadIdx.x / S4X;
   const int x0 = blockIdx.x * S4X, y0 = blockIdx.y * S4Y;
   for (int e = threadIdx.x; e < (S4Y + 4) * (S4X + 4); e += S4X * S4Y) {
@@ -527,27 +531,29 @@ __global__ void __launch_bounds__(S4X * S4Y)
     yy = yy < 0 ? yy + g.ny : yy;
     xx = xx < 0 ? xx + g.nx : xx;
     const long long o = (long long)yy * g.nx + xx;
-    rt[i][j] = rho[o];
-    mt[i][j] = mu[o];
+    rt[i][j] = (R)rho[o];
+    mt[i][j] = (R)mu[o];
   }
   __syncthreads();
   const int x = x0 + tx, y = y0 + ty;
   double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
   if (x < g.nx && y < g.ny) {
-    double f[Q];
+    R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src_offset(g, i, x, y)];
-    const double r = rt[ty + 2][tx + 2];
-    double grx, gry, gmx, gmy;
-    grad4(rt, ty + 2, tx + 2, grx, gry);
-    grad4(mt, ty + 2, tx + 2, gmx, gmy);
-    double Fx = -r * gmx, Fy = -r * gmy;
+    const R rr = rt[ty + 2][tx + 2];
+    R grx, gry, gmx, gmy;
+    const int i = ty + 2, j = tx + 2;
+    grad4r<R>(rt[i - 2], rt[i - 1], rt[i], rt[i + 1], rt[i + 2], j, grx, gry);
+    grad4r<R>(mt[i - 2], mt[i - 1], mt[i], mt[i + 1], mt[i + 2], j, gmx, gmy);
+    R Fx = -rr * gmx, Fy = -rr * gmy;
     if (SCHEME == STANDARD) {
-      Fx += grx * (1.0 / 3.0);
-      Fy += gry * (1.0 / 3.0);
+      Fx += grx * ((R)1 / (R)3);
+      Fy += gry * ((R)1 / (R)3);
     }
-    double ux, uy;
-    velocity(f, r, Fx, Fy, ux, uy);
+    R uxr, uyr;
+    velocity(f, rr, Fx, Fy, uxr, uyr);
+    const double r = (double)rr, ux = (double)uxr, uy = (double)uyr;
     const long long o = (long long)y * g.nx + x;
     if (obs.ux) obs.ux[o] = ux;
     if (obs.uy) obs.uy[o] = uy;
@@ -599,11 +605,11 @@ __global__ void __launch_bounds__(S4X * S4Y)
 // lanes of wave 0 load one population each), and a row is updated 3 rows
 // after it is loaded (rows k-3 .. k-1 wait in LDS).  Stencil sums pair the
 // rows above and below, so the march direction changes no bit of the result.
-template <int SCHEME, int BW, int D>
+template <typename T, int SCHEME, int BW, int D>
 __global__ void __launch_bounds__(BW)
-    march4(Geometry g, Physics phys, Tiling tl, const Global<double>* __restrict__ fin,
-           Global<double>* __restrict__ fout) {
-  using R = double;
+    march4(Geometry g, Physics phys, Tiling tl, const Global<T>* __restrict__ fin,
+           Global<T>* __restrict__ fout) {
+  using R = T;
   __shared__ R rs[7][BW + 6];  // column j: lattice column x0 - 3 + j
   __shared__ R ms[5][BW + 4];  // column m: lattice column x0 - 2 + m
   __shared__ R fl[3][Q][BW];   // populations of rows k-3 .. k-1, each thread its own column
@@ -677,13 +683,13 @@ __global__ void __launch_bounds__(BW)
     load_row(k + D, nxt);  // rows past the chunk are valid (periodic) and unused
     load_halo(k + D, hnxt);
     const int sk = k % 7;
-    rs[sk][t + 3] = sum9(cur);
+    rs[sk][t + 3] = p.rho_ref + sum9(cur);
     if (t < 64) {
       const int base = (hl ? hcol : 0) * Q;
       R v[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) v[i] = __shfl(hcur, base + i);
-      if (hl && hq == 0) rs[sk][hslot] = sum9(v);
+      if (hl && hq == 0) rs[sk][hslot] = p.rho_ref + sum9(v);
     }
     const int fk = k % 3;
     R out[Q];
@@ -714,8 +720,8 @@ __global__ void __launch_bounds__(BW)
                 o2 = (k - 1) % 5;
       const R rho = rs[q0][t + 3];
       R grx, gry, gmx, gmy;
-      grad4r(rs[q2], rs[q1], rs[q0], rs[p1], rs[p2], t + 3, grx, gry);
-      grad4r(ms[n2], ms[n1], ms[n0], ms[o1], ms[o2], t + 2, gmx, gmy);
+      grad4r<R>(rs[q2], rs[q1], rs[q0], rs[p1], rs[p2], t + 3, grx, gry);
+      grad4r<R>(ms[n2], ms[n1], ms[n0], ms[o1], ms[o2], t + 2, gmx, gmy);
       if (up) {
         gry = -gry;
         gmy = -gmy;
@@ -727,8 +733,9 @@ __global__ void __launch_bounds__(BW)
       }
       R ux, uy;
       velocity(out, rho, Fx, Fy, ux, uy);
-      collide<R, SCHEME>(out, rho, rho, ux, uy, Fx, Fy, grx, gry, p);
-      Global<double>* dst = fout + (long long)row_of(k - 3) * g.pitch + x;
+      const R drho = sum9(out);
+      collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
+      Global<T>* dst = fout + (long long)row_of(k - 3) * g.pitch + x;
 #pragma unroll
       for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(out[i], dst + (long long)i * g.plane);
     }
@@ -974,18 +981,19 @@ int stencil4_blocks(const Geometry& g) {
 
 namespace {
 
+template <typename T>
 hipError_t launch4_observe(int scheme, const Geometry& g, const Physics& ph, const void* f,
                            double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
   const dim3 g1((g.nx + 255) / 256, g.ny);
-  const auto* in = (const Global<double>*)(const double*)f;
-  hipLaunchKernelGGL(density4, g1, dim3(256), 0, s, g, in, rho);
-  hipLaunchKernelGGL(potential4, g1, dim3(256), 0, s, g, ph, (const double*)rho, mu);
+  const auto* in = (const Global<T>*)(const T*)f;
+  hipLaunchKernelGGL(density4<T>, g1, dim3(256), 0, s, g, ph, in, rho);
+  hipLaunchKernelGGL(potential4<T>, g1, dim3(256), 0, s, g, ph, (const double*)rho, mu);
   const dim3 g3((g.nx + S4X - 1) / S4X, (g.ny + S4Y - 1) / S4Y);
   if (scheme == STANDARD)
-    hipLaunchKernelGGL(observe4_kernel<STANDARD>, g3, dim3(S4X * S4Y), 0, s, g, in,
+    hipLaunchKernelGGL((observe4_kernel<T, STANDARD>), g3, dim3(S4X * S4Y), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
-    hipLaunchKernelGGL(observe4_kernel<WELL_BALANCED>, g3, dim3(S4X * S4Y), 0, s, g, in,
+    hipLaunchKernelGGL((observe4_kernel<T, WELL_BALANCED>), g3, dim3(S4X * S4Y), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   return hipGetLastError();
 }
@@ -994,26 +1002,28 @@ hipError_t launch4_observe(int scheme, const Geometry& g, const Physics& ph, con
 
 namespace {
 
-template <int SCHEME, int BW>
+template <typename T, int SCHEME, int BW>
 hipError_t launch_march4_d(const Geometry& g, const Physics& ph, const Tiling& t,
-                           const Global<double>* in, Global<double>* out, hipStream_t s) {
+                           const Global<T>* in, Global<T>* out, hipStream_t s) {
   const dim3 grid(t.blocks()), block(BW);
   if (t.depth == 1)
-    hipLaunchKernelGGL((march4<SCHEME, BW, 1>), grid, block, 0, s, g, ph, t, in, out);
+    hipLaunchKernelGGL((march4<T, SCHEME, BW, 1>), grid, block, 0, s, g, ph, t, in, out);
   else if (t.depth == 2)
-    hipLaunchKernelGGL((march4<SCHEME, BW, 2>), grid, block, 0, s, g, ph, t, in, out);
+    hipLaunchKernelGGL((march4<T, SCHEME, BW, 2>), grid, block, 0, s, g, ph, t, in, out);
   else if (t.depth == 3)
-    hipLaunchKernelGGL((march4<SCHEME, BW, 3>), grid, block, 0, s, g, ph, t, in, out);
+    hipLaunchKernelGGL((march4<T, SCHEME, BW, 3>), grid, block, 0, s, g, ph, t, in, out);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <int SCHEME>
-hipError_t launch_march4(const Geometry& g, const Physics& ph, const Tiling& t,
-                         const Global<double>* in, Global<double>* out, hipStream_t s) {
-  if (t.block == 256) return launch_march4_d<SCHEME, 256>(g, ph, t, in, out, s);
-  if (t.block == 512) return launch_march4_d<SCHEME, 512>(g, ph, t, in, out, s);
+template <typename T, int SCHEME>
+hipError_t launch_march4(const Geometry& g, const Physics& ph, const Tiling& t, const void* fin,
+                         void* fout, hipStream_t s) {
+  const auto* in = (const Global<T>*)(const T*)fin;
+  auto* out = (Global<T>*)(T*)fout;
+  if (t.block == 256) return launch_march4_d<T, SCHEME, 256>(g, ph, t, in, out, s);
+  if (t.block == 512) return launch_march4_d<T, SCHEME, 512>(g, ph, t, in, out, s);
   return hipErrorInvalidValue;
 }
 
@@ -1021,17 +1031,20 @@ hipError_t launch_march4(const Geometry& g, const Physics& ph, const Tiling& t,
 
 bool stencil4_block_supported(int block) { return block == 256 || block == 512; }
 
-hipError_t launch_step4(int scheme, const Geometry& g, const Physics& ph, const Tiling& t,
-                        const void* fin, void* fout, hipStream_t s) {
-  const auto* in = (const Global<double>*)(const double*)fin;
-  auto* out = (Global<double>*)(double*)fout;
-  return scheme == STANDARD ? launch_march4<STANDARD>(g, ph, t, in, out, s)
-                            : launch_march4<WELL_BALANCED>(g, ph, t, in, out, s);
+hipError_t launch_step4(int storage, int scheme, const Geometry& g, const Physics& ph,
+                        const Tiling& t, const void* fin, void* fout, hipStream_t s) {
+  if (storage == FP64)
+    return scheme == STANDARD ? launch_march4<double, STANDARD>(g, ph, t, fin, fout, s)
+                              : launch_march4<double, WELL_BALANCED>(g, ph, t, fin, fout, s);
+  return scheme == STANDARD ? launch_march4<float, STANDARD>(g, ph, t, fin, fout, s)
+                            : launch_march4<float, WELL_BALANCED>(g, ph, t, fin, fout, s);
 }
 
-hipError_t launch_observe4(int scheme, const Geometry& g, const Physics& ph, const void* f,
-                           double* rho, double* mu, const ObserveOut& o, hipStream_t s) {
-  return launch4_observe(scheme, g, ph, f, rho, mu, o, s);
+hipError_t launch_observe4(int storage, int scheme, const Geometry& g, const Physics& ph,
+                           const void* f, double* rho, double* mu, const ObserveOut& o,
+                           hipStream_t s) {
+  return storage == FP64 ? launch4_observe<double>(scheme, g, ph, f, rho, mu, o, s)
+                         : launch4_observe<float>(scheme, g, ph, f, rho, mu, o, s);
 }
 
 hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics& ph,

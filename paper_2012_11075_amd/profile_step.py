@@ -60,7 +60,8 @@ def main():
     prob = I.PROBLEMS[args.problem]
     s = lbm.Solver.for_problem(prob, precision=args.precision, force_stencil=args.force_stencil)
     tile = (args.block, args.rows, args.depth) if (args.block or args.rows or args.depth) else \
-        tune.bench_tile(prob.nx, prob.ny, args.precision)
+        (tune.stencil4_tile if args.force_stencil else tune.bench_tile)(prob.nx, prob.ny,
+                                                                         args.precision)
     s.set_tile(*tile)
     s.init(prob.rho(), scheme=args.scheme)
     print("profile_step: %s %s %s tile=%s" % (prob.name, args.precision, args.scheme,

@@ -66,6 +66,13 @@ def batch_tile(nx: int, ny: int, precision: str = "fp64"):
     return (int(t[0]), int(t[1]), int(t[2])) if t else None
 
 
+def stencil4_tile(nx: int, ny: int, precision: str = "fp64"):
+    """(block, rows, depth) of the force-stencil variant's step (measured
+    sweep at 4096^2), or None (library default)."""
+    t = _table().get("stencil4/%s/%s" % (_bucket(nx, ny), precision))
+    return (int(t[0]), int(t[1]), int(t[2])) if t else None
+
+
 def serve_tile(nx: int, ny: int, precision: str = "fp64"):
     """(block, rows, depth) for a lattice of the served stream, or None.  A
     served batch holds a few tens of lattices at a time, not hundreds, so

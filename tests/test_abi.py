@@ -37,7 +37,6 @@ def test_workspace_bytes_rejects_bad_params(lib):
                 P(4, 4, 1.0, -0.1, 0.02, 1, 0.1), P(4, 4, 1.0, 0.1, -1.0, 1, 0.1),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision=7),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=2),
-                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, precision="fp32s", force_stencil=1),
                 P(4, 70000, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=-1),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=8, precision="fp32s"),
@@ -53,9 +52,10 @@ def test_workspace_bytes_rejects_bad_params(lib):
     p3 = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, nz=40)
     n3 = lib.lbm_workspace_bytes(ctypes.byref(p3))
     assert 2 * 19 * 64 * 48 * 40 * 8 + 5 * 64 * 48 * 40 * 8 <= n3 < 1.05 * (2 * 19 + 5) * 64 * 48 * 40 * 8
-    # the fourth-order force stencil is accepted in FP64
-    good = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1)
-    assert lib.lbm_workspace_bytes(ctypes.byref(good)) > 0
+    # the fourth-order force stencil is accepted in FP64 and FP32-shifted
+    for prec in ("fp64", "fp32s"):
+        good = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1, precision=prec)
+        assert lib.lbm_workspace_bytes(ctypes.byref(good)) > 0
 
 
 def test_params_struct_matches_header(lib):

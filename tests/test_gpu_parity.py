@@ -146,21 +146,23 @@ def test_force_stencil4_graph_replay_bit_exact(lbm):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
 @pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
-def test_force_stencil4_tilings_bit_identical(orc, lbm, scheme):
+def test_force_stencil4_tilings_bit_identical(orc, lbm, scheme, prec):
     """Every tiling of the fused variant step (block width 256 or 512, two
     strips with a ragged one, chunks of 4 to 45 rows marching up and down,
-    1 to 3 rows in flight) gives the same populations bit for bit, and the
-    oracle agrees; other block widths are refused."""
+    1 to 3 rows in flight) gives the same populations bit for bit, in FP64
+    and in FP32-shifted storage, and the oracle agrees (to 1e-11, or to the
+    FP32 bound of tests/test_gpu_fp32.py); other block widths are refused."""
     prob = I.with_size(I.PAPER_DROPLET, 600, 45)
     ph = prob.physics
     steps = 100
-    print("tilings force_stencil=1", scheme, flush=True)
+    print("tilings force_stencil=1", scheme, prec, flush=True)
     p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
     fo = orc.step(scheme, p, orc.init(scheme, p, prob.rho()), steps)
     ref = None
     for tile in [(256, 16, 2), (256, 4, 1), (256, 7, 3), (512, 45, 3), (512, 9, 2), (512, 16, 1)]:
-        s = lbm.Solver.for_problem(prob, force_stencil=1)
+        s = lbm.Solver.for_problem(prob, force_stencil=1, precision=prec)
         s.set_tile(*tile)
         assert s.get_tile() == tile
         s.init(prob.rho(), scheme=scheme)
@@ -169,10 +171,10 @@ def test_force_stencil4_tilings_bit_identical(orc, lbm, scheme):
         s.close()
         if ref is None:
             ref = f
-            assert np.abs(to_oracle(f) - fo).max() <= TOL
+            assert np.abs(to_oracle(f) - fo).max() <= (TOL if prec == "fp64" else 5e-5)
         else:
             assert np.array_equal(f, ref), tile
-    s = lbm.Solver.for_problem(prob, force_stencil=1)
+    s = lbm.Solver.for_problem(prob, force_stencil=1, precision=prec)
     with pytest.raises(lbm.LbmError):
         s.set_tile(128, 16, 2)
     s.close()
@@ -360,7 +362,7 @@ def test_full_grid_sampled_force_stencil4(orc, lbm):
     ph = prob.physics
     p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
     s = lbm.Solver.for_problem(prob, force_stencil=1)
-    s.set_tile(*tune.bench_tile(prob.nx, prob.ny, "fp64"))
+    s.set_tile(*tune.stencil4_tile(prob.nx, prob.ny, "fp64"))
     s.init(prob.rho(), scheme="well_balanced")
     s.step(20, "well_balanced")
     f = s.get_populations()
@@ -381,3 +383,30 @@ def test_full_grid_sampled_force_stencil4(orc, lbm):
         want = out[M:-M, M:-M]
         got = to_oracle(g[:, ys[M:-M]][:, :, xs[M:-M]])
         assert np.abs(got - want).max() <= 1e-12, (y0, x0)
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+def test_force_stencil4_fp32_against_oracle(orc, lbm, scheme):
+    """The variant in FP32-shifted storage against the FP64 oracle after 1000
+    steps, with the bounds the main step's FP32 form meets (single-precision
+    rounding accumulated over the steps: rho, f < 5e-5, u < 1e-5); mass to
+    1e-5 relative."""
+    prob = I.with_size(I.PAPER_DROPLET, 128, 96)
+    ph = prob.physics
+    steps = 1000
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, 1)
+    fo = orc.step(scheme, p, orc.init(scheme, p, prob.rho()), steps)
+    ro, uxo, uyo, _ = orc.fields(scheme, p, fo)
+    s = lbm.Solver.for_problem(prob, force_stencil=1, precision="fp32s")
+    s.init(prob.rho(), scheme=scheme)
+    s.step(steps, scheme)
+    ob = s.observe()
+    f32 = to_oracle(s.get_populations())
+    s.close()
+    e_rho = np.abs(ob["rho"] - ro).max()
+    e_u = max(np.abs(ob["ux"] - uxo).max(), np.abs(ob["uy"] - uyo).max())
+    e_f = np.abs(f32 - fo).max()
+    print("variant fp32 vs oracle, %s, %d steps: rho %.3e  u %.3e  f %.3e"
+          % (scheme, steps, e_rho, e_u, e_f))
+    assert e_rho < 5e-5 and e_u < 1e-5 and e_f < 5e-5
+    assert abs(ob["mass"] - orc.observe(scheme, p, fo)["mass"]) < 1e-5 * ob["mass"]
