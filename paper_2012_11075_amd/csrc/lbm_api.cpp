@@ -989,8 +989,10 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
     free_range(b, r);
     return bfail(b, st, lbm_last_error(nullptr));
   }
+  // default tile of a slot (callers normally set a tuned one): block width
+  // by lattice width, 32-row chunks, two rows in flight
   const int block = p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256);
-  c->tl = make_tiling(c->L.g, block, 32, 1);
+  c->tl = make_tiling(c->L.g, block, 32, 2);
   st = lbm_init(c, rho, nullptr, nullptr, scheme);
   if (st != LBM_OK) {
     std::string m = c->err;
