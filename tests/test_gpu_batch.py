@@ -168,3 +168,34 @@ def test_lanes_with_graphs_release_and_admit(lbm):
         assert np.array_equal(b.get_populations(sl), alone(lbm, p, prec, scheme, 34)), p.name
     assert np.array_equal(b.get_populations(s_new), alone(lbm, extra, prec, scheme, 13))
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_full_batch_sampled(lbm, prec):
+    """The benchmark's batched configuration (the 512 uneven lattices, tuned
+    tiles, two lanes, graphs of 50 steps): after 60 steps, sampled slots of
+    both lanes and all size ranges hold the populations of the same lattice
+    run alone, bit for bit (NaN for NaN where a lattice diverges)."""
+    from paper_2012_11075_amd import tune
+    probs = I.batch_instances(512)
+    prms = [params_of(lbm, p, prec) for p in probs]
+    need = sum(lbm.Batch.slot_bytes(q) for q in prms)
+    b = lbm.Batch(need + lbm.Batch.overhead_bytes(2 * need, len(probs)) + (1 << 24),
+                  max_slots=len(probs))
+    b.set_graph_steps(50)
+    slots = []
+    for q, p in zip(prms, probs):
+        sl = b.admit(q, p.rho(), "well_balanced")
+        t = tune.batch_tile(p.nx, p.ny, prec)
+        if t:
+            b.set_tile(sl, *t)
+        slots.append(sl)
+    b.run(60)
+    order = sorted(range(len(probs)), key=lambda k: probs[k].nx)
+    picks = sorted(set([order[0], order[1], order[len(order) // 2], order[-2], order[-1], 7, 300]))
+    for k in picks:
+        p = probs[k]
+        print("full batch slot", k, p.nx, p.ny, prec, flush=True)
+        assert np.array_equal(b.get_populations(slots[k]), alone(lbm, p, prec, "well_balanced", 60),
+                              equal_nan=True), (k, p.nx)
+    b.close()

@@ -129,3 +129,37 @@ def test_fp32_wb_rho0_keeps_precision(lbm):
     print("fp32 error (rho, u) after 500 steps by rho0:", err)
     assert err[1.0][0] < 2e-5 and err[1.0][1] < 1e-5
     assert err[1.0][0] < 3 * err[0.0][0] + 1e-7 and err[1.0][1] < 3 * err[0.0][1] + 1e-8
+
+
+def test_fp32_full_grid_sampled(orc, lbm):
+    """The FP32-shifted step on the 4096^2 droplet in its benchmark launch
+    configuration: after 20 steps, one more GPU step against the FP64
+    oracle's step from the same (FP32-rounded) populations on periodic crops
+    around sampled windows.  One step adds only single-precision rounding of
+    O(1) populations, a few 1e-8; the bound is 2e-6."""
+    from paper_2012_11075_amd import tune
+    prob = I.DROPLET_4096_FINITE
+    ph = prob.physics
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    s = lbm.Solver.for_problem(prob, precision="fp32s")
+    s.set_tile(*tune.bench_tile(prob.nx, prob.ny, "fp32s"))
+    s.init(prob.rho(), scheme="well_balanced")
+    s.step(20, "well_balanced")
+    f = s.get_populations()
+    s.step(1, "well_balanced")
+    g = s.get_populations()
+    s.close()
+    rng = np.random.default_rng(3)
+    corners = [(0, 0), (4090, 4090), (127, 509), (2045, 3580)]
+    corners += [tuple(int(v) for v in rng.integers(0, 4096, 2)) for _ in range(6)]
+    W, M = 22, 3
+    worst = 0.0
+    for (y0, x0) in corners:
+        ys = np.arange(y0 - M, y0 + W - M) % 4096
+        xs = np.arange(x0 - M, x0 + W - M) % 4096
+        crop = np.ascontiguousarray(np.transpose(f[:, ys][:, :, xs], (1, 2, 0)))
+        want = orc.step("well_balanced", p, crop, 1)[M:-M, M:-M]
+        got = np.transpose(g[:, ys[M:-M]][:, :, xs[M:-M]], (1, 2, 0))
+        worst = max(worst, np.abs(got - want).max())
+    print("fp32 one-step error on 4096^2 crops: %.3e" % worst)
+    assert worst < 2e-6
