@@ -305,7 +305,7 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="
 D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
 
 
-def time_d3q19(steps, warmup, side=None, tile=None):
+def time_d3q19(steps, warmup, side=None, tile=None, precision="fp64"):
     """The 3-D (D3Q19) WB step on a side^3 droplet (FP64): one fused pass
     per step, 19 populations read and written = 304 algorithmic bytes per
     node.  `tile` (block threads, planes per chunk) overrides the default."""
@@ -316,7 +316,7 @@ def time_d3q19(steps, warmup, side=None, tile=None):
     ph = I.PHYS3
     rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
                              I.equilibrium_width(ph), 1e-3, seed=13)
-    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n)
+    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n, precision=precision)
     if tile:
         s.set_tile(*tile)
     s.init(rho, scheme="well_balanced")
@@ -338,13 +338,16 @@ def time_d3q19(steps, warmup, side=None, tile=None):
     del s
     torch.cuda.empty_cache()
     nodes = n ** 3
-    gbs = D3_BYTES * nodes / (ms / 1e3) / 1e9
+    bpu = D3_BYTES // 2 if precision == "fp32s" else D3_BYTES
+    gbs = bpu * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
-            "kernels_per_step": kps, "bytes_per_update": D3_BYTES, "tile": list(used),
+            "precision": precision, "kernels_per_step": kps, "bytes_per_update": bpu,
+            "tile": list(used),
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "workload": "D3Q19 droplet %d^3, R=%g, rho_l=1, rho_v=0.1, beta=0.01, kappa=0.0128, tau=1, "
-                        "WB, FP64, %d steps" % (n, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE, steps)}
+                        "WB, %s, %d steps" % (n, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
+                                              precision.upper(), steps)}
 
 
 def copy_reference(nx, ny):
@@ -473,7 +476,9 @@ def main():
         progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
     if not args.no_d3:
         out["d3q19"] = time_d3q19(100, 5)
-        progress("D3Q19 %.4f ms/step" % out["d3q19"]["ms_per_step"])
+        out["d3q19"]["fp32_shifted"] = time_d3q19(100, 5, precision="fp32s")
+        progress("D3Q19 %.4f ms/step (FP32 %.4f)" % (out["d3q19"]["ms_per_step"],
+                                                     out["d3q19"]["fp32_shifted"]["ms_per_step"]))
     if not args.no_batch:
         out["batched"] = {}
         for prec in ("fp32s", "fp64"):

@@ -90,12 +90,13 @@ typedef struct {
   int32_t nz;            /* lattice depth: 0 or 1 for the 2-D D2Q9 lattice;
                           * > 1 for the 3-D D3Q19 lattice of the same method
                           * (Eqs. 24 and 26 hold for general dimension; here
-                          * D = 3).  3-D lattices are FP64 with the central
-                          * force stencil, single lattices only, ny and
+                          * D = 3).  3-D lattices run in FP64 or
+                          * FP32-shifted storage with the central force
+                          * stencil, single lattices only, ny and
                           * nz <= 65535, a z-plane of populations
-                          * (19 * ny * nx * 8 bytes, nx rounded up to 32)
-                          * below 4 GiB; one kernel per step.  Fields are
-                          * then double[nz][ny][nx]. */
+                          * (19 * ny * nx * element bytes, nx rounded up to
+                          * 32) below 4 GiB; one kernel per step.  Fields
+                          * are then double[nz][ny][nx]. */
 } lbm_params;
 
 typedef struct {

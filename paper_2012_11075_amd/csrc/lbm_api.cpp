@@ -61,13 +61,14 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->force_stencil == 1 && p->ny > 65535)
     return *why = "the fourth-order force stencil needs ny <= 65535", false;
   if (p->nz > 1) {
-    if (p->precision != LBM_FP64) return *why = "3-D lattices are FP64 only", false;
     if (p->force_stencil != 0) return *why = "3-D lattices use the central force stencil", false;
     if (p->ny > 65535 || p->nz > 65535) return *why = "3-D lattices need ny, nz <= 65535", false;
     // the fused step addresses one z-plane of populations with 32-bit offsets
     const long long px = ((long long)p->nx + 31) / 32 * 32;
-    if ((long long)p->ny * lbmk::Q3 * px * 8 > 0xffffffffLL)
-      return *why = "3-D lattices need a z-plane of populations (19 * ny * nx * 8 bytes) below 4 GiB",
+    const long long elem = p->precision == LBM_FP64 ? 8 : 4;
+    if ((long long)p->ny * lbmk::Q3 * px * elem > 0xffffffffLL)
+      return *why = "3-D lattices need a z-plane of populations (19 * ny * nx * element bytes) "
+                    "below 4 GiB",
              false;
   }
   return true;
@@ -153,7 +154,30 @@ lbmk::Physics make_physics(const lbm_params& p, int scheme) {
   return ph;
 }
 
-lbmk::Physics3 make_physics3(const lbm_params& p) {
+// D3Q19 weights in the kernels' velocity order: rest, 6 axis, 12 edge.
+double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// The 3-D counterparts of feq_rest and shift_of.
+void feq3_rest(const lbm_params& p, int scheme, double rho, double* f) {
+  for (int i = 0; i < lbmk::Q3; ++i) {
+    if (scheme == LBM_STANDARD)
+      f[i] = w3(i) * rho;
+    else
+      f[i] = (i == 0) ? rho - (1.0 - w3(0)) * p.rho0 : w3(i) * p.rho0;
+  }
+}
+
+void shift3_of(const lbm_params& p, int scheme, double* s) {
+  for (int i = 0; i < lbmk::Q3; ++i) s[i] = 0.0;
+  if (p.precision == LBM_FP64) return;
+  if (p.shift_all) {
+    for (int i = 0; i < lbmk::Q3; ++i) s[i] = w3(i) * p.rho_ref;
+  } else {
+    feq3_rest(p, scheme, p.rho_ref, s);
+  }
+}
+
+lbmk::Physics3 make_physics3(const lbm_params& p, int scheme) {
   lbmk::Physics3 ph{};
   ph.omega = 1.0 / p.tau;
   ph.fpre = 1.0 - 0.5 / p.tau;
@@ -162,6 +186,11 @@ lbmk::Physics3 make_physics3(const lbm_params& p) {
   ph.rho_l = p.rho_l;
   ph.rho_v = p.rho_v;
   ph.rho0 = p.rho0;
+  ph.rho_ref = p.precision == LBM_FP64 ? 0.0 : p.rho_ref;
+  double fr[lbmk::Q3];
+  shift3_of(p, scheme, ph.s);
+  feq3_rest(p, scheme, ph.rho_ref, fr);
+  for (int i = 0; i < lbmk::Q3; ++i) ph.c[i] = fr[i] - ph.s[i];
   return ph;
 }
 
@@ -245,10 +274,10 @@ void drop_graphs(lbm_ctx* c) {
 // Enqueue n plain step launches.
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   const lbmk::Physics ph = make_physics(c->prm, scheme);
-  const lbmk::Physics3 ph3 = make_physics3(c->prm);
+  const lbmk::Physics3 ph3 = make_physics3(c->prm, scheme);
   for (int64_t k = 0; k < n; ++k) {
     if (c->d3()) {
-      HIPCHK(c, lbmk::launch_step3(scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
+      HIPCHK(c, lbmk::launch_step3(c->storage(), scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
                                    c->buf(1 - c->cur), s));
     } else if (c->prm.force_stencil == 1) {
       HIPCHK(c, lbmk::launch_step4(c->storage(), scheme, c->L.g, ph, c->tl, c->buf(c->cur),
@@ -301,6 +330,20 @@ lbm_status convert_shift(lbm_ctx* c, int to_scheme) {
     c->scheme = to_scheme;
     return LBM_OK;
   }
+  if (c->d3()) {
+    lbmk::Physics3 d{};
+    double so[lbmk::Q3], sn[lbmk::Q3];
+    shift3_of(c->prm, c->scheme, so);
+    shift3_of(c->prm, to_scheme, sn);
+    bool same = true;
+    for (int i = 0; i < lbmk::Q3; ++i) {
+      d.s[i] = so[i] - sn[i];
+      same = same && d.s[i] == 0.0;
+    }
+    if (!same) HIPCHK(c, lbmk::launch_reshift3(c->storage(), c->L.g3, d, c->state(), c->stream));
+    c->scheme = to_scheme;
+    return LBM_OK;
+  }
   double so[Q], sn[Q], d[Q];
   shift_of(c->prm, c->scheme, so);
   shift_of(c->prm, to_scheme, sn);
@@ -339,7 +382,9 @@ lbm_status lbm_create(const lbm_params* p, void* ws, size_t bytes, void* stream,
                 "workspace too small: need " + std::to_string(L.total) + " bytes");
   lbmk::Tiling3 t3{};
   if (L.d3) {
-    t3 = lbmk::make_tiling3(L.g3, 8, 0, 1);
+    // default chunking, measured at 256^3: about 1024 blocks for FP64 (two
+    // rounds of two blocks per CU), 512 for FP32 (one round, long chunks)
+    t3 = lbmk::make_tiling3(L.g3, 8, 0, 1, p->precision == LBM_FP64 ? 1024 : 512);
     if (lbmk::blocks_of(t3) > 0x7fffffffLL)
       return fail(nullptr, LBM_EINVAL, "3-D lattice too large for one launch");
   }
@@ -388,9 +433,9 @@ lbm_status init_impl(lbm_ctx* c, const double* rho, const double* ux, const doub
   c->cur = 0;
   c->scheme = scheme;
   if (d3) {
-    HIPCHK(c, lbmk::launch_init3(scheme, c->L.g3, make_physics3(c->prm), st, ux ? st + n : nullptr,
-                                 ux ? st + 2 * n : nullptr, ux ? st + 3 * n : nullptr, c->state(),
-                                 c->stream));
+    HIPCHK(c, lbmk::launch_init3(c->storage(), scheme, c->L.g3, make_physics3(c->prm, scheme), st,
+                                 ux ? st + n : nullptr, ux ? st + 2 * n : nullptr,
+                                 ux ? st + 3 * n : nullptr, c->state(), c->stream));
   } else {
     const lbmk::Physics ph = make_physics(c->prm, scheme);
     HIPCHK(c, lbmk::launch_init(c->storage(), scheme, c->L.g, ph, st, ux ? st + n : nullptr,
@@ -458,8 +503,9 @@ lbm_status observe_impl(lbm_ctx* c, double* rho, double* ux, double* uy, double*
     // the 3-D pass always computes rho and mu (staging fields 0 and 4)
     const lbmk::ObserveOut3 o{st, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
                               uz ? st + 3 * n : nullptr, st_mu, c->partials()};
-    HIPCHK(c, lbmk::launch_observe3(c->scheme, c->L.g3, make_physics3(c->prm), c->state(), st,
-                                    st_mu, o, c->stream));
+    HIPCHK(c, lbmk::launch_observe3(c->storage(), c->scheme, c->L.g3,
+                                    make_physics3(c->prm, c->scheme), c->state(), st, st_mu, o,
+                                    c->stream));
     nb = lbmk::blocks3(c->L.g3);
   } else {
     lbmk::ObserveOut o{rho ? st : nullptr, ux ? st + n : nullptr, uy ? st + 2 * n : nullptr,
@@ -539,7 +585,8 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
   for (int q0 = 0; q0 < nq; q0 += 4) {
     const int m = std::min(4, nq - q0);
     if (c->d3())
-      HIPCHK(c, lbmk::launch_unpack3(c->L.g3, c->state(), q0, m, c->staging(), c->stream));
+      HIPCHK(c, lbmk::launch_unpack3(c->storage(), c->L.g3, make_physics3(c->prm, c->scheme),
+                                     c->state(), q0, m, c->staging(), c->stream));
     else
       HIPCHK(c, lbmk::launch_unpack(c->storage(), c->L.g, s, c->state(), q0, m, c->staging(),
                                     c->stream));
@@ -566,7 +613,8 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, i
     HIPCHK(c, hipMemcpyAsync(c->staging(), f + (size_t)q0 * n, (size_t)m * n * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
     if (c->d3())
-      HIPCHK(c, lbmk::launch_pack3(c->L.g3, c->staging(), q0, m, c->state(), c->stream));
+      HIPCHK(c, lbmk::launch_pack3(c->storage(), c->L.g3, make_physics3(c->prm, scheme),
+                                   c->staging(), q0, m, c->state(), c->stream));
     else
       HIPCHK(c, lbmk::launch_pack(c->storage(), c->L.g, s, c->staging(), q0, m, c->state(),
                                   c->stream));
@@ -588,7 +636,7 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
     if (!lbmk::tiling3_supported(ty, d))
       return fail(c, LBM_EINVAL, "3-D tiles: block 256 with depth 1..3 or block 512 with depth 1..2");
     if (rows < 0) return fail(c, LBM_EINVAL, "rows (planes per chunk) must be >= 1");
-    const lbmk::Tiling3 t = lbmk::make_tiling3(c->L.g3, ty, rows == 0 ? c->tl3.zc : rows, d);
+    const lbmk::Tiling3 t = lbmk::make_tiling3(c->L.g3, ty, rows == 0 ? c->tl3.zc : rows, d, 0);
     if (lbmk::blocks_of(t) > 0x7fffffffLL) return fail(c, LBM_EINVAL, "too many blocks");
     drop_graphs(c);
     c->tl3 = t;

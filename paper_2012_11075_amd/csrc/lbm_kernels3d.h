@@ -17,9 +17,14 @@ struct Geometry3 {
   long long plane, pitch, slab;
 };
 
-// Constants of the 3-D step (FP64, no storage shift).
+// Constants of the 3-D step.  FP32 storage holds g_i = f_i - s_i: rho_ref
+// is the shift's reference density, c_i = feq_i(rho_ref, 0) - s_i of the
+// scheme stepped (all zero, with rho_ref, for FP64 storage).
 struct Physics3 {
   double omega, fpre, beta, kappa, rho_l, rho_v, rho0;
+  double rho_ref;
+  double c[Q3];
+  double s[Q3];
 };
 
 // Outputs of the 3-D observe pass (any field may be null).
@@ -37,27 +42,32 @@ struct Tiling3 {
   int tiles_x, tiles_y, chunks;
 };
 // ty: 8 (depth 1..3) or 16 (depth 1..2); zc <= 0 picks the chunk length for
-// about 1024 blocks.
-Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth);
+// about `target` blocks.
+Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth, int target);
 bool tiling3_supported(int ty, int depth);
 long long blocks_of(const Tiling3& t);
 
-// Three dimensions (D3Q19, FP64): init from dense fields (u may be null),
+// Three dimensions (D3Q19, FP64 or FP32-shifted storage `storage`): init from
+// dense fields (u may be null),
 // pack/unpack m populations from q0 through a dense staging area, one step
 // (one fused pass fin -> fout), and the observe pass (density into `rho`,
 // chemical potential into `mu`, fields and partials: one per block of
 // blocks3(g)).
-hipError_t launch_init3(int scheme, const Geometry3& g, const Physics3& ph, const double* rho,
-                        const double* ux, const double* uy, const double* uz, void* f,
-                        hipStream_t s);
-hipError_t launch_pack3(const Geometry3& g, const double* dense, int q0, int m, void* f,
-                        hipStream_t s);
-hipError_t launch_unpack3(const Geometry3& g, const void* f, int q0, int m, double* dense,
-                          hipStream_t s);
-hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const Tiling3& t,
-                        const void* fin, void* fout, hipStream_t s);
-hipError_t launch_observe3(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
-                           double* rho, double* mu, const ObserveOut3& o, hipStream_t s);
+hipError_t launch_init3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                        const double* rho, const double* ux, const double* uy, const double* uz,
+                        void* f, hipStream_t s);
+hipError_t launch_pack3(int storage, const Geometry3& g, const Physics3& ph, const double* dense,
+                        int q0, int m, void* f, hipStream_t s);
+hipError_t launch_unpack3(int storage, const Geometry3& g, const Physics3& ph, const void* f,
+                          int q0, int m, double* dense, hipStream_t s);
+// g_i += delta.s[i] on every node (change of the FP32 storage shift).
+hipError_t launch_reshift3(int storage, const Geometry3& g, const Physics3& delta, void* f,
+                           hipStream_t s);
+hipError_t launch_step3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                        const Tiling3& t, const void* fin, void* fout, hipStream_t s);
+hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                           const void* f, double* rho, double* mu, const ObserveOut3& o,
+                           hipStream_t s);
 int blocks3(const Geometry3& g);
 
 }  // namespace lbmk

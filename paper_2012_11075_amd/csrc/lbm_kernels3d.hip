@@ -56,8 +56,10 @@ __device__ __forceinline__ long long src3(const Geometry3& g, int q, int x, int 
   return (long long)zs * g.slab + (long long)ys * g.pitch + xs;
 }
 
-__device__ __forceinline__ double mu0_3(double r, const Physics3& p) {
-  return 2.0 * p.beta * (r - p.rho_l) * (r - p.rho_v) * (2.0 * r - p.rho_l - p.rho_v);
+template <typename R>
+__device__ __forceinline__ R mu0_3(R r, const Physics3& p) {
+  const R rl = (R)p.rho_l, rv = (R)p.rho_v;
+  return (R)2 * (R)p.beta * (r - rl) * (r - rv) * ((R)2 * r - rl - rv);
 }
 
 // Equilibrium (Eq. 3 / Eq. 24) and forcing term (Eq. 5 / Eq. 26 with D = 3:
@@ -66,45 +68,54 @@ __device__ __forceinline__ double mu0_3(double r, const Physics3& p) {
 // post-collision population as soon as it is known.  A scheduling barrier
 // after every G directions keeps the compiler from computing all 19 at once
 // (each result then dies at its store instead of holding a register).
-template <int SCHEME, int G, typename E>
-__device__ __forceinline__ void collide3(const double (&f)[Q3], double rho, double ux, double uy,
-                                         double uz, double Fx, double Fy, double Fz, double grx,
-                                         double gry, double grz, const Physics3& p, E&& emit) {
-  const double u15 = 1.5 * (ux * ux + uy * uy + uz * uz);
-  double Gx = Fx, Gy = Fy, Gz = Fz;
+// FP32 storage holds g_i = f_i - s_i: the equilibrium is then taken as
+// feq_i(rho, u) - feq_i(rho_ref, 0) from drho = rho - rho_ref, plus the
+// constant c_i = feq_i(rho_ref, 0) - s_i (the rho0 terms cancel).
+template <int SCHEME, int G, typename R, typename E>
+__device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, R uy, R uz, R Fx,
+                                         R Fy, R Fz, R grx, R gry, R grz, const Physics3& p,
+                                         E&& emit) {
+  constexpr bool SHIFTED = sizeof(R) == 4;
+  const R u15 = (R)1.5 * (ux * ux + uy * uy + uz * uz);
+  R Gx = Fx, Gy = Fy, Gz = Fz;
   if (SCHEME == WELL_BALANCED) {
-    Gx += grx * (1.0 / 3.0);
-    Gy += gry * (1.0 / 3.0);
-    Gz += grz * (1.0 / 3.0);
+    Gx += grx * ((R)1 / (R)3);
+    Gy += gry * ((R)1 / (R)3);
+    Gz += grz * ((R)1 / (R)3);
   }
-  const double uG3 = 3.0 * (ux * Gx + uy * Gy + uz * Gz);
-  const double ugr = ux * grx + uy * gry + uz * grz;
+  const R uG3 = (R)3 * (ux * Gx + uy * Gy + uz * Gz);
+  const R ugr = ux * grx + uy * gry + uz * grz;
+  const R omega = (R)p.omega, fpre = (R)p.fpre, rho0 = (R)p.rho0;
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
     int cx, cy, cz;
     c3(i, cx, cy, cz);
-    const double w = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
-    const double cu = cx * ux + cy * uy + cz * uz;
-    const double cF = cx * Fx + cy * Fy + cz * Fz;
-    const double cG = cx * Gx + cy * Gy + cz * Gz;
-    const double poly = 3.0 * cu + 4.5 * cu * cu - u15;
-    double feq, Fi;
+    const R w = i == 0 ? (R)1 / (R)3 : (i < 7 ? (R)1 / (R)18 : (R)1 / (R)36);
+    const R cu = cx * ux + cy * uy + cz * uz;
+    const R cF = cx * Fx + cy * Fy + cz * Fz;
+    const R cG = cx * Gx + cy * Gy + cz * Gz;
+    const R poly = (R)3 * cu + (R)4.5 * cu * cu - u15;
+    R feq, Fi;
     if (SCHEME == STANDARD) {
-      feq = w * rho * (1.0 + poly);
-      Fi = w * (3.0 * cF + 9.0 * cu * cG - uG3);
+      feq = SHIFTED ? w * (drho + rho * poly) + (R)p.c[i] : w * rho * ((R)1 + poly);
+      Fi = w * ((R)3 * cF + (R)9 * cu * cG - uG3);
     } else {
-      feq = i == 0 ? rho - (1.0 - w) * p.rho0 - w * rho * u15 : w * (p.rho0 + rho * poly);
-      const double k = i == 0 ? -1.5 : (i < 7 ? 0.0 : 1.5);
-      Fi = w * (3.0 * cF + 9.0 * cu * cG - uG3 + k * ugr);
+      if (SHIFTED)
+        feq = (i == 0 ? drho - w * rho * u15 : w * rho * poly) + (R)p.c[i];
+      else
+        feq = i == 0 ? rho - ((R)1 - w) * rho0 - w * rho * u15 : w * (rho0 + rho * poly);
+      const R k = i == 0 ? (R)-1.5 : (i < 7 ? (R)0 : (R)1.5);
+      Fi = w * ((R)3 * cF + (R)9 * cu * cG - uG3 + k * ugr);
     }
-    emit(i, f[i] - p.omega * (f[i] - feq) + p.fpre * Fi);
+    emit(i, f[i] - omega * (f[i] - feq) + fpre * Fi);
     if (G > 0 && i % G == G - 1) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
 // rho = sum_i f_i in a fixed order (every kernel sums a node the same way).
-__device__ __forceinline__ double sum19(const double (&f)[Q3]) {
-  double s = 0.0;
+template <typename R>
+__device__ __forceinline__ R sum19(const R (&f)[Q3]) {
+  R s = (R)0;
 #pragma unroll
   for (int i = 0; i < Q3; ++i) s += f[i];
   return s;
@@ -112,53 +123,52 @@ __device__ __forceinline__ double sum19(const double (&f)[Q3]) {
 
 // 19-point Laplacian (2/cs2) sum_i w_i [phi(x + c_i) - phi(x)] from
 // at(dx, dy, dz) = phi(x + (dx, dy, dz)); the sums pair +z with -z.
-template <typename A>
-__device__ __forceinline__ double lap19(const A& at, double c) {
-  const double ax = ((at(1, 0, 0) + at(-1, 0, 0)) + (at(0, 1, 0) + at(0, -1, 0))) +
-                    (at(0, 0, 1) + at(0, 0, -1));
-  const double xy = (at(1, 1, 0) + at(-1, -1, 0)) + (at(1, -1, 0) + at(-1, 1, 0));
-  const double xz = (at(1, 0, 1) + at(1, 0, -1)) + (at(-1, 0, -1) + at(-1, 0, 1));
-  const double yz = (at(0, 1, 1) + at(0, 1, -1)) + (at(0, -1, -1) + at(0, -1, 1));
-  return (2.0 * ax + ((xy + xz) + yz) - 24.0 * c) * (1.0 / 6.0);
+template <typename R, typename A>
+__device__ __forceinline__ R lap19(const A& at, R c) {
+  const R ax = ((at(1, 0, 0) + at(-1, 0, 0)) + (at(0, 1, 0) + at(0, -1, 0))) +
+               (at(0, 0, 1) + at(0, 0, -1));
+  const R xy = (at(1, 1, 0) + at(-1, -1, 0)) + (at(1, -1, 0) + at(-1, 1, 0));
+  const R xz = (at(1, 0, 1) + at(1, 0, -1)) + (at(-1, 0, -1) + at(-1, 0, 1));
+  const R yz = (at(0, 1, 1) + at(0, 1, -1)) + (at(0, -1, -1) + at(0, -1, 1));
+  return ((R)2 * ax + ((xy + xz) + yz) - (R)24 * c) * ((R)1 / (R)6);
 }
 
 // Isotropic central gradient (1/cs2) sum_i w_i c_i phi(x + c_i) at row j,
 // column i of the LDS plane a0, with am and ap the planes at z - 1 and z + 1.
 // Swapping am and ap negates gz exactly and leaves gx, gy unchanged.
-template <int W>
-__device__ __forceinline__ void grad3p(const double (*am)[W], const double (*a0)[W],
-                                       const double (*ap)[W], int j, int i, double& gx,
-                                       double& gy, double& gz) {
-  gx = (a0[j][i + 1] - a0[j][i - 1]) * (1.0 / 6.0) +
+template <int W, typename R>
+__device__ __forceinline__ void grad3p(const R (*am)[W], const R (*a0)[W], const R (*ap)[W], int j,
+                                       int i, R& gx, R& gy, R& gz) {
+  const R s6 = (R)1 / (R)6, s12 = (R)1 / (R)12;
+  gx = (a0[j][i + 1] - a0[j][i - 1]) * s6 +
        (((a0[j + 1][i + 1] - a0[j + 1][i - 1]) + (a0[j - 1][i + 1] - a0[j - 1][i - 1])) +
         ((ap[j][i + 1] - ap[j][i - 1]) + (am[j][i + 1] - am[j][i - 1]))) *
-           (1.0 / 12.0);
-  gy = (a0[j + 1][i] - a0[j - 1][i]) * (1.0 / 6.0) +
+           s12;
+  gy = (a0[j + 1][i] - a0[j - 1][i]) * s6 +
        (((a0[j + 1][i + 1] - a0[j - 1][i + 1]) + (a0[j + 1][i - 1] - a0[j - 1][i - 1])) +
         ((ap[j + 1][i] - ap[j - 1][i]) + (am[j + 1][i] - am[j - 1][i]))) *
-           (1.0 / 12.0);
-  gz = (ap[j][i] - am[j][i]) * (1.0 / 6.0) +
+           s12;
+  gz = (ap[j][i] - am[j][i]) * s6 +
        (((ap[j][i + 1] - am[j][i + 1]) + (ap[j][i - 1] - am[j][i - 1])) +
         ((ap[j + 1][i] - am[j + 1][i]) + (ap[j - 1][i] - am[j - 1][i]))) *
-           (1.0 / 12.0);
+           s12;
 }
 
 // Force (F = -rho grad mu for WB, Eq. 25; plus grad(rho)/3 for the standard
 // scheme, Eq. 6) and the half-force velocity of Eq. (4).
-template <int SCHEME>
-__device__ __forceinline__ void force_velocity3(const double (&f)[Q3], double r, double grx,
-                                                double gry, double grz, double gmx, double gmy,
-                                                double gmz, double& Fx, double& Fy, double& Fz,
-                                                double& ux, double& uy, double& uz) {
+template <int SCHEME, typename R>
+__device__ __forceinline__ void force_velocity3(const R (&f)[Q3], R r, R grx, R gry, R grz, R gmx,
+                                                R gmy, R gmz, R& Fx, R& Fy, R& Fz, R& ux, R& uy,
+                                                R& uz) {
   Fx = -r * gmx;
   Fy = -r * gmy;
   Fz = -r * gmz;
   if (SCHEME == STANDARD) {
-    Fx += grx * (1.0 / 3.0);
-    Fy += gry * (1.0 / 3.0);
-    Fz += grz * (1.0 / 3.0);
+    Fx += grx * ((R)1 / (R)3);
+    Fy += gry * ((R)1 / (R)3);
+    Fz += grz * ((R)1 / (R)3);
   }
-  double jx = 0.0, jy = 0.0, jz = 0.0;
+  R jx = (R)0, jy = (R)0, jz = (R)0;
 #pragma unroll
   for (int i = 0; i < Q3; ++i) {
     int cx, cy, cz;
@@ -167,10 +177,10 @@ __device__ __forceinline__ void force_velocity3(const double (&f)[Q3], double r,
     if (cy) jy += cy > 0 ? f[i] : -f[i];
     if (cz) jz += cz > 0 ? f[i] : -f[i];
   }
-  const double inv = 1.0 / r;
-  ux = (jx + 0.5 * Fx) * inv;
-  uy = (jy + 0.5 * Fy) * inv;
-  uz = (jz + 0.5 * Fz) * inv;
+  const R inv = (R)1 / r;
+  ux = (jx + (R)0.5 * Fx) * inv;
+  uy = (jy + (R)0.5 * Fy) * inv;
+  uz = (jz + (R)0.5 * Fz) * inv;
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -195,8 +205,27 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int RSRC_WORD3 = 0x00020000;  // raw 32-bit data, no swizzle (gfx9 family)
 constexpr int CPOL_NT = 2;              // non-temporal
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_buffer(const double* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)bytes, RSRC_WORD3);
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_buffer(const T* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), 0, (int)bytes, RSRC_WORD3);
+}
+
+// One element at a byte offset of a buffer, and its non-temporal store.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t b, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store_nt(T v, __amdgpu_buffer_rsrc_t b, unsigned voff,
+                                             unsigned soff) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), b, voff, soff, CPOL_NT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), b, voff, soff, CPOL_NT);
 }
 
 // Pull sources of one node (x, y) within a z-plane: byte offset of the node
@@ -205,6 +234,7 @@ struct Pull3 {
   unsigned off[3][3];
 };
 
+template <typename T>
 __device__ __forceinline__ Pull3 pull_of(const Geometry3& g, int x, int y) {
   Pull3 s;
 #pragma unroll
@@ -212,31 +242,31 @@ __device__ __forceinline__ Pull3 pull_of(const Geometry3& g, int x, int y) {
     const long long row = (long long)wrapi(y - cy, g.ny) * g.pitch;
 #pragma unroll
     for (int cx = -1; cx <= 1; ++cx)
-      s.off[cy + 1][cx + 1] = (unsigned)((row + wrapi(x - cx, g.nx)) * (long long)sizeof(double));
+      s.off[cy + 1][cx + 1] = (unsigned)((row + wrapi(x - cx, g.nx)) * (long long)sizeof(T));
   }
   return s;
 }
 
 // The 19 pulled populations of node s on a plane; b[c_z + 1] is the plane
 // z - c_z, pb the bytes between populations.
+template <typename T>
 __device__ __forceinline__ void load19(const __amdgpu_buffer_rsrc_t (&b)[3], unsigned pb,
-                                       const Pull3& s, double (&f)[Q3]) {
+                                       const Pull3& s, T (&f)[Q3]) {
 #pragma unroll
   for (int q = 0; q < Q3; ++q) {
     int cx, cy, cz;
     c3(q, cx, cy, cz);
-    f[q] = __builtin_bit_cast(
-        double, __builtin_amdgcn_raw_buffer_load_b64(b[cz + 1], s.off[cy + 1][cx + 1], q * pb, 0));
+    f[q] = buf_load<T>(b[cz + 1], s.off[cy + 1][cx + 1], q * pb);
   }
 }
 
 // Fused step: one block per (32 x TY column, chunk of tl.zc planes).  D:
 // planes of populations loaded ahead of the plane being summed (0 = none).
 constexpr int CG = 3;  // directions per scheduling region of the collision
-template <int SCHEME, int TY, int D>
+template <typename T, int SCHEME, int TY, int D>
 __global__ void __launch_bounds__(M3X * TY)
-    march3(Geometry3 g, Physics3 p, Tiling3 tl, const double* __restrict__ fin,
-           double* __restrict__ fout) {
+    march3(Geometry3 g, Physics3 p, Tiling3 tl, const T* __restrict__ fin, T* __restrict__ fout) {
+  using R = T;
   constexpr int NT = M3X * TY;
   constexpr int RX = M3X + 4, RY = TY + 4;  // rho region: tile and a 2-node halo
   constexpr int MX = M3X + 2, MY = TY + 2;  // mu region: tile and a 1-node halo
@@ -247,9 +277,9 @@ __global__ void __launch_bounds__(M3X * TY)
   // (each thread its own column); halo of planes k .. k+D-1.
   constexpr int RP = 2 + D, RH = D > 0 ? D : 1;
   constexpr int U = (RP % RH == 0) ? RP : RP * RH;  // unroll: slots are compile-time
-  __shared__ double pk[Q3][NT];
-  __shared__ double rs[5][RY][RX];  // region (i, j) is lattice (x0 - 2 + i, y0 - 2 + j)
-  __shared__ double ms[3][MY][MX];  // region (i, j) is lattice (x0 - 1 + i, y0 - 1 + j)
+  __shared__ R pk[Q3][NT];
+  __shared__ R rs[5][RY][RX];  // region (i, j) is lattice (x0 - 2 + i, y0 - 2 + j)
+  __shared__ R ms[3][MY][MX];  // region (i, j) is lattice (x0 - 1 + i, y0 - 1 + j)
   const int t = threadIdx.x;
   const int per_plane = tl.tiles_x * tl.tiles_y;
   const int item = xcd_item(blockIdx.x, per_plane * tl.chunks);
@@ -265,7 +295,7 @@ __global__ void __launch_bounds__(M3X * TY)
 
   const int tx = t % M3X, ty = t / M3X;
   const bool own = x0 + tx < g.nx && y0 + ty < g.ny;
-  const Pull3 si = pull_of(g, x0 + tx, y0 + ty);
+  const Pull3 si = pull_of<T>(g, x0 + tx, y0 + ty);
   // Halo node of this lane: wave w takes halo nodes w*HPW .. w*HPW+HPW-1,
   // numbered along the two rows above the tile, the side columns, then the
   // two rows below.
@@ -286,33 +316,33 @@ __global__ void __launch_bounds__(M3X * TY)
       hi = e - (e / RX) * RX;
     }
   }
-  const Pull3 sh = pull_of(g, x0 - 2 + hi, y0 - 2 + hj);
+  const Pull3 sh = pull_of<T>(g, x0 - 2 + hi, y0 - 2 + hj);
+  const R rho_ref = (R)p.rho_ref, kappa = (R)p.kappa;
 
-  const unsigned pb = (unsigned)(g.plane * (long long)sizeof(double));
-  const unsigned slab_bytes = (unsigned)(g.slab * (long long)sizeof(double));
+  const unsigned pb = (unsigned)(g.plane * (long long)sizeof(T));
+  const unsigned slab_bytes = (unsigned)(g.slab * (long long)sizeof(T));
   const unsigned own_off =
-      (unsigned)(((long long)(y0 + ty) * g.pitch + (x0 + tx)) * (long long)sizeof(double));
+      (unsigned)(((long long)(y0 + ty) * g.pitch + (x0 + tx)) * (long long)sizeof(T));
 
   // Loads of plane k.
-  auto load_plane = [&](int k, double(&Pl)[Q3], double(&Hl)[Q3]) {
+  auto load_plane = [&](int k, R(&Pl)[Q3], R(&Hl)[Q3]) {
     const int z = plane_of(k);
     __amdgpu_buffer_rsrc_t b[3];
 #pragma unroll
     for (int c = -1; c <= 1; ++c)
-      b[c + 1] = plane_buffer(fin + (long long)wrapi(z - c, g.nz) * g.slab, slab_bytes);
-    load19(b, pb, si, Pl);
-    if (hl) load19(b, pb, sh, Hl);
+      b[c + 1] = plane_buffer<T>(fin + (long long)wrapi(z - c, g.nz) * g.slab, slab_bytes);
+    load19<T>(b, pb, si, Pl);
+    if (hl) load19<T>(b, pb, sh, Hl);
   };
 
   // Plane step k: publish rho of plane k (populations in Pk, halo in Hk),
   // start the loads of plane k+D (into Pn, Hk), mu of plane k-1, update the
   // nodes of plane k-2 (populations parked in LDS), park plane k-1 (Pm).
-  auto stage = [&](int k, double(&Pk)[Q3], double(&Hk)[Q3], double(&Pn)[Q3],
-                   double(&Pm)[Q3]) {
+  auto stage = [&](int k, R(&Pk)[Q3], R(&Hk)[Q3], R(&Pn)[Q3], R(&Pm)[Q3]) {
     if (D == 0) load_plane(k, Pk, Hk);
     const int sk = k % 5;
-    rs[sk][ty + 2][tx + 2] = sum19(Pk);
-    if (hl) rs[sk][hj][hi] = sum19(Hk);
+    rs[sk][ty + 2][tx + 2] = rho_ref + sum19(Pk);
+    if (hl) rs[sk][hj][hi] = rho_ref + sum19(Hk);
     if (D > 0 && k + D < K) load_plane(k + D, Pn, Hk);
     __syncthreads();
     if (k >= 2) {
@@ -323,8 +353,8 @@ __global__ void __launch_bounds__(M3X * TY)
         auto at = [&](int dx, int dy, int dz) {
           return rs[dz < 0 ? sm : (dz > 0 ? sk : s0)][j + dy][i + dx];
         };
-        const double r0 = rs[s0][j][i];
-        ms[mk][mj][mi] = mu0_3(r0, p) - p.kappa * lap19(at, r0);
+        const R r0 = rs[s0][j][i];
+        ms[mk][mj][mi] = mu0_3(r0, p) - kappa * lap19(at, r0);
       }
     }
     __syncthreads();
@@ -333,7 +363,7 @@ __global__ void __launch_bounds__(M3X * TY)
       // thread its own column), then the collision: the scheduling barriers
       // keep the phases apart, so their temporaries are not live at once.
       const int c = k - 2;
-      double grx = 0.0, gry = 0.0, grz = 0.0, gmx = 0.0, gmy = 0.0, gmz = 0.0, r = 1.0;
+      R grx = (R)0, gry = (R)0, grz = (R)0, gmx = (R)0, gmy = (R)0, gmz = (R)0, r = (R)1;
       if (k >= 4) {
         const int sM = (c - 1) % 5, s0 = c % 5, sP = (c + 1) % 5;
         const int mM = (c - 1) % 3, m0 = c % 3, mP = (c + 1) % 3;
@@ -342,7 +372,7 @@ __global__ void __launch_bounds__(M3X * TY)
         r = rs[s0][ty + 2][tx + 2];
       }
       __builtin_amdgcn_sched_barrier(0);
-      double f[Q3];
+      R f[Q3];
       if (k >= 4) {
 #pragma unroll
         for (int q = 0; q < Q3; ++q) f[q] = pk[q][t];
@@ -357,20 +387,18 @@ __global__ void __launch_bounds__(M3X * TY)
           grz = -grz;
           gmz = -gmz;
         }
-        double Fx, Fy, Fz, ux, uy, uz;
+        R Fx, Fy, Fz, ux, uy, uz;
         force_velocity3<SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
         const __amdgpu_buffer_rsrc_t o =
-            plane_buffer(fout + (long long)plane_of(c) * g.slab, slab_bytes);
-        collide3<SCHEME, CG>(f, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p,
-                             [&](int q, double v) {
-                               __builtin_amdgcn_raw_buffer_store_b64(
-                                   __builtin_bit_cast(u32x2, v), o, own_off, q * pb, CPOL_NT);
-                             });
+            plane_buffer<T>(fout + (long long)plane_of(c) * g.slab, slab_bytes);
+        const R drho = sum19(f);
+        collide3<SCHEME, CG>(f, drho, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p,
+                             [&](int q, R v) { buf_store_nt<T>(v, o, own_off, q * pb); });
       }
     }
   };
 
-  double P[RP][Q3], H[RH][Q3];
+  R P[RP][Q3], H[RH][Q3];
 #pragma unroll
   for (int k = 0; k < D; ++k) load_plane(k, P[k], H[k % RH]);
   for (int k0 = 0; k0 < K; k0 += U) {
@@ -381,39 +409,45 @@ __global__ void __launch_bounds__(M3X * TY)
   }
 }
 
+// Observe pass, in the storage type's arithmetic as the step (FP32 storage:
+// rho = rho_ref + sum_i g_i, then every stencil in FP32); fields as double.
+template <typename T>
 __global__ void __launch_bounds__(256)
-    density3(Geometry3 g, const Global<double>* __restrict__ fin, double* __restrict__ rho) {
+    density3(Geometry3 g, Physics3 p, const Global<T>* __restrict__ fin, double* __restrict__ rho) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
-  double f[Q3];
+  T f[Q3];
 #pragma unroll
   for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
-  rho[((long long)z * g.ny + y) * g.nx + x] = sum19(f);
+  rho[((long long)z * g.ny + y) * g.nx + x] = (double)((T)p.rho_ref + sum19(f));
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256)
     potential3(Geometry3 g, Physics3 p, const double* __restrict__ rho, double* __restrict__ mu) {
+  using R = T;
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
   auto at = [&](int dx, int dy, int dz) {
     const int a = wrapi(x + dx, g.nx), b = wrapi(y + dy, g.ny), c = wrapi(z + dz, g.nz);
-    return rho[((long long)c * g.ny + b) * g.nx + a];
+    return (R)rho[((long long)c * g.ny + b) * g.nx + a];
   };
-  const double c = at(0, 0, 0);
-  mu[((long long)z * g.ny + y) * g.nx + x] = mu0_3(c, p) - p.kappa * lap19(at, c);
+  const R c = at(0, 0, 0);
+  mu[((long long)z * g.ny + y) * g.nx + x] = (double)(mu0_3(c, p) - (R)p.kappa * lap19(at, c));
 }
 
 constexpr int T3X = 32, T3Y = 4, T3Z = 2;  // observe block (threads)
 
 // Fields and per-block partials (max|u|, mass, kinetic energy, non-finite
 // flag) of the state f, from dense rho and mu.
-template <int SCHEME>
+template <typename T, int SCHEME>
 __global__ void __launch_bounds__(T3X * T3Y * T3Z)
-    observe3_kernel(Geometry3 g, const Global<double>* __restrict__ fin,
+    observe3_kernel(Geometry3 g, const Global<T>* __restrict__ fin,
                     const double* __restrict__ rho, const double* __restrict__ mu,
                     ObserveOut3 obs) {
-  __shared__ double rt[T3Z + 2][T3Y + 2][T3X + 2];
-  __shared__ double mt[T3Z + 2][T3Y + 2][T3X + 2];
+  using R = T;
+  __shared__ R rt[T3Z + 2][T3Y + 2][T3X + 2];
+  __shared__ R mt[T3Z + 2][T3Y + 2][T3X + 2];
   const int tid = threadIdx.x;
   const int tx = tid % T3X, ty = (tid / T3X) % T3Y, tz = tid / (T3X * T3Y);
   const int x0 = blockIdx.x * T3X, y0 = blockIdx.y * T3Y, z0 = blockIdx.z * T3Z;
@@ -423,22 +457,23 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
     const int xx = wrapi(x0 + i - 1, g.nx), yy = wrapi(y0 + j - 1, g.ny),
               zz = wrapi(z0 + k - 1, g.nz);
     const long long o = ((long long)zz * g.ny + yy) * g.nx + xx;
-    rt[k][j][i] = rho[o];
-    mt[k][j][i] = mu[o];
+    rt[k][j][i] = (R)rho[o];
+    mt[k][j][i] = (R)mu[o];
   }
   __syncthreads();
   const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
   double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
   if (x < g.nx && y < g.ny && z < g.nz) {
-    double f[Q3];
+    R f[Q3];
 #pragma unroll
     for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
-    const double r = rt[tz + 1][ty + 1][tx + 1];
-    double grx, gry, grz, gmx, gmy, gmz;
+    const R rr = rt[tz + 1][ty + 1][tx + 1];
+    R grx, gry, grz, gmx, gmy, gmz;
     grad3p<T3X + 2>(rt[tz], rt[tz + 1], rt[tz + 2], ty + 1, tx + 1, grx, gry, grz);
     grad3p<T3X + 2>(mt[tz], mt[tz + 1], mt[tz + 2], ty + 1, tx + 1, gmx, gmy, gmz);
-    double Fx, Fy, Fz, ux, uy, uz;
-    force_velocity3<SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
+    R Fx, Fy, Fz, uxr, uyr, uzr;
+    force_velocity3<SCHEME>(f, rr, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, uxr, uyr, uzr);
+    const double r = (double)rr, ux = (double)uxr, uy = (double)uyr, uz = (double)uzr;
     const long long o = ((long long)z * g.ny + y) * g.nx + x;
     if (obs.ux) obs.ux[o] = ux;
     if (obs.uy) obs.uy[o] = uy;
@@ -486,12 +521,13 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
   }
 }
 
-// f = feq(rho, u) of every node, stored where the next pull reads it.
-template <int SCHEME>
+// f = feq(rho, u) of every node (in double), stored minus the storage shift
+// s_i where the next pull reads it.
+template <typename T, int SCHEME>
 __global__ void __launch_bounds__(256)
     init3_kernel(Geometry3 g, Physics3 p, const double* __restrict__ rho,
                  const double* __restrict__ ux, const double* __restrict__ uy,
-                 const double* __restrict__ uz, double* __restrict__ f) {
+                 const double* __restrict__ uz, T* __restrict__ f) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
   const long long k = ((long long)z * g.ny + y) * g.nx + x;
@@ -509,14 +545,16 @@ __global__ void __launch_bounds__(256)
       q = w * r * (1.0 + poly);
     else
       q = i == 0 ? r - (1.0 - w) * p.rho0 - w * r * u15 : w * (p.rho0 + r * poly);
-    f[(long long)i * g.plane + src3(g, i, x, y, z)] = q;
+    f[(long long)i * g.plane + src3(g, i, x, y, z)] = (T)(q - p.s[i]);
   }
 }
 
-// dense[m][z][y][x] <-> populations q0 .. q0+m-1 (pre-collision f at each node).
-template <bool PACK>
+// dense[m][z][y][x] <-> populations q0 .. q0+m-1 (pre-collision f at each
+// node), removing (to storage) or adding back (from storage) the shift s_q.
+template <typename T, bool PACK>
 __global__ void __launch_bounds__(256)
-    pack3_kernel(Geometry3 g, int q0, int m, double* __restrict__ dense, double* __restrict__ f) {
+    pack3_kernel(Geometry3 g, Physics3 p, int q0, int m, double* __restrict__ dense,
+                 T* __restrict__ f) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
   const long long n = (long long)g.nx * g.ny * g.nz;
@@ -525,9 +563,21 @@ __global__ void __launch_bounds__(256)
     const int q = q0 + j;
     const long long o = (long long)q * g.plane + src3(g, q, x, y, z);
     if (PACK)
-      f[o] = dense[j * n + k];
+      f[o] = (T)(dense[j * n + k] - p.s[q]);
     else
-      dense[j * n + k] = f[o];
+      dense[j * n + k] = (double)f[o] + p.s[q];
+  }
+}
+
+// g_i += d_i on every node (change of the FP32 storage shift).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    reshift3_kernel(Geometry3 g, Physics3 d, T* __restrict__ f) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= g.nx) return;
+  for (int q = 0; q < Q3; ++q) {
+    const long long o = (long long)z * g.slab + (long long)y * g.pitch + (long long)q * g.plane + x;
+    f[o] = (T)((double)f[o] + d.s[q]);
   }
 }
 
@@ -543,42 +593,70 @@ int blocks3(const Geometry3& g) {
   return ((g.nx + T3X - 1) / T3X) * ((g.ny + T3Y - 1) / T3Y) * ((g.nz + T3Z - 1) / T3Z);
 }
 
-hipError_t launch_init3(int scheme, const Geometry3& g, const Physics3& ph, const double* rho,
-                        const double* ux, const double* uy, const double* uz, void* f,
-                        hipStream_t s) {
-  if (scheme == STANDARD)
-    hipLaunchKernelGGL(init3_kernel<STANDARD>, grid_rows3(g), dim3(256), 0, s, g, ph, rho, ux,
-                       uy, uz, (double*)f);
+hipError_t launch_init3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                        const double* rho, const double* ux, const double* uy, const double* uz,
+                        void* f, hipStream_t s) {
+  if (storage == FP64) {
+    if (scheme == STANDARD)
+      hipLaunchKernelGGL((init3_kernel<double, STANDARD>), grid_rows3(g), dim3(256), 0, s, g, ph,
+                         rho, ux, uy, uz, (double*)f);
+    else
+      hipLaunchKernelGGL((init3_kernel<double, WELL_BALANCED>), grid_rows3(g), dim3(256), 0, s, g,
+                         ph, rho, ux, uy, uz, (double*)f);
+  } else {
+    if (scheme == STANDARD)
+      hipLaunchKernelGGL((init3_kernel<float, STANDARD>), grid_rows3(g), dim3(256), 0, s, g, ph,
+                         rho, ux, uy, uz, (float*)f);
+    else
+      hipLaunchKernelGGL((init3_kernel<float, WELL_BALANCED>), grid_rows3(g), dim3(256), 0, s, g,
+                         ph, rho, ux, uy, uz, (float*)f);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pack3(int storage, const Geometry3& g, const Physics3& ph, const double* dense,
+                        int q0, int m, void* f, hipStream_t s) {
+  if (storage == FP64)
+    hipLaunchKernelGGL((pack3_kernel<double, true>), grid_rows3(g), dim3(256), 0, s, g, ph, q0, m,
+                       const_cast<double*>(dense), (double*)f);
   else
-    hipLaunchKernelGGL(init3_kernel<WELL_BALANCED>, grid_rows3(g), dim3(256), 0, s, g, ph, rho,
-                       ux, uy, uz, (double*)f);
+    hipLaunchKernelGGL((pack3_kernel<float, true>), grid_rows3(g), dim3(256), 0, s, g, ph, q0, m,
+                       const_cast<double*>(dense), (float*)f);
   return hipGetLastError();
 }
 
-hipError_t launch_pack3(const Geometry3& g, const double* dense, int q0, int m, void* f,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(pack3_kernel<true>, grid_rows3(g), dim3(256), 0, s, g, q0, m,
-                     const_cast<double*>(dense), (double*)f);
+hipError_t launch_unpack3(int storage, const Geometry3& g, const Physics3& ph, const void* f,
+                          int q0, int m, double* dense, hipStream_t s) {
+  if (storage == FP64)
+    hipLaunchKernelGGL((pack3_kernel<double, false>), grid_rows3(g), dim3(256), 0, s, g, ph, q0, m,
+                       dense, const_cast<double*>((const double*)f));
+  else
+    hipLaunchKernelGGL((pack3_kernel<float, false>), grid_rows3(g), dim3(256), 0, s, g, ph, q0, m,
+                       dense, const_cast<float*>((const float*)f));
   return hipGetLastError();
 }
 
-hipError_t launch_unpack3(const Geometry3& g, const void* f, int q0, int m, double* dense,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(pack3_kernel<false>, grid_rows3(g), dim3(256), 0, s, g, q0, m, dense,
-                     const_cast<double*>((const double*)f));
+hipError_t launch_reshift3(int storage, const Geometry3& g, const Physics3& delta, void* f,
+                           hipStream_t s) {
+  if (storage == FP64)
+    hipLaunchKernelGGL(reshift3_kernel<double>, grid_rows3(g), dim3(256), 0, s, g, delta,
+                       (double*)f);
+  else
+    hipLaunchKernelGGL(reshift3_kernel<float>, grid_rows3(g), dim3(256), 0, s, g, delta,
+                       (float*)f);
   return hipGetLastError();
 }
 
-Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth) {
+Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth, int target) {
   Tiling3 t{};
   t.ty = ty;
   t.depth = depth;
   t.tiles_x = (g.nx + M3X - 1) / M3X;
   t.tiles_y = (g.ny + ty - 1) / ty;
   if (zc <= 0) {
-    // about 1024 blocks (four per CU), chunks of at least 16 planes
+    // about `target` blocks, chunks of at least 16 planes
     const long long per = (long long)t.tiles_x * t.tiles_y;
-    long long ch = (1024 + per - 1) / per;
+    long long ch = (target + per - 1) / per;
     ch = std::max(1LL, std::min(ch, (long long)(g.nz + 15) / 16));
     zc = (int)((g.nz + ch - 1) / ch);
   }
@@ -595,57 +673,70 @@ long long blocks_of(const Tiling3& t) { return (long long)t.tiles_x * t.tiles_y 
 
 namespace {
 
-template <int SCHEME, int TY, int D>
-void launch_m3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const double* in,
-               double* out, long long nb, hipStream_t s) {
-  hipLaunchKernelGGL((march3<SCHEME, TY, D>), dim3((unsigned)nb), dim3(M3X * TY), 0, s, g, ph, t,
-                     in, out);
+template <typename T, int SCHEME, int TY, int D>
+void launch_m3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const T* in, T* out,
+               long long nb, hipStream_t s) {
+  hipLaunchKernelGGL((march3<T, SCHEME, TY, D>), dim3((unsigned)nb), dim3(M3X * TY), 0, s, g, ph,
+                     t, in, out);
 }
 
-template <int SCHEME>
-hipError_t launch_march3(const Geometry3& g, const Physics3& ph, const Tiling3& t,
-                         const double* in, double* out, hipStream_t s) {
+template <typename T, int SCHEME>
+hipError_t launch_march3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const T* in,
+                         T* out, hipStream_t s) {
   const long long nb = blocks_of(t);
   if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
   if (t.ty == 8 && t.depth == 1)
-    launch_m3<SCHEME, 8, 0>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 8, 0>(g, ph, t, in, out, nb, s);
   else if (t.ty == 8 && t.depth == 2)
-    launch_m3<SCHEME, 8, 1>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 8, 1>(g, ph, t, in, out, nb, s);
   else if (t.ty == 8 && t.depth == 3)
-    launch_m3<SCHEME, 8, 2>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 8, 2>(g, ph, t, in, out, nb, s);
   else if (t.ty == 16 && t.depth == 1)
-    launch_m3<SCHEME, 16, 0>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 16, 0>(g, ph, t, in, out, nb, s);
   else if (t.ty == 16 && t.depth == 2)
-    launch_m3<SCHEME, 16, 1>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 16, 1>(g, ph, t, in, out, nb, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_step3(int scheme, const Geometry3& g, const Physics3& ph, const Tiling3& t,
-                        const void* fin, void* fout, hipStream_t s) {
-  if (g.slab * (long long)sizeof(double) > 0xffffffffLL) return hipErrorInvalidValue;
-  const auto* in = (const double*)fin;
-  auto* out = (double*)fout;
-  return scheme == STANDARD ? launch_march3<STANDARD>(g, ph, t, in, out, s)
-                            : launch_march3<WELL_BALANCED>(g, ph, t, in, out, s);
-}
-
-hipError_t launch_observe3(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
-                           double* rho, double* mu, const ObserveOut3& o, hipStream_t s) {
-  const auto* in = (const Global<double>*)(const double*)f;
-  hipLaunchKernelGGL(density3, grid_rows3(g), dim3(256), 0, s, g, in, rho);
-  hipLaunchKernelGGL(potential3, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
+template <typename T>
+hipError_t launch_observe3_t(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
+                             double* rho, double* mu, const ObserveOut3& o, hipStream_t s) {
+  const auto* in = (const Global<T>*)(const T*)f;
+  hipLaunchKernelGGL(density3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, in, rho);
+  hipLaunchKernelGGL(potential3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
   const dim3 gc((g.nx + T3X - 1) / T3X, (g.ny + T3Y - 1) / T3Y, (g.nz + T3Z - 1) / T3Z);
   if (scheme == STANDARD)
-    hipLaunchKernelGGL(observe3_kernel<STANDARD>, gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
+    hipLaunchKernelGGL((observe3_kernel<T, STANDARD>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
-    hipLaunchKernelGGL(observe3_kernel<WELL_BALANCED>, gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
+    hipLaunchKernelGGL((observe3_kernel<T, WELL_BALANCED>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                        const Tiling3& t, const void* fin, void* fout, hipStream_t s) {
+  const long long elem = storage == FP64 ? 8 : 4;
+  if (g.slab * elem > 0xffffffffLL) return hipErrorInvalidValue;
+  if (storage == FP64)
+    return scheme == STANDARD
+               ? launch_march3<double, STANDARD>(g, ph, t, (const double*)fin, (double*)fout, s)
+               : launch_march3<double, WELL_BALANCED>(g, ph, t, (const double*)fin, (double*)fout,
+                                                      s);
+  return scheme == STANDARD
+             ? launch_march3<float, STANDARD>(g, ph, t, (const float*)fin, (float*)fout, s)
+             : launch_march3<float, WELL_BALANCED>(g, ph, t, (const float*)fin, (float*)fout, s);
+}
+
+hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
+                           const void* f, double* rho, double* mu, const ObserveOut3& o,
+                           hipStream_t s) {
+  return storage == FP64 ? launch_observe3_t<double>(scheme, g, ph, f, rho, mu, o, s)
+                         : launch_observe3_t<float>(scheme, g, ph, f, rho, mu, o, s);
 }
 
 }  // namespace lbmk

@@ -48,9 +48,11 @@ def main():
         n, ph = args.d3, I.PHYS3
         rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
                                  I.equilibrium_width(ph), 1e-3, seed=13)
-        s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n)
+        s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n,
+                       precision=args.precision)
         s.init(rho, scheme=args.scheme)
-        print("profile_step: D3Q19 %d^3 %s" % (n, args.scheme), flush=True)
+        print("profile_step: D3Q19 %d^3 %s %s tile=%s" % (n, args.precision, args.scheme,
+                                                          s.get_tile()), flush=True)
         s.step(args.steps, args.scheme)
         torch.cuda.synchronize()
         print("profile_step: %d steps done" % args.steps, flush=True)

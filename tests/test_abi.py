@@ -39,7 +39,6 @@ def test_workspace_bytes_rejects_bad_params(lib):
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=2),
                 P(4, 70000, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=-1),
-                P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=8, precision="fp32s"),
                 P(4, 4, 1.0, 0.1, 0.02, 1, 0.1, nz=8, force_stencil=1),
                 P(2048, 2048, 1.0, 0.1, 0.02, 1, 0.1, nz=1024),
                 # a z-plane of 19 * 4096 * 8192 * 8 bytes is over 4 GiB
@@ -52,6 +51,10 @@ def test_workspace_bytes_rejects_bad_params(lib):
     p3 = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, nz=40)
     n3 = lib.lbm_workspace_bytes(ctypes.byref(p3))
     assert 2 * 19 * 64 * 48 * 40 * 8 + 5 * 64 * 48 * 40 * 8 <= n3 < 1.05 * (2 * 19 + 5) * 64 * 48 * 40 * 8
+    # 3-D lattices in FP32-shifted storage (half the bytes of FP64)
+    p3f = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, nz=40, precision="fp32s")
+    n3f = lib.lbm_workspace_bytes(ctypes.byref(p3f))
+    assert 2 * 19 * 64 * 48 * 40 * 4 + 5 * 64 * 48 * 40 * 8 <= n3f < n3
     # the fourth-order force stencil is accepted in FP64 and FP32-shifted
     for prec in ("fp64", "fp32s"):
         good = P(64, 48, 1.0, 0.1, 0.02, 1, 0.1, force_stencil=1, precision=prec)

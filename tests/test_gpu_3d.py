@@ -22,8 +22,9 @@ def lbm():
     return L
 
 
-def solver(L, nx, ny, nz, ph):
-    return L.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, nz=nz)
+def solver(L, nx, ny, nz, ph, precision="fp64"):
+    return L.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, nz=nz,
+                    precision=precision)
 
 
 def to_oracle(f):
@@ -120,22 +121,24 @@ def test_wb_flat_interface_fixed_point_3d(lbm, axis):
     assert ob["max_u"] < 1e-14
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
 @pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
-def test_tilings_bit_identical_3d(orc, lbm, scheme):
+def test_tilings_bit_identical_3d(orc, lbm, scheme, prec):
     """Every tiling of the fused 3-D step gives the same populations bit for
     bit: tiles of 32 x 8 or 32 x 16 nodes (ragged in x and y), chunks of 1 to
-    13 planes (odd chunks march towards -z), 1 to 3 planes in flight, and the
-    oracle agrees."""
+    13 planes (odd chunks march towards -z), 1 to 3 planes in flight, in FP64
+    and FP32-shifted storage, and the oracle agrees (to 1e-11, or to the FP32
+    bound of the main step's FP32 form)."""
     ph = I.PAPER_PHYS
     nx, ny, nz, steps = 37, 19, 13, 60
-    print("tilings 3-D", nx, ny, nz, scheme, flush=True)
+    print("tilings 3-D", nx, ny, nz, scheme, prec, flush=True)
     rho0 = I.droplet3_density(nx, ny, nz, ph, 5.0, 4.0, 1e-2, seed=5)
     p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
     fo = orc.step3(scheme, p, orc.init3(scheme, p, rho0), steps)
     ref = None
     for block, rows, depth in [(256, 0, 2), (256, 1, 1), (256, 2, 3), (256, 5, 2), (512, 3, 1),
                                (512, 4, 2), (512, 13, 1), (256, 13, 3)]:
-        s = solver(lbm, nx, ny, nz, ph)
+        s = solver(lbm, nx, ny, nz, ph, prec)
         s.set_tile(block, rows, depth)
         b, r, d = s.get_tile()
         assert b == block and d == depth and (rows == 0 or r == rows)
@@ -145,7 +148,7 @@ def test_tilings_bit_identical_3d(orc, lbm, scheme):
         s.close()
         if ref is None:
             ref = f
-            assert np.abs(to_oracle(f) - fo).max() <= TOL
+            assert np.abs(to_oracle(f) - fo).max() <= (TOL if prec == "fp64" else 5e-5)
         else:
             assert np.array_equal(f, ref), (block, rows, depth)
 
@@ -190,3 +193,47 @@ def test_full_grid_sampled_3d(orc, lbm):
         want = orc.step3("well_balanced", p, crop, 1)[M:-M, M:-M, M:-M]
         got = to_oracle(g[:, zs[M:-M]][:, :, ys[M:-M]][:, :, :, xs[M:-M]])
         assert np.abs(got - want).max() <= 1e-12, (z0, y0, x0)
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+def test_fp32_3d_against_oracle(orc, lbm, scheme):
+    """The 3-D step in FP32-shifted storage against the FP64 oracle after 300
+    steps, with the main step's FP32 bounds (single-precision rounding
+    accumulated over the steps: rho, f < 5e-5, u < 1e-5); mass to 1e-5."""
+    ph = I.PAPER_PHYS
+    nx, ny, nz, steps = 40, 24, 16, 300
+    rho0 = I.droplet3_density(nx, ny, nz, ph, 0.3 * min(nx, ny, nz) + 1.0, 4.0, 1e-2, seed=7)
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    fo = orc.step3(scheme, p, orc.init3(scheme, p, rho0), steps)
+    m = orc.macro3(scheme, p, fo)
+    s = solver(lbm, nx, ny, nz, ph, "fp32s")
+    s.init(rho0, scheme=scheme)
+    s.step(steps, scheme)
+    f32 = to_oracle(s.get_populations())
+    ob = s.observe()
+    s.close()
+    e_rho = np.abs(ob["rho"] - m["rho"]).max()
+    e_u = max(np.abs(ob[k] - m[k]).max() for k in ("ux", "uy", "uz"))
+    e_f = np.abs(f32 - fo).max()
+    print("3-D fp32 vs oracle, %s, %d steps: rho %.3e  u %.3e  f %.3e"
+          % (scheme, steps, e_rho, e_u, e_f))
+    assert e_rho < 5e-5 and e_u < 1e-5 and e_f < 5e-5
+    assert abs(ob["mass"] - orc.observe3(scheme, p, fo)["mass"]) < 1e-5 * ob["mass"]
+
+
+def test_fp32_3d_scheme_switch_keeps_populations(lbm):
+    """Stepping with the other scheme converts the FP32 storage shift (the WB
+    shift holds rho_ref on f_0, the standard one w_i rho_ref on every
+    population): the populations are kept to FP32 rounding."""
+    ph = I.PAPER_PHYS
+    rho0 = I.droplet3_density(20, 16, 12, ph, 5.0, 4.0, 1e-2, seed=3)
+    s = solver(lbm, 20, 16, 12, ph, "fp32s")
+    s.init(rho0, scheme="well_balanced")
+    s.step(30, "well_balanced")
+    a = s.get_populations()
+    s.step(0, "standard")
+    b = s.get_populations()
+    s.step(0, "well_balanced")
+    c = s.get_populations()
+    s.close()
+    assert np.abs(b - a).max() <= 1.2e-7 and np.abs(c - a).max() <= 1.2e-7
