@@ -201,13 +201,15 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
   int hsx = 0, hcy = 0;
   long long hplane = 0;
   if (hl) {
-    const int cxq[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    const int cyq[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    // c_x, c_y of velocity hq (paper numbering), without an indexed array
+    // (which would live in scratch memory)
+    const int cxq = (hq == 1 || hq == 5 || hq == 8) ? 1 : ((hq == 3 || hq == 6 || hq == 7) ? -1 : 0);
+    const int cyq = (hq == 2 || hq == 5 || hq == 6) ? 1 : ((hq == 4 || hq == 7 || hq == 8) ? -1 : 0);
     int hc = hcol < 2 ? x0 - 2 + hcol : x0 + BW + hcol - 2;
     hc = ((hc % g.nx) + g.nx) % g.nx;
-    hsx = hc - cxq[hq];
+    hsx = hc - cxq;
     hsx = hsx < 0 ? hsx + g.nx : (hsx >= g.nx ? hsx - g.nx : hsx);
-    hcy = cyq[hq];
+    hcy = cyq;
     hplane = (long long)hq * g.plane;
   }
   auto load_halo = [&](int k, R& dst) {
