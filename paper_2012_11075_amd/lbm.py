@@ -126,8 +126,8 @@ def _scheme(s) -> int:
 def make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
                 rho_ref=None, shift_all=False, force_stencil=0, nz=0) -> Params:
     """force_stencil: 0 the central gradients of Sec. II in the force, 1 the
-    fourth-order ones (FP64 single lattices only).  nz > 1: a 3-D D3Q19
-    lattice (FP64 single lattices)."""
+    fourth-order ones (single lattices only).  nz > 1: a 3-D D3Q19 lattice
+    (single lattices).  Both run in FP64 or FP32-shifted storage."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     if rho_ref is None:
         rho_ref = 0.5 * (rho_l + rho_v)

@@ -31,7 +31,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--force-stencil", type=int, default=0,
-                    help="1: the fourth-order force-stencil variant (FP64, three kernels per step)")
+                    help="1: the fourth-order force-stencil variant (one fused kernel per step)")
     ap.add_argument("--d3", type=int, default=0,
                     help="profile the 3-D (D3Q19) step on an N^3 droplet instead")
     ap.add_argument("--batch", type=int, default=0,
