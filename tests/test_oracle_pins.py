@@ -123,6 +123,36 @@ def test_stencils_exact_on_quadratics(orc):
     np.testing.assert_allclose(lap[s], 0.002 - 0.003, atol=1e-13)
 
 
+@pytest.mark.parametrize("ny,nx,dim", [(4, 6, 4), (6, 5, 2), (5, 3, 1), (3, 7, 1)])
+def test_gradient_null_space(orc, ny, nx, dim):
+    """The ICS gradient (Sec. II) on a periodic lattice is zero exactly on
+    fields made of the constant and the alternating modes the lattice
+    supports: (-1)^x needs even nx, (-1)^y even ny.  So a vanishing
+    gradient fixes a field (mu at the WB steady state, Sec. III) only up to
+    those modes, and only to a constant when both sides are odd.  Checked
+    by building the operator column by column on tiny lattices."""
+    cols = []
+    for k in range(ny * nx):
+        e = np.zeros(ny * nx)
+        e[k] = 1.0
+        gx, gy = orc.gradient(e.reshape(ny, nx))
+        cols.append(np.concatenate([gx.ravel(), gy.ravel()]))
+    sv = np.linalg.svd(np.array(cols).T, compute_uv=False)
+    assert int(np.sum(sv < 1e-12)) == dim
+    y, x = np.mgrid[0:ny, 0:nx]
+    modes = [np.ones((ny, nx))]
+    if nx % 2 == 0:
+        modes.append((-1.0) ** x)
+    if ny % 2 == 0:
+        modes.append((-1.0) ** y)
+    if nx % 2 == 0 and ny % 2 == 0:
+        modes.append((-1.0) ** (x + y))
+    assert len(modes) == dim
+    for mode in modes:
+        gx, gy = orc.gradient(mode)
+        assert np.abs(gx).max() < 1e-15 and np.abs(gy).max() < 1e-15
+
+
 def test_fourth_order_gradient_exact_on_cubics(orc):
     """The force-stencil variant's gradient (the higher-order discretisation
     discussed after Eq. 23) is exact for cubic fields away from the periodic
@@ -418,20 +448,23 @@ def _discrete_flat_equilibrium(p, n, mass, guess):
     return z[:n], z[n]
 
 
+@pytest.mark.parametrize("axis", ["x", "y"])
 @pytest.mark.parametrize("phys", ["bj", "paper"])
-def test_wb_flat_interface_is_a_discrete_fixed_point(orc, phys):
+def test_wb_flat_interface_is_a_discrete_fixed_point(orc, phys, axis):
     """Sec. III (after Eq. 34): v = 0 with mu = const solves the WB discrete
     balance, so the discrete equilibrium of mu0 - kappa lap rho = const is an
     exact fixed point of the WB-LBE (to round-off), with the 1-D structure
     f_A = rho, f_B = f_C = 0 of Eqs. (30)-(32); the same density is NOT a
-    fixed point of the standard LBE (Sec. II)."""
+    fixed point of the standard LBE (Sec. II).  The paper's interface is
+    normal to y, the slab workload's normal to x: both are checked."""
     ph = I.BJ_PHYS if phys == "bj" else I.PAPER_PHYS
     p = params(orc, ph)
     n = 201
     W = orc.equilibrium_width(p)
     guess = I.tanh_slab(n, p.rho_l, p.rho_v, 50.5, 149.5, W)
     prof, mub = _discrete_flat_equilibrium(p, n, guess.sum(), guess)
-    rho = np.ascontiguousarray(np.broadcast_to(prof[None, :], (3, n)))
+    rho = np.broadcast_to(prof[None, :], (3, n))
+    rho = np.ascontiguousarray(rho if axis == "x" else rho.T)
     f = orc.init("well_balanced", p, rho)
     g = orc.step("well_balanced", p, f, 200)
     assert np.abs(g - f).max() < 1e-13
