@@ -8,6 +8,9 @@
  *
  *   - the standard LBE  : Sec. II, Eqs. (2)-(5) with the potential-form force
  *                         F = grad(cs2 rho) - rho grad(mu)          (Eq. 6)
+ *   - the standard LBE with the other forcing term the paper names after
+ *     Eq. (5): F_i = (c_i - u).F feq_i / (cs2 rho), same equilibrium and
+ *     force (scheme ORC_STANDARD_EQF)
  *   - the well-balanced : Sec. III, Eq. (2) with the equilibrium of Eq. (24),
  *     (WB) LBE            the force F = -rho grad(mu) of Eq. (25) and the
  *                         forcing term of Eq. (26)
@@ -72,7 +75,7 @@ static const double WT[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                              1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                              1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
-enum { ORC_STANDARD = 0, ORC_WELL_BALANCED = 1 };
+enum { ORC_STANDARD = 0, ORC_WELL_BALANCED = 1, ORC_STANDARD_EQF = 2 };
 
 typedef struct {
   double tau;   /* relaxation time, Eq. (2) */
@@ -122,13 +125,24 @@ void orc_feq(int scheme, const orc_params *p, double rho, double ux, double uy,
   for (int i = 0; i < Q; ++i) {
     double cu = CX[i] * ux + CY[i] * uy;
     double poly = cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2);
-    if (scheme == ORC_STANDARD) {
+    if (scheme != ORC_WELL_BALANCED) {
       feq[i] = WT[i] * rho * (1.0 + poly);
     } else if (i == 0) {
       feq[i] = rho - (1.0 - WT[0]) * p->rho0 - WT[0] * rho * uu / (2.0 * CS2);
     } else {
       feq[i] = WT[i] * (p->rho0 + rho * poly);
     }
+  }
+}
+
+/* Forcing term F_i of the standard LBE named after Eq. (5):
+ *   F_i = (c_i - u).F feq_i / (cs2 rho)
+ * with feq the standard equilibrium of Eq. (3) at (rho, u). */
+void orc_forcing_eq(const double *feq, double rho, double ux, double uy,
+                    double Fx, double Fy, double *Fi) {
+  for (int i = 0; i < Q; ++i) {
+    double cmuF = (CX[i] - ux) * Fx + (CY[i] - uy) * Fy;
+    Fi[i] = cmuF * feq[i] / (CS2 * rho);
   }
 }
 
@@ -251,7 +265,7 @@ void orc_macro(int scheme, const orc_params *p, int nx, int ny,
   for (size_t k = 0; k < n; ++k) {
     double fx = -rho[k] * gmx[k];
     double fy = -rho[k] * gmy[k];
-    if (scheme == ORC_STANDARD) {
+    if (scheme != ORC_WELL_BALANCED) {
       fx += CS2 * grx[k];
       fy += CS2 * gry[k];
     }
@@ -320,7 +334,10 @@ void orc_step(int scheme, const orc_params *p, int nx, int ny, double *f,
         size_t k = (size_t)y * nx + x;
         double feq[Q], Fi[Q];
         orc_feq(scheme, p, rho[k], ux[k], uy[k], feq);
-        orc_forcing(scheme, ux[k], uy[k], Fx[k], Fy[k], gr[k], gry[k], Fi);
+        if (scheme == ORC_STANDARD_EQF)
+          orc_forcing_eq(feq, rho[k], ux[k], uy[k], Fx[k], Fy[k], Fi);
+        else
+          orc_forcing(scheme, ux[k], uy[k], Fx[k], Fy[k], gr[k], gry[k], Fi);
         for (int i = 0; i < Q; ++i) {
           double fs = f[k * Q + i] - omega * (f[k * Q + i] - feq[i]) +
                       fpre * Fi[i];

@@ -31,7 +31,9 @@ LIB = os.path.join(BUILD_DIR, "liboracle.so")
 
 STANDARD = 0
 WELL_BALANCED = 1
-SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED}
+STANDARD_EQF = 2  # standard LBE with F_i = (c_i - u).F feq_i / (cs2 rho) (2-D only)
+SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED,
+           "standard_eq_forcing": STANDARD_EQF}
 
 # D2Q9 in the paper's numbering (Sec. II): used by diagnostics that regroup
 # populations, never by the step itself (which lives in C).
@@ -95,6 +97,7 @@ def _load():
             "orc_p0": (d, [P, d]),
             "orc_feq": (None, [i, P, d, d, d, _D]),
             "orc_forcing": (None, [i, d, d, d, d, d, d, _D]),
+            "orc_forcing_eq": (None, [_D, d, d, d, d, d, _D]),
             "orc_gradient": (None, [i, i, _D, _D, _D]),
             "orc_gradient4": (None, [i, i, _D, _D, _D]),
             "orc_laplacian": (None, [i, i, _D, _D]),
@@ -133,6 +136,13 @@ def _scheme(s) -> int:
     return SCHEMES[s] if isinstance(s, str) else int(s)
 
 
+def _scheme3(s) -> int:
+    k = _scheme(s)
+    if k not in (STANDARD, WELL_BALANCED):
+        raise ValueError("the 3-D oracle has the standard and well-balanced schemes only")
+    return k
+
+
 def set_threads(n: int) -> None:
     _load().orc_set_threads(int(n))
 
@@ -165,9 +175,22 @@ def feq(scheme, p: Params, rho: float, ux: float, uy: float) -> np.ndarray:
 
 
 def forcing(scheme, ux, uy, Fx, Fy, grx=0.0, gry=0.0) -> np.ndarray:
-    """Forcing term: Eq. (5) standard, Eq. (26) well-balanced."""
+    """Forcing term: Eq. (5) standard, Eq. (26) well-balanced (the
+    equilibrium-proportional form is ``forcing_eq``)."""
+    k = _scheme(scheme)
+    if k not in (STANDARD, WELL_BALANCED):
+        raise ValueError("forcing(): use forcing_eq for the standard_eq_forcing scheme")
     out = np.zeros(9)
-    _load().orc_forcing(_scheme(scheme), ux, uy, Fx, Fy, grx, gry, _ptr(out))
+    _load().orc_forcing(k, ux, uy, Fx, Fy, grx, gry, _ptr(out))
+    return out
+
+
+def forcing_eq(p: Params, rho, ux, uy, Fx, Fy) -> np.ndarray:
+    """The other forcing term of the standard LBE named after Eq. (5):
+    F_i = (c_i - u).F feq_i / (cs2 rho), feq of Eq. (3)."""
+    fe = feq(STANDARD, p, rho, ux, uy)
+    out = np.zeros(9)
+    _load().orc_forcing_eq(_ptr(fe), rho, ux, uy, Fx, Fy, _ptr(out))
     return out
 
 
@@ -298,14 +321,14 @@ C3 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1
 def feq3(scheme, p: Params, rho, ux, uy, uz) -> np.ndarray:
     """D3Q19 equilibrium: Eq. (3) standard, Eq. (24) well-balanced."""
     out = np.zeros(19)
-    _load().orc3_feq(_scheme(scheme), ctypes.byref(p.c()), rho, ux, uy, uz, _ptr(out))
+    _load().orc3_feq(_scheme3(scheme), ctypes.byref(p.c()), rho, ux, uy, uz, _ptr(out))
     return out
 
 
 def forcing3(scheme, u, F, gr=(0.0, 0.0, 0.0)) -> np.ndarray:
     """D3Q19 forcing term: Eq. (5) standard, Eq. (26) with D = 3."""
     out = np.zeros(19)
-    _load().orc3_forcing(_scheme(scheme), *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
+    _load().orc3_forcing(_scheme3(scheme), *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
     return out
 
 
@@ -330,7 +353,7 @@ def macro3(scheme, p: Params, f: np.ndarray) -> dict:
     nz, ny, nx, _ = f.shape
     names = ["rho", "ux", "uy", "uz", "mu", "Fx", "Fy", "Fz", "grx", "gry", "grz"]
     out = {k: np.empty((nz, ny, nx)) for k in names}
-    _load().orc3_macro(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f),
+    _load().orc3_macro(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f),
                        *[_ptr(out[k]) for k in names])
     return out
 
@@ -340,7 +363,7 @@ def init3(scheme, p: Params, rho: np.ndarray, u=None) -> np.ndarray:
     nz, ny, nx = rho.shape
     comps = [None, None, None] if u is None else [np.ascontiguousarray(a, dtype=np.float64) for a in u]
     f = np.empty((nz, ny, nx, 19))
-    _load().orc3_init(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(rho),
+    _load().orc3_init(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(rho),
                       *[_ptr(a) for a in comps], _ptr(f))
     return f
 
@@ -348,7 +371,7 @@ def init3(scheme, p: Params, rho: np.ndarray, u=None) -> np.ndarray:
 def step3(scheme, p: Params, f: np.ndarray, n: int = 1) -> np.ndarray:
     g = np.array(f, dtype=np.float64, order="C", copy=True)
     nz, ny, nx, _ = g.shape
-    _load().orc3_step(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(g), int(n))
+    _load().orc3_step(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(g), int(n))
     return g
 
 
@@ -356,5 +379,5 @@ def observe3(scheme, p: Params, f: np.ndarray) -> dict:
     f = np.ascontiguousarray(f, dtype=np.float64)
     nz, ny, nx, _ = f.shape
     out = np.zeros(4)
-    _load().orc3_observe(_scheme(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
+    _load().orc3_observe(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
     return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3])}

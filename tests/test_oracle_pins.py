@@ -18,6 +18,9 @@ CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 C = np.stack([CX, CY], axis=1).astype(float)
 CS2 = 1.0 / 3.0
 SCHEMES = ["standard", "well_balanced"]
+# Step-level pins also run the standard LBE with the equilibrium-proportional
+# forcing term named after Eq. (5).
+STEP_SCHEMES = SCHEMES + ["standard_eq_forcing"]
 
 
 def params(orc, ph, **kw):
@@ -69,6 +72,44 @@ def test_forcing_moments(orc, scheme):
         assert abs(Fi.sum()) < 1e-15
         np.testing.assert_allclose(C.T @ Fi, F, atol=1e-15)
         np.testing.assert_allclose(m2, want, atol=1e-15)
+
+
+def test_eq_forcing_moments(orc):
+    """The forcing term named after Eq. (5), F_i = (c_i - u).F feq_i/(cs2 rho):
+    from the moments of the Eq. (3) equilibrium (sum feq = rho, sum c feq =
+    rho u, sum cc feq = cs2 rho I + rho uu, sum ccc feq = cs2 rho (u d)_sym)
+    its moments are sum F_i = 0, sum c F_i = F and
+    sum cc F_i = uF + Fu - uu (u.F)/cs2.  So it agrees with Eq. (5) in the
+    first two and differs at third order in the velocity scale, as the paper
+    says; F_i does not depend on rho."""
+    rng = np.random.default_rng(11)
+    p = orc.Params(0.8, 0.1, 0.02, 1.0, 0.1)
+    for _ in range(50):
+        rho = rng.uniform(0.05, 2.0)
+        u = rng.uniform(-0.2, 0.2, 2)
+        F = rng.uniform(-0.1, 0.1, 2)
+        Fi = orc.forcing_eq(p, rho, u[0], u[1], F[0], F[1])
+        m2 = np.einsum("i,ia,ib->ab", Fi, C, C)
+        want = np.outer(u, F) + np.outer(F, u) - np.outer(u, u) * np.dot(u, F) / CS2
+        assert abs(Fi.sum()) < 1e-15
+        np.testing.assert_allclose(C.T @ Fi, F, atol=1e-15)
+        np.testing.assert_allclose(m2, want, atol=1e-15)
+        np.testing.assert_allclose(orc.forcing_eq(p, 3.0 * rho, u[0], u[1], F[0], F[1]), Fi,
+                                   atol=1e-16)
+
+
+def test_eq_forcing_departs_from_eq5_at_second_order_in_u(orc):
+    """At u = 0 both forcing terms are w_i c.F/cs2; their difference grows as
+    |u|^2 |F| (halving u quarters it)."""
+    p = orc.Params(0.8, 0.1, 0.02, 1.0, 0.1)
+    F = (0.02, -0.013)
+    u = np.array([0.08, 0.05])
+    np.testing.assert_allclose(orc.forcing_eq(p, 0.6, 0.0, 0.0, *F),
+                               orc.forcing("standard", 0.0, 0.0, *F), atol=1e-17)
+    d = [np.abs(orc.forcing_eq(p, 0.6, *(u * h), *F) - orc.forcing("standard", *(u * h), *F)).max()
+         for h in (1.0, 0.5, 0.25)]
+    assert d[0] > 1e-6
+    assert 3.6 < d[0] / d[1] < 4.4 and 3.8 < d[1] / d[2] < 4.2
 
 
 def test_double_well_thermodynamics(orc):
@@ -226,7 +267,7 @@ def test_net_force_structure_at_equilibrium(orc):
 
 
 # ---------------------------------------------------------------- dynamics
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_mass_conservation(orc, scheme):
     """sum_i feq_i = rho and sum_i F_i = 0 with streaming a permutation: the
     total mass is invariant (Eqs. 2, 4, 27, 28)."""
@@ -239,7 +280,7 @@ def test_mass_conservation(orc, scheme):
     assert abs(m1 - m0) / m0 < 1e-13
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_momentum_budget(orc, scheme):
     """Half-force velocity of Eq. (4) with the forcing of Eq. (5)/(26): the
     post-collision momentum of a node is rho u + F/2, so one step changes the
@@ -256,7 +297,7 @@ def test_momentum_budget(orc, scheme):
     np.testing.assert_allclose(P1 - P0, dF, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_uniform_state_is_fixed(orc, scheme):
     """A uniform density at rest is a fixed point of both schemes (all
     gradients vanish, feq = f).  For WB it is exact: f_0 = rho carries the
@@ -296,7 +337,7 @@ def test_wb_rho0_only_offsets_the_trajectory(orc, rho0):
     assert np.abs(fa - off - f0).max() < 1e-12
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_translation_equivariance(orc, scheme):
     """The step commutes with lattice translations on the torus, bit for bit."""
     pr = I.with_size(I.PAPER_DROPLET, 40, 36)
@@ -313,7 +354,7 @@ MIRROR_X = [0, 3, 2, 1, 4, 6, 5, 8, 7]
 ROT90 = [0, 2, 3, 4, 1, 6, 7, 8, 5]  # c_i rotated by +90 degrees is c_ROT90[i]
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_mirror_and_rotation_symmetry(orc, scheme):
     """D2Q9 and both stencils are D4-symmetric, so mirrored or rotated initial
     data give mirrored or rotated states (up to summation order)."""
@@ -340,7 +381,7 @@ def test_mirror_and_rotation_symmetry(orc, scheme):
     np.testing.assert_allclose(g, f_r, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_symmetric_state_stays_symmetric(orc, scheme):
     """A noise-free slab symmetric about its centre stays mirror symmetric."""
     pr = I.with_size(I.FLAT_200x4, 60, 3, noise=0.0)
@@ -374,7 +415,7 @@ def test_bump_is_carried_downstream(orc):
     assert abs(yc - (30 + n * U[1])) < 0.05
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_shear_wave_is_advected_by_mean_flow(orc, scheme):
     """Streaming direction for both schemes: a shear wave u_x = A sin(k y)
     riding on a uniform u_y = V is carried to +y at speed V (Galilean
@@ -393,7 +434,7 @@ def test_shear_wave_is_advected_by_mean_flow(orc, scheme):
     assert abs(shift - n * V) < 0.3, shift
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_shear_wave_viscosity(orc, scheme):
     """nu = cs2 (tau - 1/2) (Sec. II below Eq. 2; same shear viscosity for the
     WB scheme, Eq. 29): a shear wave u_x = U sin(k y) decays as exp(-nu k^2 t)."""
@@ -576,7 +617,7 @@ def paper_flat_steady(orc):
     p = params(orc, pr.physics)
     rho = I.initial_density(pr)
     out = {}
-    for scheme in SCHEMES:
+    for scheme in STEP_SCHEMES:
         f = orc.step(scheme, p, orc.init(scheme, p, rho), 30_000)
         out[scheme] = f
     return p, out
@@ -595,6 +636,23 @@ def test_paper_flat_standard_magnitudes(orc, paper_flat_steady):
     assert 1e-13 < obs["kinetic_energy"] < 1e-10
     assert 1e-9 < obs["max_u"] < 1e-6
     assert 3e-4 < mu.max() - mu.min() < 3e-3
+
+
+def test_paper_flat_eq_forcing_keeps_spurious_velocity(orc, paper_flat_steady):
+    """Sec. II: the forcing term named after Eq. (5) changes F_i only at
+    second order in u, while the spurious velocity comes from the net force
+    of Eqs. (21)-(23), which neither form touches: the steady state of the
+    standard LBE with either forcing term has the same kinetic energy, max|u|
+    and spread of mu (to 1%)."""
+    p, st = paper_flat_steady
+    a = orc.observe("standard", p, st["standard"])
+    b = orc.observe("standard_eq_forcing", p, st["standard_eq_forcing"])
+    _, _, _, mua = orc.fields("standard", p, st["standard"])
+    _, _, _, mub = orc.fields("standard_eq_forcing", p, st["standard_eq_forcing"])
+    assert abs(b["max_u"] / a["max_u"] - 1) < 0.01
+    assert abs(b["kinetic_energy"] / a["kinetic_energy"] - 1) < 0.01
+    assert abs((mub.max() - mub.min()) / (mua.max() - mua.min()) - 1) < 0.01
+    assert 0 < np.abs(st["standard_eq_forcing"] - st["standard"]).max() < 1e-5
 
 
 def test_paper_flat_standard_discrete_balance(orc, paper_flat_steady):
