@@ -263,14 +263,17 @@ def finite_state(steps, warmup):
 STENCIL4_BYTES = 144   # FP64 bytes per node of the variant step: 9 populations read and written
 
 
-def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="fp64"):
-    """The force-stencil variant (fourth-order gradients in the force): one
-    fused pass per step, 9 populations read and written = 144 (FP64) or 72
-    (FP32-shifted) algorithmic bytes per node.  `tile` (block, rows, depth)
-    overrides the default."""
+def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="fp64",
+                  force_stencil=1):
+    """A variant of the 2-D step: by default the force-stencil variant
+    (fourth-order gradients in the force); with force_stencil=0 the main
+    step, e.g. under the standard_eq_forcing scheme.  One fused pass per
+    step, 9 populations read and written = 144 (FP64) or 72 (FP32-shifted)
+    algorithmic bytes per node.  `tile` (block, rows, depth) overrides the
+    default."""
     import torch
     from paper_2012_11075_amd import lbm
-    s = lbm.Solver.for_problem(prob, force_stencil=1, precision=precision)
+    s = lbm.Solver.for_problem(prob, force_stencil=force_stencil, precision=precision)
     if tile:
         s.set_tile(*tile)
     s.init(prob.rho(), scheme=scheme)
@@ -298,8 +301,9 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="
             "bytes_per_update": bpu,
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "workload": "%s, %s scheme, fourth-order force stencil, %s, %d steps"
-                        % (prob.name, scheme, precision.upper(), steps)}
+            "workload": "%s, %s scheme, %s force stencil, %s, %d steps"
+                        % (prob.name, scheme, "fourth-order" if force_stencil else "central",
+                           precision.upper(), steps)}
 
 
 D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
@@ -403,6 +407,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-finite", action="store_true")
     ap.add_argument("--no-stencil4", action="store_true")
+    ap.add_argument("--no-eq-forcing", action="store_true")
     ap.add_argument("--no-d3", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -474,6 +479,21 @@ def main():
             I.DROPLET_4096_FINITE, 200, 5, "well_balanced",
             tile=tune.stencil4_tile(prob.nx, prob.ny, "fp32s"), precision="fp32s")
         progress("force-stencil variant %.4f ms/step" % out["force_stencil4"]["ms_per_step"])
+    if not args.no_eq_forcing:
+        # the standard LBE with the forcing term named after Eq. (5), on the
+        # 4096^2 droplet with the Sec. IV.B constants (the standard LBE goes
+        # to negative densities within a few steps at density ratio 100)
+        pd = I.PAPER_DROPLET_4096
+        out["standard_eq_forcing"] = time_stencil4(
+            pd, 100, 5, "standard_eq_forcing", tile=tune.bench_tile(pd.nx, pd.ny, "fp64"),
+            force_stencil=0)
+        out["standard_eq_forcing"]["fp32_shifted"] = time_stencil4(
+            pd, 100, 5, "standard_eq_forcing", tile=tune.bench_tile(pd.nx, pd.ny, "fp32s"),
+            precision="fp32s", force_stencil=0)
+        out["standard_eq_forcing"]["eq5_same_grid"] = time_stencil4(
+            pd, 100, 5, "standard", tile=tune.bench_tile(pd.nx, pd.ny, "fp64"), force_stencil=0)
+        progress("standard LBE, eq-proportional forcing %.4f ms/step"
+                 % out["standard_eq_forcing"]["ms_per_step"])
     if not args.no_d3:
         out["d3q19"] = time_d3q19(100, 5)
         out["d3q19"]["fp32_shifted"] = time_d3q19(100, 5, precision="fp32s")

@@ -60,7 +60,18 @@ typedef enum {
   LBM_EBUSY = -6        /* no free batch slot */
 } lbm_status;
 
-typedef enum { LBM_STANDARD = 0, LBM_WELL_BALANCED = 1 } lbm_scheme;
+/* LBM_STANDARD: the standard LBE of Sec. II (equilibrium Eq. 3, force Eq. 6,
+ * forcing term Eq. 5).  LBM_WELL_BALANCED: Sec. III (Eqs. 24-26).
+ * LBM_STANDARD_EQ_FORCING: the standard LBE with the other forcing term the
+ * paper names after Eq. (5), F_i = (c_i - u).F feq_i / (cs2 rho); same
+ * equilibrium, force, observe pass and FP32 shift as LBM_STANDARD.  2-D
+ * single lattices only, with either force stencil and either precision:
+ * 3-D contexts and lbm_batch_admit reject it with LBM_EINVAL. */
+typedef enum {
+  LBM_STANDARD = 0,
+  LBM_WELL_BALANCED = 1,
+  LBM_STANDARD_EQ_FORCING = 2
+} lbm_scheme;
 
 /* LBM_FP64: populations stored and updated in double precision.
  * LBM_FP32_SHIFTED: populations stored as float g_i = f_i - s_i and updated

@@ -114,10 +114,11 @@ Layout make_layout(const lbm_params& p) {
   return L;
 }
 
-// Equilibrium at rest feq_i(rho, 0) of a scheme (Eq. 3 / Eq. 24).
+// Equilibrium at rest feq_i(rho, 0) of a scheme (Eq. 3 for both standard
+// forms / Eq. 24).
 void feq_rest(const lbm_params& p, int scheme, double rho, double* f) {
   for (int i = 0; i < Q; ++i) {
-    if (scheme == LBM_STANDARD)
+    if (scheme != LBM_WELL_BALANCED)
       f[i] = W[i] * rho;
     else
       f[i] = (i == 0) ? rho - (1.0 - W[0]) * p.rho0 : W[i] * p.rho0;
@@ -160,7 +161,7 @@ double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)
 // The 3-D counterparts of feq_rest and shift_of.
 void feq3_rest(const lbm_params& p, int scheme, double rho, double* f) {
   for (int i = 0; i < lbmk::Q3; ++i) {
-    if (scheme == LBM_STANDARD)
+    if (scheme != LBM_WELL_BALANCED)
       f[i] = w3(i) * rho;
     else
       f[i] = (i == 0) ? rho - (1.0 - w3(0)) * p.rho0 : w3(i) * p.rho0;
@@ -230,7 +231,7 @@ struct lbm_ctx {
   int scheme = LBM_WELL_BALANCED;  // scheme the storage shift currently follows
   int64_t step = 0;
   int graph_steps = 0;
-  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [scheme][cur]
+  hipGraphExec_t graph[3][2] = {};  // [scheme][cur]
   std::string err;
 
   void* buf(int which) const { return ws + (which == 0 ? L.off_a : L.off_b); }
@@ -357,7 +358,17 @@ lbm_status convert_shift(lbm_ctx* c, int to_scheme) {
   return LBM_OK;
 }
 
-bool valid_scheme(int s) { return s == LBM_STANDARD || s == LBM_WELL_BALANCED; }
+bool valid_scheme(int s) {
+  return s == LBM_STANDARD || s == LBM_WELL_BALANCED || s == LBM_STANDARD_EQ_FORCING;
+}
+
+// nullptr if the context can run `scheme`, else the reason it cannot.
+const char* scheme_error(const lbm_ctx* c, int scheme) {
+  if (!valid_scheme(scheme)) return "unknown scheme";
+  if (scheme == LBM_STANDARD_EQ_FORCING && c->d3())
+    return "the equilibrium-proportional forcing term is implemented for 2-D lattices only";
+  return nullptr;
+}
 
 }  // namespace
 
@@ -408,7 +419,7 @@ lbm_status init_impl(lbm_ctx* c, const double* rho, const double* ux, const doub
                      const double* uz, int scheme) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!rho) return fail(c, LBM_EINVAL, "rho is NULL");
-  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  if (const char* why = scheme_error(c, scheme)) return fail(c, LBM_EINVAL, why);
   const bool d3 = c->d3();
   if (!d3 && uz) return fail(c, LBM_EINVAL, "uz is for 3-D lattices");
   if (!d3 && (ux == nullptr) != (uy == nullptr))
@@ -466,7 +477,7 @@ lbm_status lbm_init3d(lbm_ctx* c, const double* rho, const double* ux, const dou
 lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
-  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  if (const char* why = scheme_error(c, scheme)) return fail(c, LBM_EINVAL, why);
   if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_step before lbm_init");
   lbm_status st = convert_shift(c, scheme);
   if (st != LBM_OK) return st;
@@ -600,7 +611,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
 lbm_status lbm_set_populations(lbm_ctx* c, const double* f, lbm_scheme scheme, int64_t step) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!f) return fail(c, LBM_EINVAL, "f is NULL");
-  if (!valid_scheme(scheme)) return fail(c, LBM_EINVAL, "unknown scheme");
+  if (const char* why = scheme_error(c, scheme)) return fail(c, LBM_EINVAL, why);
   const long long n = c->nodes();
   const int nq = c->L.q;
   for (long long k = 0; k < (long long)nq * n; ++k)
@@ -1016,7 +1027,8 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
                            double tol, int64_t cap, int32_t* slot) {
   if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
   if (!slot || !rho) return bfail(b, LBM_EINVAL, "slot and rho must not be NULL");
-  if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
+  if (scheme != LBM_STANDARD && scheme != LBM_WELL_BALANCED)
+    return bfail(b, LBM_EINVAL, "batches run the standard (Eq. 5) and well-balanced schemes");
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
   if (p->force_stencil != 0) return bfail(b, LBM_EINVAL, "batches use the central force stencil");

@@ -46,7 +46,10 @@ struct ObserveOut {
   double* partials;  // 4 doubles per block: max|u|, mass, E, nonfinite flag
 };
 
-enum Scheme { STANDARD = 0, WELL_BALANCED = 1 };
+// STANDARD_EQF: the standard LBE (equilibrium Eq. 3, force Eq. 6) with the
+// forcing term F_i = (c_i - u).F feq_i / cs2 rho named after Eq. (5) in
+// place of Eq. (5); its observe and init passes are the standard ones.
+enum Scheme { STANDARD = 0, WELL_BALANCED = 1, STANDARD_EQF = 2 };
 
 // One lattice of a batched launch (lives in device memory).
 struct BatchSlot {

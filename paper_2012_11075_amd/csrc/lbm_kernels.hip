@@ -8,7 +8,9 @@
 //                      9-point Laplacian of the same family)
 //   force              Eq. (6) potential form (standard) / Eq. (25) (WB)
 //   equilibrium        Eq. (3) (standard) / Eq. (24) (WB)
-//   forcing term       Eq. (5) (standard) / Eq. (26) (WB)
+//   forcing term       Eq. (5) (standard) / Eq. (26) (WB); or, for the
+//                      standard LBE, (c_i - u).F feq_i / (cs2 rho), the
+//                      form named after Eq. (5) (STANDARD_EQF)
 //   collide + stream   Eq. (2): f*_i = f_i - (f_i - feq_i)/tau + (1 - 1/2tau) F_i,
 //                      f_i(x + c_i, t+1) = f*_i(x, t), periodic.
 //
@@ -78,6 +80,8 @@ __device__ __forceinline__ void velocity(const R (&f)[Q], R rho, R Fx, R Fy, R& 
 // Shifted equilibrium geq_i = feq_i(rho, u) - s_i and forcing term F_i.
 //   standard: feq_i = w_i rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)     (Eq. 3)
 //             F_i   = w_i (3 c.F + 9 (c.u)(c.F) - 3 u.F)              (Eq. 5)
+//   STANDARD_EQF: feq_i as above, F_i = 3 (c - u).F feq_i / rho
+//             = w_i (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)(3 c.F - 3 u.F)
 //   WB:       feq_0 = rho - (1-w0) rho0 - 1.5 w0 rho u.u,
 //             feq_i = w_i (rho0 + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)) (Eq. 24)
 //             F_i   = w_i (3 c.F + 9 (c.u)(c.G) - 3 u.G
@@ -109,6 +113,9 @@ __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R 
     if (SCHEME == STANDARD) {
       geq = w * (drho + rho * poly);
       Fi = w * ((R)3 * cF[i] + (R)9 * cu[i] * cF[i] - uG3);
+    } else if (SCHEME == STANDARD_EQF) {
+      geq = w * (drho + rho * poly);
+      Fi = w * ((R)1 + poly) * ((R)3 * cF[i] - uG3);  // G = F here
     } else {
       geq = (i == 0) ? drho - w0 * rho * u15 : w * rho * poly;
       const R k = (i == 0) ? (R)-1 : (i < 5 ? (R)0.5 : (R)2);
@@ -274,7 +281,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
         gmy = -gmy;
       }
       R Fx = -rho * gmx, Fy = -rho * gmy;
-      if (SCHEME == STANDARD) {
+      if (SCHEME != WELL_BALANCED) {
         Fx += grx * third;
         Fy += gry * third;
       }
@@ -549,7 +556,7 @@ __global__ void __launch_bounds__(S4X * S4Y)
     grad4r<R>(rt[i - 2], rt[i - 1], rt[i], rt[i + 1], rt[i + 2], j, grx, gry);
     grad4r<R>(mt[i - 2], mt[i - 1], mt[i], mt[i + 1], mt[i + 2], j, gmx, gmy);
     R Fx = -rr * gmx, Fy = -rr * gmy;
-    if (SCHEME == STANDARD) {
+    if (SCHEME != WELL_BALANCED) {
       Fx += grx * ((R)1 / (R)3);
       Fy += gry * ((R)1 / (R)3);
     }
@@ -729,7 +736,7 @@ __global__ void __launch_bounds__(BW)
         gmy = -gmy;
       }
       R Fx = -rho * gmx, Fy = -rho * gmy;
-      if (SCHEME == STANDARD) {
+      if (SCHEME != WELL_BALANCED) {
         Fx += grx * ((R)1 / (R)3);
         Fy += gry * ((R)1 / (R)3);
       }
@@ -888,13 +895,19 @@ hipError_t launch_march(int storage, int scheme, const Geometry& g, const Physic
                         const Tiling& t, const void* fin, void* fout, const ObserveOut& o,
                         hipStream_t s) {
   if (t.blocks() <= 0) return hipErrorInvalidValue;
+  // the observe pass of STANDARD_EQF is the standard one (same force and u)
+  if (OBS && scheme == STANDARD_EQF) scheme = STANDARD;
   if (storage == FP64) {
-    return scheme == STANDARD
-               ? launch_march_w<double, STANDARD, OBS>(g, ph, t, fin, fout, o, s)
-               : launch_march_w<double, WELL_BALANCED, OBS>(g, ph, t, fin, fout, o, s);
+    if (scheme == STANDARD)
+      return launch_march_w<double, STANDARD, OBS>(g, ph, t, fin, fout, o, s);
+    if (!OBS && scheme == STANDARD_EQF)
+      return launch_march_w<double, STANDARD_EQF, false>(g, ph, t, fin, fout, o, s);
+    return launch_march_w<double, WELL_BALANCED, OBS>(g, ph, t, fin, fout, o, s);
   }
-  return scheme == STANDARD ? launch_march_w<float, STANDARD, OBS>(g, ph, t, fin, fout, o, s)
-                            : launch_march_w<float, WELL_BALANCED, OBS>(g, ph, t, fin, fout, o, s);
+  if (scheme == STANDARD) return launch_march_w<float, STANDARD, OBS>(g, ph, t, fin, fout, o, s);
+  if (!OBS && scheme == STANDARD_EQF)
+    return launch_march_w<float, STANDARD_EQF, false>(g, ph, t, fin, fout, o, s);
+  return launch_march_w<float, WELL_BALANCED, OBS>(g, ph, t, fin, fout, o, s);
 }
 
 inline unsigned grid1(long long n) { return (unsigned)((n + 255) / 256); }
@@ -940,6 +953,7 @@ const void* batch_kernel_t(int block, int depth) {
 }
 
 const void* batch_kernel(int storage, int scheme, int block, int depth, bool observe) {
+  if (scheme != STANDARD && scheme != WELL_BALANCED) return nullptr;  // batches: Eq. 5 / Eq. 26
   if (observe) depth = 1;
   if (storage == FP64) {
     if (scheme == STANDARD)
@@ -991,7 +1005,7 @@ hipError_t launch4_observe(int scheme, const Geometry& g, const Physics& ph, con
   hipLaunchKernelGGL(density4<T>, g1, dim3(256), 0, s, g, ph, in, rho);
   hipLaunchKernelGGL(potential4<T>, g1, dim3(256), 0, s, g, ph, (const double*)rho, mu);
   const dim3 g3((g.nx + S4X - 1) / S4X, (g.ny + S4Y - 1) / S4Y);
-  if (scheme == STANDARD)
+  if (scheme != WELL_BALANCED)
     hipLaunchKernelGGL((observe4_kernel<T, STANDARD>), g3, dim3(S4X * S4Y), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
@@ -1035,11 +1049,14 @@ bool stencil4_block_supported(int block) { return block == 256 || block == 512; 
 
 hipError_t launch_step4(int storage, int scheme, const Geometry& g, const Physics& ph,
                         const Tiling& t, const void* fin, void* fout, hipStream_t s) {
-  if (storage == FP64)
-    return scheme == STANDARD ? launch_march4<double, STANDARD>(g, ph, t, fin, fout, s)
-                              : launch_march4<double, WELL_BALANCED>(g, ph, t, fin, fout, s);
-  return scheme == STANDARD ? launch_march4<float, STANDARD>(g, ph, t, fin, fout, s)
-                            : launch_march4<float, WELL_BALANCED>(g, ph, t, fin, fout, s);
+  if (storage == FP64) {
+    if (scheme == STANDARD) return launch_march4<double, STANDARD>(g, ph, t, fin, fout, s);
+    if (scheme == STANDARD_EQF) return launch_march4<double, STANDARD_EQF>(g, ph, t, fin, fout, s);
+    return launch_march4<double, WELL_BALANCED>(g, ph, t, fin, fout, s);
+  }
+  if (scheme == STANDARD) return launch_march4<float, STANDARD>(g, ph, t, fin, fout, s);
+  if (scheme == STANDARD_EQF) return launch_march4<float, STANDARD_EQF>(g, ph, t, fin, fout, s);
+  return launch_march4<float, WELL_BALANCED>(g, ph, t, fin, fout, s);
 }
 
 hipError_t launch_observe4(int storage, int scheme, const Geometry& g, const Physics& ph,
@@ -1054,14 +1071,14 @@ hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics
                        hipStream_t s) {
   const long long n = (long long)g.nx * g.ny;
   if (storage == FP64) {
-    if (scheme == STANDARD)
+    if (scheme != WELL_BALANCED)
       hipLaunchKernelGGL((init_kernel<double, STANDARD>), dim3(grid1(n)), dim3(256), 0, s, g, ph,
                          rho, ux, uy, (double*)f);
     else
       hipLaunchKernelGGL((init_kernel<double, WELL_BALANCED>), dim3(grid1(n)), dim3(256), 0, s, g,
                          ph, rho, ux, uy, (double*)f);
   } else {
-    if (scheme == STANDARD)
+    if (scheme != WELL_BALANCED)
       hipLaunchKernelGGL((init_kernel<float, STANDARD>), dim3(grid1(n)), dim3(256), 0, s, g, ph,
                          rho, ux, uy, (float*)f);
     else

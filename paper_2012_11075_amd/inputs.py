@@ -146,6 +146,12 @@ DROPLET_4096 = Problem("droplet_4096", 4096, 4096, THROUGHPUT_PHYS, "droplet", 5
 FINITE_PHYS = Physics(tau=0.8, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=0.01)
 DROPLET_4096_FINITE = Problem("droplet_4096_finite", 4096, 4096, FINITE_PHYS, "droplet",
                               equilibrium_width(FINITE_PHYS), 1024.0, 0.0, 1e-3, "mul", 3, 2_000)
+# The Sec. IV.B droplet constants (density ratio 5) on the 4096 x 4096 grid:
+# a full-size case on which the standard LBE stays finite (at density ratio
+# 100 it goes to negative densities within a few steps), used for the
+# forcing-term comparison of Sec. II.
+PAPER_DROPLET_4096 = Problem("paper_droplet_4096", 4096, 4096, PAPER_PHYS, "droplet", 4.0,
+                             1024.0, 0.0, 1e-3, "mul", 5, 2_000)
 # The same physics on a 512 x 512 crop (radius scaled), for parity at moderate size.
 DROPLET_512_RATIO100 = Problem("droplet_512_ratio100", 512, 512, THROUGHPUT_PHYS, "droplet",
                                5.0, 128.0, 0.0, 1e-3, "mul", 3, 1_000)
@@ -158,7 +164,7 @@ PAPER_DROPLET = Problem("paper_droplet_100", 100, 100, PAPER_PHYS, "droplet", 4.
                         1e-2, "mul", 12, 0)
 
 PROBLEMS = {p.name: p for p in [FLAT_200x4, DROPLET_256, DROPLET_4096, DROPLET_4096_FINITE,
-                                DROPLET_512_RATIO100,
+                                PAPER_DROPLET_4096, DROPLET_512_RATIO100,
                                 PAPER_FLAT, PAPER_DROPLET]}
 
 

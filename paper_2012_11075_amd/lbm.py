@@ -18,9 +18,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "_lib", "liblbm.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "lbm.h")
 
-STANDARD, WELL_BALANCED = 0, 1
+STANDARD, WELL_BALANCED, STANDARD_EQ_FORCING = 0, 1, 2
 FP64, FP32_SHIFTED = 0, 1
-SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED}
+SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED,
+           "standard_eq_forcing": STANDARD_EQ_FORCING}
 PRECISIONS = {"fp64": FP64, "fp32s": FP32_SHIFTED, "fp32_shifted": FP32_SHIFTED}
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOSPACE", -3: "LBM_EHIP",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE", -6: "LBM_EBUSY"}
