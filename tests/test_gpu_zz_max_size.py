@@ -1,0 +1,87 @@
+"""The step at the largest lattices the library accepts (2^31 nodes) and
+HBM holds: element offsets into one population copy far beyond 2^32.
+
+No population array comes back to the host (it would be 77-155 GB).  The
+initial populations are a local function of the initial density, so the
+oracle rebuilds any window's state from the same density; after one GPU
+step, rho of sampled windows (the far corner, the periodic seams, the
+middle) is compared with the oracle's step on periodic crops with a 3-node
+margin.
+"""
+import ctypes
+import gc
+
+import numpy as np
+import pytest
+
+from paper_2012_11075_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _density(nx, ny, seed):
+    """rho(y, x) = a(y) + b(x): smooth periodic profiles plus per-row and
+    per-column noise (grid-scale structure in both directions), in [0.16, 0.94]."""
+    rng = np.random.default_rng(seed)
+    a = 0.55 + 0.35 * np.sin(2 * np.pi * 3 * np.arange(ny) / ny) + 0.01 * rng.uniform(-1, 1, ny)
+    b = 0.02 * np.sin(2 * np.pi * 5 * np.arange(nx) / nx) + 0.01 * rng.uniform(-1, 1, nx)
+    return a[:, None] + b[None, :]
+
+
+def _run(orc, nx, ny, precision, scheme, tol):
+    import torch
+    from paper_2012_11075_amd import lbm
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ph = I.PAPER_PHYS
+    prm = lbm.make_params(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                          precision=precision)
+    need = lbm.load().lbm_workspace_bytes(ctypes.byref(prm))
+    assert need > 0
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (2 << 30):
+        pytest.skip("needs %.0f GB of free device memory, %.0f GB free" % (need / 1e9, free / 1e9))
+    print("max-size case", nx, ny, precision, scheme, "workspace %.1f GB" % (need / 1e9), flush=True)
+    rho0 = _density(nx, ny, 17)
+    s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                   precision=precision)
+    s.init(rho0, scheme=scheme)
+    s.step(1, scheme)
+    ob = s.observe(fields=("rho",))
+    s.close()
+    del s
+    gc.collect()
+    torch.cuda.empty_cache()
+    assert not ob["nonfinite"] and ob["step"] == 1
+    rho = ob["rho"]
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    rng = np.random.default_rng(5)
+    W, M = 22, 3
+    corners = [(ny - W + M, nx - W + M), (ny - 1, nx - 1), (0, 0), (ny // 2, nx // 2),
+               (ny - 2, 7), (5, nx - 3)]
+    corners += [(int(rng.integers(0, ny)), int(rng.integers(0, nx))) for _ in range(6)]
+    worst = 0.0
+    for (y0, x0) in corners:
+        ys = np.arange(y0 - M, y0 + W - M) % ny
+        xs = np.arange(x0 - M, x0 + W - M) % nx
+        crop = np.ascontiguousarray(rho0[ys][:, xs])
+        f = orc.step(scheme, p, orc.init(scheme, p, crop), 1)
+        want = orc.fields(scheme, p, f)[0][M:-M, M:-M]
+        got = rho[ys[M:-M]][:, xs[M:-M]]
+        err = np.abs(got - want).max()
+        worst = max(worst, err)
+        assert err <= tol, (y0, x0, err)
+    print("max-size case", nx, ny, precision, "worst rho error %.3e" % worst, flush=True)
+
+
+def test_fp64_32768_squared(orc):
+    """FP64 at 32768^2 (1.07e9 nodes, 77 GB per population copy): 1e-12."""
+    _run(orc, 32768, 32768, "fp64", "well_balanced", 1e-12)
+
+
+def test_fp32_at_the_node_limit(orc):
+    """FP32-shifted at 46340^2 = 2,147,395,600 nodes, the largest square
+    lattice within the 2^31-node limit (155 GB of populations): within the
+    FP32 bound of one step, 2e-6."""
+    _run(orc, 46340, 46340, "fp32s", "standard", 2e-6)
