@@ -410,3 +410,54 @@ def test_force_stencil4_fp32_against_oracle(orc, lbm, scheme):
           % (scheme, steps, e_rho, e_u, e_f))
     assert e_rho < 5e-5 and e_u < 1e-5 and e_f < 5e-5
     assert abs(ob["mass"] - orc.observe(scheme, p, fo)["mass"]) < 1e-5 * ob["mass"]
+
+
+def test_droplet_256_full_run_against_oracle(orc, lbm):
+    """The 256^2 droplet workload as configured: 20,000 WB steps on the GPU
+    against the oracle's 20,000 steps from the same state (populations, rho,
+    u to 1e-10), and the Sec. IV.B reads of the GPU fields (max|u|, bulk
+    densities at the centre and the farthest node, Laplace jump p0(rho_in) -
+    p0(rho_out)) against the oracle's own reads.  The standard scheme
+    diverges on this workload (interface 1.4 nodes wide): the GPU flags it
+    non-finite in the same 5-step window as the oracle."""
+    from paper_2012_11075_amd import diagnostics as D
+    prob = I.DROPLET_256
+    ph = prob.physics
+    p = oparams(orc, ph)
+    rho0 = prob.rho()
+    steps = prob.steps
+    assert steps == 20_000
+    print("full run droplet_256 well_balanced", steps, flush=True)
+    fo = orc.step("well_balanced", p, orc.init("well_balanced", p, rho0), steps)
+    ro, uxo, uyo, _ = orc.fields("well_balanced", p, fo)
+    oo = orc.observe("well_balanced", p, fo)
+    s = run_gpu(lbm, prob, "well_balanced", steps, rho=rho0)
+    fg = to_oracle(s.get_populations())
+    ob = s.observe()
+    s.close()
+    assert np.abs(fg - fo).max() <= 1e-10
+    assert np.abs(ob["rho"] - ro).max() <= 1e-10
+    assert max(np.abs(ob["ux"] - uxo).max(), np.abs(ob["uy"] - uyo).max()) <= 1e-10
+    assert abs(ob["max_u"] - oo["max_u"]) <= 1e-10
+    g = D.droplet_reads(ob["rho"], ph.beta, ph.rho_l, ph.rho_v)
+    o = orc.droplet_diagnostics(p, ro, prob.nx // 2, prob.ny // 2)
+    print("droplet_256 after %d WB steps: max|u| %.3e, rho_in %.6f, rho_out %.6f, dp %.3e"
+          % (steps, ob["max_u"], g["rho_in"], g["rho_out"], g["laplace_dp"]))
+    assert abs(g["rho_in"] - o["rho_in"]) <= 1e-10 and abs(g["rho_out"] - o["rho_out"]) <= 1e-10
+    assert abs(g["laplace_dp"] - o["dp"]) <= 1e-12
+    # the standard scheme on the same workload
+    fo = orc.init("standard", p, rho0)
+    s = run_gpu(lbm, prob, "standard", 0, rho=rho0)
+    k = 0
+    while k < 200:
+        fo = orc.step("standard", p, fo, 5)
+        s.step(5, "standard")
+        k += 5
+        orc_bad = orc.observe("standard", p, fo)["nonfinite"]
+        gpu_bad = s.observe(fields=(), raise_nonfinite=False)["nonfinite"]
+        assert orc_bad == gpu_bad, k
+        if orc_bad:
+            break
+    s.close()
+    print("droplet_256 standard scheme: non-finite at step window ending %d" % k)
+    assert k < 200
