@@ -461,3 +461,43 @@ def test_droplet_256_full_run_against_oracle(orc, lbm):
     s.close()
     print("droplet_256 standard scheme: non-finite at step window ending %d" % k)
     assert k < 200
+
+
+def test_flat_200x4_full_run_against_oracle(orc, lbm):
+    """The 200x4 flat-interface workload as configured: 10,000 WB steps
+    against the oracle's (f, rho, u to 1e-10, max|u| and kinetic energy),
+    and the standard scheme's divergence on it (interface 1.4 nodes wide)
+    detected in the same 5-step window as the oracle's."""
+    prob = I.FLAT_200x4
+    p = oparams(orc, prob.physics)
+    rho0 = prob.rho()
+    steps = prob.steps
+    assert steps == 10_000
+    fo = orc.step("well_balanced", p, orc.init("well_balanced", p, rho0), steps)
+    ro, uxo, uyo, _ = orc.fields("well_balanced", p, fo)
+    oo = orc.observe("well_balanced", p, fo)
+    s = run_gpu(lbm, prob, "well_balanced", steps, rho=rho0)
+    fg = to_oracle(s.get_populations())
+    ob = s.observe()
+    s.close()
+    assert np.abs(fg - fo).max() <= 1e-10
+    assert np.abs(ob["rho"] - ro).max() <= 1e-10
+    assert max(np.abs(ob["ux"] - uxo).max(), np.abs(ob["uy"] - uyo).max()) <= 1e-10
+    assert abs(ob["max_u"] - oo["max_u"]) <= 1e-10
+    assert abs(ob["kinetic_energy"] - oo["kinetic_energy"]) <= 1e-12 * max(1.0, oo["kinetic_energy"])
+    print("flat_200x4 after %d WB steps: max|u| %.3e, E %.3e" % (steps, ob["max_u"],
+                                                               ob["kinetic_energy"]))
+    fo = orc.init("standard", p, rho0)
+    s = run_gpu(lbm, prob, "standard", 0, rho=rho0)
+    k = 0
+    while k < 500:
+        fo = orc.step("standard", p, fo, 5)
+        s.step(5, "standard")
+        k += 5
+        orc_bad = orc.observe("standard", p, fo)["nonfinite"]
+        assert orc_bad == s.observe(fields=(), raise_nonfinite=False)["nonfinite"], k
+        if orc_bad:
+            break
+    s.close()
+    print("flat_200x4 standard scheme: non-finite at step window ending %d" % k)
+    assert k < 500
