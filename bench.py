@@ -306,6 +306,57 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="
                            precision.upper(), steps)}
 
 
+def time_largest(steps, warmup, n=32768):
+    """The FP64 WB step on the largest square lattice HBM holds in FP64
+    (32768^2, a 189 GB workspace), with the headline's tile, on a separable
+    density (Sec. IV constants, density ratio 5): the rate at 64x the
+    headline's node count."""
+    import ctypes
+    import gc
+    import torch
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm, tune
+    ph = I.PAPER_PHYS
+    prm = lbm.make_params(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    need = lbm.load().lbm_workspace_bytes(ctypes.byref(prm))
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (2 << 30):
+        return {"skipped": "needs %.0f GB of free device memory, %.0f GB free"
+                           % (need / 1e9, free / 1e9)}
+    rho = I.separable_density(n, n, 17)
+    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    s.set_tile(*tune.bench_tile(4096, 4096, "fp64"))
+    s.init(rho, scheme="well_balanced")
+    del rho
+    s.step(warmup, "well_balanced")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps, "well_balanced")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ob = s.observe(fields=(), raise_nonfinite=False)
+    used = s.get_tile()
+    s.close()
+    del s
+    gc.collect()
+    torch.cuda.empty_cache()
+    nodes = n * n
+    gbs = 144 * nodes / (ms / 1e3) / 1e9
+    return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 4),
+            "nx": n, "ny": n, "workspace_gb": round(need / 1e9, 1), "tile": list(used),
+            "bytes_per_update": 144, "hbm_gbs_algorithmic": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
+            "workload": "%d^2 separable density, Sec. IV constants (ratio 5), WB, FP64, %d steps "
+                        "after %d" % (n, steps, warmup)}
+
+
 D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
 
 
@@ -408,6 +459,7 @@ def main():
     ap.add_argument("--no-finite", action="store_true")
     ap.add_argument("--no-stencil4", action="store_true")
     ap.add_argument("--no-eq-forcing", action="store_true")
+    ap.add_argument("--no-largest", action="store_true")
     ap.add_argument("--no-d3", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -497,6 +549,10 @@ def main():
             pd, 400, 150, "standard", tile=tune.bench_tile(pd.nx, pd.ny, "fp64"), force_stencil=0)
         progress("standard LBE, eq-proportional forcing %.4f ms/step"
                  % out["standard_eq_forcing"]["ms_per_step"])
+    if not args.no_largest:
+        out["largest_lattice"] = time_largest(100, 100)
+        progress("largest lattice %s" % out["largest_lattice"].get("ms_per_step",
+                                                                   out["largest_lattice"]))
     if not args.no_d3:
         out["d3q19"] = time_d3q19(100, 50)
         out["d3q19"]["fp32_shifted"] = time_d3q19(100, 50, precision="fp32s")

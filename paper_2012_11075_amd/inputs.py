@@ -168,6 +168,16 @@ PROBLEMS = {p.name: p for p in [FLAT_200x4, DROPLET_256, DROPLET_4096, DROPLET_4
                                 PAPER_FLAT, PAPER_DROPLET]}
 
 
+def separable_density(nx: int, ny: int, seed: int) -> np.ndarray:
+    """rho(y, x) = a(y) + b(x) for lattices too large for the tanh profiles:
+    smooth periodic profiles plus per-row and per-column noise, so the field
+    has grid-scale structure in both directions; values in [0.16, 0.94]."""
+    rng = np.random.default_rng(seed)
+    a = 0.55 + 0.35 * np.sin(2 * np.pi * 3 * np.arange(ny) / ny) + 0.01 * rng.uniform(-1, 1, ny)
+    b = 0.02 * np.sin(2 * np.pi * 5 * np.arange(nx) / nx) + 0.01 * rng.uniform(-1, 1, nx)
+    return a[:, None] + b[None, :]
+
+
 def batch_instances(count: int = 512, seed: int = 4, side_lo: int = 32, side_hi: int = 512,
                     steps: int = 5_000) -> list:
     """Uneven independent problems for one batched launch: side log-uniform on

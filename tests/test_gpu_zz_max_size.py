@@ -19,15 +19,6 @@ from paper_2012_11075_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def _density(nx, ny, seed):
-    """rho(y, x) = a(y) + b(x): smooth periodic profiles plus per-row and
-    per-column noise (grid-scale structure in both directions), in [0.16, 0.94]."""
-    rng = np.random.default_rng(seed)
-    a = 0.55 + 0.35 * np.sin(2 * np.pi * 3 * np.arange(ny) / ny) + 0.01 * rng.uniform(-1, 1, ny)
-    b = 0.02 * np.sin(2 * np.pi * 5 * np.arange(nx) / nx) + 0.01 * rng.uniform(-1, 1, nx)
-    return a[:, None] + b[None, :]
-
-
 def _run(orc, nx, ny, precision, scheme, tol):
     import torch
     from paper_2012_11075_amd import lbm
@@ -43,7 +34,7 @@ def _run(orc, nx, ny, precision, scheme, tol):
     if free < need + (2 << 30):
         pytest.skip("needs %.0f GB of free device memory, %.0f GB free" % (need / 1e9, free / 1e9))
     print("max-size case", nx, ny, precision, scheme, "workspace %.1f GB" % (need / 1e9), flush=True)
-    rho0 = _density(nx, ny, 17)
+    rho0 = I.separable_density(nx, ny, 17)
     s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
                    precision=precision)
     s.init(rho0, scheme=scheme)
