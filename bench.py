@@ -420,8 +420,20 @@ def copy_reference(nx, ny):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, budget_s=15.0):
-    """The FP64 oracle on the same lattice for a bounded number of steps."""
+    """The FP64 oracle on the same lattice for a bounded number of steps, on
+    up to 16 host threads (OpenMP over rows) and on one thread."""
     import oracle
     oracle.build()
     ph = prob.physics
@@ -437,10 +449,60 @@ def cpu_baseline(prob, budget_s=15.0):
     f = oracle.step("well_balanced", p, f, k)
     dt = time.perf_counter() - t0
     nodes = prob.nx * prob.ny
-    return {"value": round(nodes * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.get_threads(),
+    used = oracle.get_threads()
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    f = oracle.step("well_balanced", p, f, 1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    return {"value": round(nodes * k / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
             "kind": "oracle",
             "sample": "%dx%d %s lattice, %d WB steps after one warm-up step, FP64, %d threads"
-                      % (prob.nx, prob.ny, prob.name, k, oracle.get_threads())}
+                      % (prob.nx, prob.ny, prob.name, k, used),
+            "single_thread_mlups": round(nodes / dt1 / 1e6, 3),
+            "single_thread_sample": "1 WB step of the same lattice on one thread",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def full_runs():
+    """The 200x4 flat interface (10,000 steps) and the 256^2 droplet (20,000
+    steps) in full with the WB scheme: wall time on the GPU (HIP-graph
+    captured steps, 100 per graph, after 100 warm-up steps) and of the FP64
+    oracle on up to 16 host threads, from the same initial state."""
+    import torch
+    import oracle
+    from paper_2012_11075_amd import inputs as I
+    from paper_2012_11075_amd import lbm
+    out = {}
+    for prob in (I.FLAT_200x4, I.DROPLET_256):
+        rho = prob.rho()
+        s = lbm.Solver.for_problem(prob)
+        s.set_graph_steps(100)
+        s.init(rho, scheme="well_balanced")
+        s.step(100, "well_balanced")
+        s.init(rho, scheme="well_balanced")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(prob.steps, "well_balanced")
+        torch.cuda.synchronize()
+        gpu_s = time.perf_counter() - t0
+        g = s.observe(fields=(), raise_nonfinite=False)
+        s.close()
+        ph = prob.physics
+        p = oracle.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+        oracle.set_threads(min(16, os.cpu_count() or 1))
+        f = oracle.init("well_balanced", p, rho)
+        t0 = time.perf_counter()
+        f = oracle.step("well_balanced", p, f, prob.steps)
+        cpu_s = time.perf_counter() - t0
+        o = oracle.observe("well_balanced", p, f)
+        upd = prob.nx * prob.ny * prob.steps
+        out[prob.name] = {"steps": prob.steps, "gpu_s": round(gpu_s, 4),
+                          "gpu_mlups": round(upd / gpu_s / 1e6, 1),
+                          "oracle_s": round(cpu_s, 3), "oracle_mlups": round(upd / cpu_s / 1e6, 2),
+                          "oracle_threads": oracle.get_threads(),
+                          "max_u": {"gpu": g["max_u"], "oracle": o["max_u"]}}
+    return out
 
 
 def progress(msg):
@@ -569,6 +631,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
         progress("cpu baseline done")
+        out["cpu_baseline"]["full_runs"] = full_runs()
+        progress("full 200x4 and 256^2 runs done")
     print(json.dumps(out), flush=True)
 
 

@@ -172,14 +172,16 @@ lbm_status lbm_observe3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, doub
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme, int64_t step);
 
-/* Tile shape of the step kernel: block width in threads (128, 192, 256, 320
- * or 512; the block computes block_width output columns), output rows
+/* Tile shape of the step kernel: block width in threads (64, 128, 192, 256,
+ * 320 or 512; the block computes block_width output columns), output rows
  * per block (>= 4) and prefetch depth (rows of populations each thread keeps
  * in flight, 1..3).  3-D lattices (nz > 1): block width 256 or 512 threads
  * (tiles of 32 x 8 or 32 x 16 nodes), rows = z planes each block marches
  * through (>= 1), depth 1.  Any valid shape gives bit-identical populations.
- * 0 keeps the current value.  lbm_get_tile reports the shape in use (any
- * output pointer may be NULL). */
+ * 0 keeps the current value.  A new 2-D context starts from a default
+ * chosen from the lattice size (64-wide strips with short chunks up to
+ * 512 columns, 256-wide strips above).  lbm_get_tile reports the shape in
+ * use (any output pointer may be NULL). */
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t block_width, int32_t rows, int32_t depth);
 lbm_status lbm_get_tile(const lbm_ctx* ctx, int32_t* block_width, int32_t* rows, int32_t* depth);
 

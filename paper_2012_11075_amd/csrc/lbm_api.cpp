@@ -205,15 +205,23 @@ lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows, int depth
   return t;
 }
 
-// Default tile: 256-wide strips; rows chosen so that the grid holds a few
-// blocks per compute unit of a 256-CU device and chunks stay tall (the y-halo
-// costs 4 rows per chunk).
-lbmk::Tiling default_tiling(const lbmk::Geometry& g) {
-  const int block = 256;
+// Default tile.  Rows are chosen so that the grid holds about 2048 blocks
+// (eight per compute unit of a 256-CU device) while chunks stay as tall as
+// that allows, since the y-halo costs 4 rows per chunk.  Lattices up to 512
+// wide are latency-bound (a step lasts about as long as one block's march
+// through its chunk), so they get 64-wide strips and chunks down to 4 rows:
+// a 256^2 step takes ~11 us instead of ~35 us with 256 x 16 tiles.  Wider
+// lattices get 256-wide strips and chunks of at least 8 rows.  The
+// force-stencil variant keeps 256-wide strips and chunks of at least 16 rows
+// (its block widths are 256 and 512).
+lbmk::Tiling default_tiling(const lbmk::Geometry& g, bool stencil4) {
+  const bool narrow = !stencil4 && g.nx <= 512;
+  const int block = narrow ? 64 : 256;
   const int strips = (g.nx + block - 1) / block;
   const long long target = 2048;
   long long rows = ((long long)g.ny * strips + target - 1) / target;
-  rows = std::max<long long>(16, std::min<long long>(rows, 128));
+  const long long min_rows = stencil4 ? 16 : (narrow ? 4 : 8);
+  rows = std::max<long long>(min_rows, std::min<long long>(rows, 128));
   return make_tiling(g, block, (int)rows, 2);
 }
 
@@ -404,7 +412,7 @@ lbm_status lbm_create(const lbm_params* p, void* ws, size_t bytes, void* stream,
   c->L = L;
   c->ws = (char*)ws;
   c->stream = (hipStream_t)stream;
-  c->tl = default_tiling(L.g);
+  c->tl = default_tiling(L.g, p->force_stencil == 1);
   c->tl3 = t3;
   *out = c;
   return LBM_OK;
