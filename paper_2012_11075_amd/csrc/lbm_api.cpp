@@ -210,17 +210,18 @@ lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows, int depth
 // that allows, since the y-halo costs 4 rows per chunk.  Lattices up to 512
 // wide are latency-bound (a step lasts about as long as one block's march
 // through its chunk), so they get 64-wide strips and chunks down to 4 rows:
-// a 256^2 step takes ~11 us instead of ~35 us with 256 x 16 tiles.  Wider
-// lattices get 256-wide strips and chunks of at least 8 rows.  The
-// force-stencil variant keeps 256-wide strips and chunks of at least 16 rows
-// (its block widths are 256 and 512).
+// a 256^2 step takes ~12 us instead of ~35 us with 256 x 16 tiles.  Up to
+// 1024 wide, 256-wide strips with chunks of at least 8 rows; wider lattices
+// (and the force-stencil variant, whose block widths are 256 and 512) keep
+// chunks of at least 16 rows, measured faster there (2048^2 FP64: 115 us
+// against 121 us with 8-row chunks).
 lbmk::Tiling default_tiling(const lbmk::Geometry& g, bool stencil4) {
   const bool narrow = !stencil4 && g.nx <= 512;
   const int block = narrow ? 64 : 256;
   const int strips = (g.nx + block - 1) / block;
   const long long target = 2048;
   long long rows = ((long long)g.ny * strips + target - 1) / target;
-  const long long min_rows = stencil4 ? 16 : (narrow ? 4 : 8);
+  const long long min_rows = narrow ? 4 : (!stencil4 && g.nx <= 1024 ? 8 : 16);
   rows = std::max<long long>(min_rows, std::min<long long>(rows, 128));
   return make_tiling(g, block, (int)rows, 2);
 }
