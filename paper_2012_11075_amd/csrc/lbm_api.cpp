@@ -205,25 +205,31 @@ lbmk::Tiling make_tiling(const lbmk::Geometry& g, int block, int rows, int depth
   return t;
 }
 
-// Default tile.  Rows are chosen so that the grid holds about 2048 blocks
-// (eight per compute unit of a 256-CU device) while chunks stay as tall as
-// that allows, since the y-halo costs 4 rows per chunk.  Lattices up to 512
-// wide are latency-bound (a step lasts about as long as one block's march
-// through its chunk), so they get 64-wide strips and chunks down to 4 rows:
-// a 256^2 step takes ~12 us instead of ~35 us with 256 x 16 tiles.  Up to
-// 1024 wide, 256-wide strips with chunks of at least 8 rows; wider lattices
-// (and the force-stencil variant, whose block widths are 256 and 512) keep
-// chunks of at least 16 rows, measured faster there (2048^2 FP64: 115 us
-// against 121 us with 8-row chunks).
+// Default tile, by lattice width (measured with 100-step graphs).  Lattices
+// up to 512 wide are latency-bound: a step lasts about as long as one
+// block's march through its chunk, so they get many 4-row chunks in 64-wide
+// strips (256-wide at depth 1 for the force-stencil variant, whose block
+// widths are 256 and 512): a 256^2 step takes ~12 us instead of ~35 us with
+// 256 x 16 tiles.  Up to 1024 wide: 256-wide strips, chunks of at least 8
+// rows, about 2048 blocks.  Wider: about 512 blocks with chunks of at least
+// 16 rows (2048^2 FP64: 32-row chunks, 114 us, against 115 us with 16 and
+// 121 us with 8).
 lbmk::Tiling default_tiling(const lbmk::Geometry& g, bool stencil4) {
-  const bool narrow = !stencil4 && g.nx <= 512;
-  const int block = narrow ? 64 : 256;
+  int block = 256, depth = 2;
+  long long target = 2048, min_rows = 16;
+  if (g.nx <= 512) {
+    block = stencil4 ? 256 : 64;
+    depth = stencil4 ? 1 : 2;
+    min_rows = 4;
+  } else if (g.nx <= 1024) {
+    min_rows = 8;
+  } else {
+    target = 512;
+  }
   const int strips = (g.nx + block - 1) / block;
-  const long long target = 2048;
   long long rows = ((long long)g.ny * strips + target - 1) / target;
-  const long long min_rows = narrow ? 4 : (!stencil4 && g.nx <= 1024 ? 8 : 16);
   rows = std::max<long long>(min_rows, std::min<long long>(rows, 128));
-  return make_tiling(g, block, (int)rows, 2);
+  return make_tiling(g, block, (int)rows, depth);
 }
 
 }  // namespace
