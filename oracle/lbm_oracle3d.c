@@ -40,7 +40,7 @@ static const double WT3[Q3] = {1.0 / 3.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
-enum { ORC3_STANDARD = 0, ORC3_WELL_BALANCED = 1 };
+enum { ORC3_STANDARD = 0, ORC3_WELL_BALANCED = 1, ORC3_STANDARD_EQF = 2 };
 
 /* Same layout as orc_params of lbm_oracle.c; force_stencil must be 0. */
 typedef struct {
@@ -65,12 +65,22 @@ void orc3_feq(int scheme, const orc3_params *p, double rho, double ux, double uy
   for (int i = 0; i < Q3; ++i) {
     double cu = CX3[i] * ux + CY3[i] * uy + CZ3[i] * uz;
     double poly = cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2);
-    if (scheme == ORC3_STANDARD)
+    if (scheme != ORC3_WELL_BALANCED)
       feq[i] = WT3[i] * rho * (1.0 + poly);
     else if (i == 0)
       feq[i] = rho - (1.0 - WT3[0]) * p->rho0 - WT3[0] * rho * uu / (2.0 * CS2);
     else
       feq[i] = WT3[i] * (p->rho0 + rho * poly);
+  }
+}
+
+/* The standard LBE's other forcing term, named after Eq. (5):
+ *   F_i = (c_i - u).F feq_i / (cs2 rho), feq of Eq. (3) at (rho, u). */
+void orc3_forcing_eq(const double *feq, double rho, double ux, double uy, double uz,
+                     double Fx, double Fy, double Fz, double *Fi) {
+  for (int i = 0; i < Q3; ++i) {
+    double cmuF = (CX3[i] - ux) * Fx + (CY3[i] - uy) * Fy + (CZ3[i] - uz) * Fz;
+    Fi[i] = cmuF * feq[i] / (CS2 * rho);
   }
 }
 
@@ -159,7 +169,7 @@ void orc3_macro(int scheme, const orc3_params *p, int nx, int ny, int nz, const 
   orc3_gradient(nx, ny, nz, rho, grx, gry, grz);
   for (size_t k = 0; k < n; ++k) {
     double fx = -rho[k] * gmx[k], fy = -rho[k] * gmy[k], fz = -rho[k] * gmz[k];
-    if (scheme == ORC3_STANDARD) {
+    if (scheme != ORC3_WELL_BALANCED) {
       fx += CS2 * grx[k];
       fy += CS2 * gry[k];
       fz += CS2 * grz[k];
@@ -208,7 +218,11 @@ void orc3_step(int scheme, const orc3_params *p, int nx, int ny, int nz, double 
           size_t k = idx3(x, y, z, nx, ny);
           double feq[Q3], Fi[Q3];
           orc3_feq(scheme, p, rho[k], ux[k], uy[k], uz[k], feq);
-          orc3_forcing(scheme, ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], grx[k], gry[k], grz[k], Fi);
+          if (scheme == ORC3_STANDARD_EQF)
+            orc3_forcing_eq(feq, rho[k], ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], Fi);
+          else
+            orc3_forcing(scheme, ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], grx[k], gry[k], grz[k],
+                         Fi);
           for (int i = 0; i < Q3; ++i) {
             double fs = f[k * Q3 + i] - omega * (f[k * Q3 + i] - feq[i]) + fpre * Fi[i];
             size_t d = idx3(wrap3(x + CX3[i], nx), wrap3(y + CY3[i], ny), wrap3(z + CZ3[i], nz), nx, ny);

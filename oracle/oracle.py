@@ -31,7 +31,7 @@ LIB = os.path.join(BUILD_DIR, "liboracle.so")
 
 STANDARD = 0
 WELL_BALANCED = 1
-STANDARD_EQF = 2  # standard LBE with F_i = (c_i - u).F feq_i / (cs2 rho) (2-D only)
+STANDARD_EQF = 2  # standard LBE with F_i = (c_i - u).F feq_i / (cs2 rho)
 SCHEMES = {"standard": STANDARD, "well_balanced": WELL_BALANCED, "wb": WELL_BALANCED,
            "standard_eq_forcing": STANDARD_EQF}
 
@@ -108,6 +108,7 @@ def _load():
             "orc_observe": (None, [i, P, i, i, _D, _D]),
             "orc3_feq": (None, [i, P, d, d, d, d, _D]),
             "orc3_forcing": (None, [i] + [d] * 9 + [_D]),
+            "orc3_forcing_eq": (None, [_D] + [d] * 7 + [_D]),
             "orc3_gradient": (None, [i, i, i, _D, _D, _D, _D]),
             "orc3_laplacian": (None, [i, i, i, _D, _D]),
             "orc3_macro": (None, [i, P, i, i, i, _D] + [_D] * 11),
@@ -138,8 +139,8 @@ def _scheme(s) -> int:
 
 def _scheme3(s) -> int:
     k = _scheme(s)
-    if k not in (STANDARD, WELL_BALANCED):
-        raise ValueError("the 3-D oracle has the standard and well-balanced schemes only")
+    if k not in (STANDARD, WELL_BALANCED, STANDARD_EQF):
+        raise ValueError("unknown scheme %r" % (s,))
     return k
 
 
@@ -326,9 +327,22 @@ def feq3(scheme, p: Params, rho, ux, uy, uz) -> np.ndarray:
 
 
 def forcing3(scheme, u, F, gr=(0.0, 0.0, 0.0)) -> np.ndarray:
-    """D3Q19 forcing term: Eq. (5) standard, Eq. (26) with D = 3."""
+    """D3Q19 forcing term: Eq. (5) standard, Eq. (26) with D = 3 (the
+    equilibrium-proportional form is ``forcing_eq3``)."""
+    k = _scheme3(scheme)
+    if k == STANDARD_EQF:
+        raise ValueError("forcing3(): use forcing_eq3 for the standard_eq_forcing scheme")
     out = np.zeros(19)
-    _load().orc3_forcing(_scheme3(scheme), *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
+    _load().orc3_forcing(k, *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
+    return out
+
+
+def forcing_eq3(p: Params, rho, u, F) -> np.ndarray:
+    """D3Q19 form of the forcing term named after Eq. (5):
+    F_i = (c_i - u).F feq_i / (cs2 rho), feq of Eq. (3)."""
+    fe = feq3(STANDARD, p, rho, *map(float, u))
+    out = np.zeros(19)
+    _load().orc3_forcing_eq(_ptr(fe), float(rho), *map(float, u), *map(float, F), _ptr(out))
     return out
 
 

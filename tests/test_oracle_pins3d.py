@@ -16,6 +16,7 @@ C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1]
               [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=float)
 CS2 = 1.0 / 3.0
 SCHEMES = ["standard", "well_balanced"]
+STEP_SCHEMES = SCHEMES + ["standard_eq_forcing"]
 
 
 def test_velocity_set_is_the_oracles(orc):
@@ -65,6 +66,26 @@ def test_forcing_moments3(orc, scheme):
         np.testing.assert_allclose(np.einsum("i,ia,ib->ab", Fi, C, C), want, atol=1e-15)
 
 
+def test_eq_forcing_moments3(orc):
+    """The D3Q19 form of the forcing term named after Eq. (5),
+    F_i = (c_i - u).F feq_i/(cs2 rho): from the moments of the D3Q19
+    equilibrium (second cs2 rho I + rho uu, third cs2 rho (u d)_sym, which
+    D3Q19's fourth-order isotropy gives), sum F_i = 0, sum c F_i = F and
+    sum cc F_i = uF + Fu - uu (u.F)/cs2; F_i does not depend on rho."""
+    rng = np.random.default_rng(16)
+    p = orc.Params(0.8, 0.1, 0.02, 1.0, 0.1)
+    for _ in range(40):
+        rho = rng.uniform(0.05, 2.0)
+        u = rng.uniform(-0.2, 0.2, 3)
+        F = rng.uniform(-0.1, 0.1, 3)
+        Fi = orc.forcing_eq3(p, rho, u, F)
+        want = np.outer(u, F) + np.outer(F, u) - np.outer(u, u) * np.dot(u, F) / CS2
+        assert abs(Fi.sum()) < 1e-15
+        np.testing.assert_allclose(C.T @ Fi, F, atol=1e-15)
+        np.testing.assert_allclose(np.einsum("i,ia,ib->ab", Fi, C, C), want, atol=1e-15)
+        np.testing.assert_allclose(orc.forcing_eq3(p, 2.5 * rho, u, F), Fi, atol=1e-16)
+
+
 def test_stencils3_exact_on_quadratics_and_reduce_to_1d(orc):
     """The 3-D isotropic gradient and Laplacian are exact for quadratics
     (away from the seam), and on a field that varies along one axis they are
@@ -103,7 +124,7 @@ def droplet3(n, R, ph, width=4.0, noise=0.0, seed=1):
     return rho
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_mass_conservation_and_uniform_fixed_point3(orc, scheme):
     ph = I.PAPER_PHYS
     p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v)
@@ -126,7 +147,7 @@ def _index_map(transform):
     return out
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_translation_permutation_and_mirror3(orc, scheme):
     """The step commutes with translations (bit for bit), with a cyclic
     permutation of the axes and with a mirror (to summation order)."""
@@ -156,7 +177,7 @@ def test_translation_permutation_and_mirror3(orc, scheme):
     np.testing.assert_allclose(g, f_m, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("scheme", STEP_SCHEMES)
 def test_shear_wave_viscosity3(orc, scheme):
     """A small shear wave u_x(z) = U sin(k z) decays as exp(-nu k^2 t) with
     nu = cs2 (tau - 1/2) (no free energy: beta = kappa = 0)."""
