@@ -64,9 +64,9 @@ typedef enum {
  * forcing term Eq. 5).  LBM_WELL_BALANCED: Sec. III (Eqs. 24-26).
  * LBM_STANDARD_EQ_FORCING: the standard LBE with the other forcing term the
  * paper names after Eq. (5), F_i = (c_i - u).F feq_i / (cs2 rho); same
- * equilibrium, force, observe pass and FP32 shift as LBM_STANDARD.  2-D
- * single lattices only, with either force stencil and either precision:
- * 3-D contexts and lbm_batch_admit reject it with LBM_EINVAL. */
+ * equilibrium, force, observe pass and FP32 shift as LBM_STANDARD.  Single
+ * lattices, 2-D (either force stencil) and 3-D, in either precision;
+ * lbm_batch_admit rejects it with LBM_EINVAL. */
 typedef enum {
   LBM_STANDARD = 0,
   LBM_WELL_BALANCED = 1,

@@ -378,11 +378,8 @@ bool valid_scheme(int s) {
 }
 
 // nullptr if the context can run `scheme`, else the reason it cannot.
-const char* scheme_error(const lbm_ctx* c, int scheme) {
-  if (!valid_scheme(scheme)) return "unknown scheme";
-  if (scheme == LBM_STANDARD_EQ_FORCING && c->d3())
-    return "the equilibrium-proportional forcing term is implemented for 2-D lattices only";
-  return nullptr;
+const char* scheme_error(const lbm_ctx*, int scheme) {
+  return valid_scheme(scheme) ? nullptr : "unknown scheme";
 }
 
 }  // namespace

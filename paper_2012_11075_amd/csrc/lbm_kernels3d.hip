@@ -99,6 +99,10 @@ __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, 
     if (SCHEME == STANDARD) {
       feq = SHIFTED ? w * (drho + rho * poly) + (R)p.c[i] : w * rho * ((R)1 + poly);
       Fi = w * ((R)3 * cF + (R)9 * cu * cG - uG3);
+    } else if (SCHEME == STANDARD_EQF) {
+      // F_i = (c_i - u).F feq_i / (cs2 rho) with feq_i / rho = w (1 + poly); G = F here
+      feq = SHIFTED ? w * (drho + rho * poly) + (R)p.c[i] : w * rho * ((R)1 + poly);
+      Fi = w * ((R)1 + poly) * ((R)3 * cF - uG3);
     } else {
       if (SHIFTED)
         feq = (i == 0 ? drho - w * rho * u15 : w * rho * poly) + (R)p.c[i];
@@ -163,7 +167,7 @@ __device__ __forceinline__ void force_velocity3(const R (&f)[Q3], R r, R grx, R 
   Fx = -r * gmx;
   Fy = -r * gmy;
   Fz = -r * gmz;
-  if (SCHEME == STANDARD) {
+  if (SCHEME != WELL_BALANCED) {
     Fx += grx * ((R)1 / (R)3);
     Fy += gry * ((R)1 / (R)3);
     Fz += grz * ((R)1 / (R)3);
@@ -596,6 +600,7 @@ int blocks3(const Geometry3& g) {
 hipError_t launch_init3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
                         const double* rho, const double* ux, const double* uy, const double* uz,
                         void* f, hipStream_t s) {
+  if (scheme == STANDARD_EQF) scheme = STANDARD;  // same equilibrium
   if (storage == FP64) {
     if (scheme == STANDARD)
       hipLaunchKernelGGL((init3_kernel<double, STANDARD>), grid_rows3(g), dim3(256), 0, s, g, ph,
@@ -713,7 +718,7 @@ hipError_t launch_observe3_t(int scheme, const Geometry3& g, const Physics3& ph,
   hipLaunchKernelGGL(density3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, in, rho);
   hipLaunchKernelGGL(potential3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
   const dim3 gc((g.nx + T3X - 1) / T3X, (g.ny + T3Y - 1) / T3Y, (g.nz + T3Z - 1) / T3Z);
-  if (scheme == STANDARD)
+  if (scheme != WELL_BALANCED)  // both standard forms: same force and velocity
     hipLaunchKernelGGL((observe3_kernel<T, STANDARD>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
@@ -728,14 +733,18 @@ hipError_t launch_step3(int storage, int scheme, const Geometry3& g, const Physi
                         const Tiling3& t, const void* fin, void* fout, hipStream_t s) {
   const long long elem = storage == FP64 ? 8 : 4;
   if (g.slab * elem > 0xffffffffLL) return hipErrorInvalidValue;
-  if (storage == FP64)
-    return scheme == STANDARD
-               ? launch_march3<double, STANDARD>(g, ph, t, (const double*)fin, (double*)fout, s)
-               : launch_march3<double, WELL_BALANCED>(g, ph, t, (const double*)fin, (double*)fout,
-                                                      s);
-  return scheme == STANDARD
-             ? launch_march3<float, STANDARD>(g, ph, t, (const float*)fin, (float*)fout, s)
-             : launch_march3<float, WELL_BALANCED>(g, ph, t, (const float*)fin, (float*)fout, s);
+  if (storage == FP64) {
+    const auto* in = (const double*)fin;
+    auto* out = (double*)fout;
+    if (scheme == STANDARD) return launch_march3<double, STANDARD>(g, ph, t, in, out, s);
+    if (scheme == STANDARD_EQF) return launch_march3<double, STANDARD_EQF>(g, ph, t, in, out, s);
+    return launch_march3<double, WELL_BALANCED>(g, ph, t, in, out, s);
+  }
+  const auto* in = (const float*)fin;
+  auto* out = (float*)fout;
+  if (scheme == STANDARD) return launch_march3<float, STANDARD>(g, ph, t, in, out, s);
+  if (scheme == STANDARD_EQF) return launch_march3<float, STANDARD_EQF>(g, ph, t, in, out, s);
+  return launch_march3<float, WELL_BALANCED>(g, ph, t, in, out, s);
 }
 
 hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Physics3& ph,

@@ -35,7 +35,7 @@ def to_oracle(f):
 CASES3 = [(16, 12, 10, 300), (33, 9, 5, 200), (1, 7, 3, 200), (5, 2, 6, 200), (40, 24, 16, 100)]
 
 
-@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard", "standard_eq_forcing"])
 @pytest.mark.parametrize("nx,ny,nz,steps", CASES3)
 def test_parity_3d(orc, lbm, nx, ny, nz, steps, scheme):
     ph = I.PAPER_PHYS
@@ -122,7 +122,7 @@ def test_wb_flat_interface_fixed_point_3d(lbm, axis):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s"])
-@pytest.mark.parametrize("scheme", ["well_balanced", "standard"])
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard", "standard_eq_forcing"])
 def test_tilings_bit_identical_3d(orc, lbm, scheme, prec):
     """Every tiling of the fused 3-D step gives the same populations bit for
     bit: tiles of 32 x 8 or 32 x 16 nodes (ragged in x and y), chunks of 1 to

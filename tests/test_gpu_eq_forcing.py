@@ -1,6 +1,7 @@
 """GPU step of the standard LBE with the forcing term named after Eq. (5),
 F_i = (c_i - u).F feq_i / (cs2 rho), against the FP64 CPU oracle through
-the C ABI (scheme LBM_STANDARD_EQ_FORCING).
+the C ABI (scheme LBM_STANDARD_EQ_FORCING; its 3-D form is covered by
+tests/test_gpu_3d.py).
 
 Same bar as the other parity tests: max abs difference <= 1e-11 on f, rho and
 u after fixed step counts in FP64; the FP32-shifted bounds of the main step in
@@ -177,23 +178,10 @@ def test_switching_between_forcing_terms(orc, lbm, prec):
     assert np.abs(fg - fo).max() <= (TOL if prec == "fp64" else 5e-5)
 
 
-def test_eq_forcing_rejected_in_3d_and_batches(lbm):
-    """3-D contexts and batches run only the Eq. (5) and Eq. (26) forcing
-    terms: the other one is refused with LBM_EINVAL and leaves the state
-    as it was."""
+def test_eq_forcing_rejected_in_batches(lbm):
+    """Batches run only the Eq. (5) and Eq. (26) forcing terms: admitting a
+    lattice with the other one is refused with LBM_EINVAL."""
     ph = I.PAPER_PHYS
-    s = lbm.Solver(8, 8, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=4)
-    rho = np.full((4, 8, 8), 0.6)
-    with pytest.raises(lbm.LbmError) as e:
-        s.init(rho, scheme=EQF)
-    assert e.value.status == -1
-    s.init(rho, scheme="standard")
-    f0 = s.get_populations()
-    with pytest.raises(lbm.LbmError) as e:
-        s.step(1, EQF)
-    assert e.value.status == -1
-    assert np.array_equal(s.get_populations(), f0)
-    s.close()
     prob = I.with_size(I.PAPER_DROPLET, 32, 32)
     b = lbm.Batch(1 << 26, max_slots=4)
     prm = lbm.make_params(32, 32, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v)
