@@ -177,7 +177,9 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme,
  * per block (>= 4) and prefetch depth (rows of populations each thread keeps
  * in flight, 1..3).  3-D lattices (nz > 1): block width 256 or 512 threads
  * (tiles of 32 x 8 or 32 x 16 nodes), rows = z planes each block marches
- * through (>= 1), depth 1.  Any valid shape gives bit-identical populations.
+ * through (>= 1), depth = planes of populations in flight (1..3 with 256
+ * threads, 1..2 with 512; 1 is the fastest measured).  Any valid shape gives
+ * bit-identical populations.
  * 0 keeps the current value.  A new 2-D context starts from a default
  * chosen from the lattice size (64-wide strips with short chunks up to
  * 512 columns, 256-wide strips above).  lbm_get_tile reports the shape in
