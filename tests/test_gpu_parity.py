@@ -501,3 +501,45 @@ def test_flat_200x4_full_run_against_oracle(orc, lbm):
     s.close()
     print("flat_200x4 standard scheme: non-finite at step window ending %d" % k)
     assert k < 500
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard", "standard_eq_forcing"])
+def test_single_phase_limit(orc, lbm, scheme):
+    """beta = kappa = 0: mu vanishes, the WB force is zero and the standard
+    force is grad(cs2 rho) alone; a perturbed density with an initial shear
+    flow, 300 steps, against the oracle to 1e-11."""
+    from paper_2012_11075_amd.inputs import Physics
+    nx, ny, steps = 70, 45, 300
+    rng = np.random.default_rng(23)
+    rho0 = 1.0 + 0.05 * rng.uniform(-1, 1, (ny, nx))
+    ux0 = 0.03 * np.sin(2 * np.pi * np.arange(ny) / ny)[:, None] * np.ones((1, nx))
+    uy0 = np.zeros((ny, nx))
+    p = orc.Params(0.9, 0.0, 0.0, 1.0, 0.1)
+    fo = orc.step(scheme, p, orc.init(scheme, p, rho0, ux0, uy0), steps)
+    s = lbm.Solver(nx, ny, 0.9, 0.0, 0.0, 1.0, 0.1)
+    s.init(rho0, ux0, uy0, scheme=scheme)
+    s.step(steps, scheme)
+    fg = to_oracle(s.get_populations())
+    s.close()
+    assert np.abs(fg - fo).max() <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard", "standard_eq_forcing"])
+def test_uniform_state_at_rest_is_kept(lbm, scheme):
+    """A uniform density at rest is a fixed point of every scheme (no
+    gradient, f = feq): after 100 steps the WB populations are unchanged bit
+    for bit (f_0 = rho carries everything), the standard ones to round-off."""
+    nx, ny = 37, 29
+    ph = I.PAPER_PHYS
+    s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v)
+    s.init(np.full((ny, nx), 0.7), scheme=scheme)
+    f0 = s.get_populations()
+    s.step(100, scheme)
+    f1 = s.get_populations()
+    ob = s.observe(fields=())
+    s.close()
+    if scheme == "well_balanced":
+        assert np.array_equal(f0, f1)
+    else:
+        assert np.abs(f1 - f0).max() <= 1e-15
+    assert ob["max_u"] <= 1e-15
