@@ -237,3 +237,31 @@ def test_fp32_3d_scheme_switch_keeps_populations(lbm):
     c = s.get_populations()
     s.close()
     assert np.abs(b - a).max() <= 1.2e-7 and np.abs(c - a).max() <= 1.2e-7
+
+
+@pytest.mark.parametrize("scheme", ["well_balanced", "standard", "standard_eq_forcing"])
+def test_degenerate_cases_3d(orc, lbm, scheme):
+    """The single-phase limit beta = kappa = 0 (a perturbed density, 150
+    steps, against the oracle to 1e-11) and a uniform density at rest (a
+    fixed point: unchanged bit for bit under WB, to round-off otherwise)."""
+    nx, ny, nz = 21, 13, 11
+    rng = np.random.default_rng(29)
+    rho0 = 1.0 + 0.05 * rng.uniform(-1, 1, (nz, ny, nx))
+    p = orc.Params(0.9, 0.0, 0.0, 1.0, 0.1)
+    fo = orc.step3(scheme, p, orc.init3(scheme, p, rho0), 150)
+    s = lbm.Solver(nx, ny, 0.9, 0.0, 0.0, 1.0, 0.1, nz=nz)
+    s.init(rho0, scheme=scheme)
+    s.step(150, scheme)
+    assert np.abs(to_oracle(s.get_populations()) - fo).max() <= TOL
+    s.close()
+    ph = I.PAPER_PHYS
+    s = solver(lbm, nx, ny, nz, ph)
+    s.init(np.full((nz, ny, nx), 0.7), scheme=scheme)
+    f0 = s.get_populations()
+    s.step(60, scheme)
+    f1 = s.get_populations()
+    s.close()
+    if scheme == "well_balanced":
+        assert np.array_equal(f0, f1)
+    else:
+        assert np.abs(f1 - f0).max() <= 1e-15
