@@ -36,6 +36,9 @@ def main():
                     help="profile the 3-D (D3Q19) step on an N^3 droplet instead")
     ap.add_argument("--batch", type=int, default=0,
                     help="profile the batched launch over this many uneven instances instead")
+    ap.add_argument("--side", type=int, default=0,
+                    help="profile an N x N lattice with a separable density and the Sec. IV "
+                         "constants instead (the 4096^2 tile), e.g. 32768")
     args = ap.parse_args()
     import torch
     from paper_2012_11075_amd import inputs as I
@@ -53,6 +56,20 @@ def main():
         s.init(rho, scheme=args.scheme)
         print("profile_step: D3Q19 %d^3 %s %s tile=%s" % (n, args.precision, args.scheme,
                                                           s.get_tile()), flush=True)
+        s.step(args.steps, args.scheme)
+        torch.cuda.synchronize()
+        print("profile_step: %d steps done" % args.steps, flush=True)
+        calibrate(args, torch)
+        s.close()
+        return
+    if args.side:
+        n, ph = args.side, I.PAPER_PHYS
+        s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                       precision=args.precision)
+        s.set_tile(*tune.bench_tile(4096, 4096, args.precision))
+        s.init(I.separable_density(n, n, 17), scheme=args.scheme)
+        print("profile_step: %d^2 separable density %s %s tile=%s" % (n, args.precision, args.scheme,
+                                                                      s.get_tile()), flush=True)
         s.step(args.steps, args.scheme)
         torch.cuda.synchronize()
         print("profile_step: %d steps done" % args.steps, flush=True)
