@@ -116,6 +116,11 @@ typedef struct {
   double mass;            /* sum over nodes of rho */
   double kinetic_energy;  /* (1/2) sum rho |u|^2, the E(t) of Sec. IV.A */
   int32_t nonfinite;      /* 1 if any rho or u is NaN/Inf, or rho <= 0 */
+  double momentum[3];     /* sum over nodes of rho u (x, y, z; z is 0 in 2-D).
+                           * Eq. (2) moves the populations' momentum by the
+                           * summed force of Eq. (6)/(25) each step, which
+                           * vanishes in the continuum but not on the lattice
+                           * away from equilibrium */
 } lbm_observation;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -63,6 +63,10 @@
 #include <omp.h>
 #endif
 
+/* Lattices smaller than this run their loops on one thread (thread start-up
+ * would cost more than the work); the arithmetic is the same either way. */
+#define ORC_OMP_MIN_NODES 16384L
+
 #define Q 9
 #define CS2 (1.0 / 3.0)
 #define DIM 2.0
@@ -177,7 +181,7 @@ void orc_forcing(int scheme, double ux, double uy, double Fx, double Fy,
 /* Isotropic central gradient, grad(phi)(x) = (1/cs2) sum_i w_i c_i phi(x+c_i),
  * periodic. */
 void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= ORC_OMP_MIN_NODES)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
       double sx = 0.0, sy = 0.0;
@@ -195,7 +199,7 @@ void orc_gradient(int nx, int ny, const double *phi, double *gx, double *gy) {
 /* Isotropic Laplacian, lap(phi)(x) = (2/cs2) sum_i w_i [phi(x+c_i) - phi(x)],
  * periodic. */
 void orc_laplacian(int nx, int ny, const double *phi, double *lap) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= ORC_OMP_MIN_NODES)
   for (int y = 0; y < ny; ++y) {
     for (int x = 0; x < nx; ++x) {
       double c = phi[y * nx + x];
@@ -328,7 +332,7 @@ void orc_step(int scheme, const orc_params *p, int nx, int ny, double *f,
 
   for (int64_t s = 0; s < nsteps; ++s) {
     orc_macro(scheme, p, nx, ny, f, rho, ux, uy, mu, Fx, Fy, gr, gry);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= ORC_OMP_MIN_NODES)
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         size_t k = (size_t)y * nx + x;
@@ -366,7 +370,9 @@ static inline void neumaier(double *sum, double *comp, double v) {
 /* Scalar observables of the state f:
  *   out[0] = max |u|, out[1] = total mass sum rho (compensated),
  *   out[2] = kinetic energy E = (1/2) sum rho |u|^2 (Sec. IV.A, compensated),
- *   out[3] = 1 if any rho, u is NaN/Inf or rho <= 0, else 0. */
+ *   out[3] = 1 if any rho, u is NaN/Inf or rho <= 0, else 0,
+ *   out[4], out[5] = total momentum sum rho u_x, sum rho u_y (compensated;
+ *   with u the half-force velocity of Eq. 4). */
 void orc_observe(int scheme, const orc_params *p, int nx, int ny,
                  const double *f, double *out) {
   size_t n = (size_t)nx * ny;
@@ -374,6 +380,7 @@ void orc_observe(int scheme, const orc_params *p, int nx, int ny,
   double *rho = buf, *ux = buf + n, *uy = buf + 2 * n;
   orc_fields(scheme, p, nx, ny, f, rho, ux, uy, NULL);
   double umax = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0, bad = 0.0;
+  double pxs = 0.0, pxc = 0.0, pys = 0.0, pyc = 0.0;
   for (size_t k = 0; k < n; ++k) {
     double u2 = ux[k] * ux[k] + uy[k] * uy[k];
     double um = sqrt(u2);
@@ -381,11 +388,15 @@ void orc_observe(int scheme, const orc_params *p, int nx, int ny,
     if (um > umax) umax = um;
     neumaier(&ms, &mc, rho[k]);
     neumaier(&es, &ec, 0.5 * rho[k] * u2);
+    neumaier(&pxs, &pxc, rho[k] * ux[k]);
+    neumaier(&pys, &pyc, rho[k] * uy[k]);
   }
   out[0] = umax;
   out[1] = ms + mc;
   out[2] = es + ec;
   out[3] = bad;
+  out[4] = pxs + pxc;
+  out[5] = pys + pyc;
   free(buf);
 }
 

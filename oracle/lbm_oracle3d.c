@@ -28,6 +28,10 @@
 #include <omp.h>
 #endif
 
+/* Lattices smaller than this run their loops on one thread (thread start-up
+ * would cost more than the work); the arithmetic is the same either way. */
+#define ORC_OMP_MIN_NODES 16384L
+
 #define Q3 19
 #define CS2 (1.0 / 3.0)
 #define DIM 3.0
@@ -116,7 +120,7 @@ static inline size_t idx3(int x, int y, int z, int nx, int ny) {
 /* Isotropic central gradient, periodic. */
 void orc3_gradient(int nx, int ny, int nz, const double *phi, double *gx, double *gy,
                    double *gz) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -136,7 +140,7 @@ void orc3_gradient(int nx, int ny, int nz, const double *phi, double *gx, double
 
 /* Isotropic Laplacian, periodic. */
 void orc3_laplacian(int nx, int ny, int nz, const double *phi, double *lap) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
@@ -211,7 +215,7 @@ void orc3_step(int scheme, const orc3_params *p, int nx, int ny, int nz, double 
   double omega = 1.0 / p->tau, fpre = 1.0 - 0.5 / p->tau;
   for (int64_t s = 0; s < nsteps; ++s) {
     orc3_macro(scheme, p, nx, ny, nz, f, rho, ux, uy, uz, mu, Fx, Fy, Fz, grx, gry, grz);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -245,7 +249,8 @@ static inline void neumaier3(double *sum, double *comp, double v) {
 }
 
 /* out[0] max|u|, out[1] mass (compensated), out[2] kinetic energy
- * (compensated), out[3] 1 if any rho or u is non-finite or rho <= 0. */
+ * (compensated), out[3] 1 if any rho or u is non-finite or rho <= 0,
+ * out[4..6] total momentum sum rho u (compensated, half-force u of Eq. 4). */
 void orc3_observe(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *f,
                   double *out) {
   size_t n = (size_t)nx * ny * nz;
@@ -253,6 +258,7 @@ void orc3_observe(int scheme, const orc3_params *p, int nx, int ny, int nz, cons
   orc3_macro(scheme, p, nx, ny, nz, f, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n,
              b + 6 * n, b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n);
   double umax = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0, bad = 0.0;
+  double ps[3] = {0.0, 0.0, 0.0}, pc[3] = {0.0, 0.0, 0.0};
   for (size_t k = 0; k < n; ++k) {
     double r = b[k], u2 = b[n + k] * b[n + k] + b[2 * n + k] * b[2 * n + k] + b[3 * n + k] * b[3 * n + k];
     double um = sqrt(u2);
@@ -260,10 +266,12 @@ void orc3_observe(int scheme, const orc3_params *p, int nx, int ny, int nz, cons
     if (um > umax) umax = um;
     neumaier3(&ms, &mc, r);
     neumaier3(&es, &ec, 0.5 * r * u2);
+    for (int a = 0; a < 3; ++a) neumaier3(&ps[a], &pc[a], r * b[(size_t)(a + 1) * n + k]);
   }
   out[0] = umax;
   out[1] = ms + mc;
   out[2] = es + ec;
   out[3] = bad;
+  for (int a = 0; a < 3; ++a) out[4 + a] = ps[a] + pc[a];
   free(b);
 }

@@ -263,12 +263,14 @@ def step(scheme, p: Params, f: np.ndarray, n: int = 1) -> np.ndarray:
 
 
 def observe(scheme, p: Params, f: np.ndarray) -> dict:
-    """max|u|, total mass, kinetic energy E (Sec. IV.A) and a non-finite flag."""
+    """max|u|, total mass, kinetic energy E (Sec. IV.A), a non-finite flag
+    and the total momentum sum rho u (u the half-force velocity of Eq. 4)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     ny, nx, _ = f.shape
-    out = np.zeros(4)
+    out = np.zeros(6)
     _load().orc_observe(_scheme(scheme), ctypes.byref(p.c()), nx, ny, _ptr(f), _ptr(out))
-    return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3])}
+    return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3]),
+            "momentum": (out[4], out[5])}
 
 
 # --------------------------------------------------------- steady-state reads
@@ -392,6 +394,7 @@ def step3(scheme, p: Params, f: np.ndarray, n: int = 1) -> np.ndarray:
 def observe3(scheme, p: Params, f: np.ndarray) -> dict:
     f = np.ascontiguousarray(f, dtype=np.float64)
     nz, ny, nx, _ = f.shape
-    out = np.zeros(4)
+    out = np.zeros(7)
     _load().orc3_observe(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
-    return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3])}
+    return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3]),
+            "momentum": (out[4], out[5], out[6])}

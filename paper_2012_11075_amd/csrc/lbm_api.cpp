@@ -110,7 +110,7 @@ Layout make_layout(const lbm_params& p) {
   L.off_b = L.off_a + L.state_bytes;
   L.off_staging = L.off_b + L.state_bytes;
   L.off_partials = L.off_staging + L.staging_bytes;
-  L.total = L.off_partials + align_up(L.partial_count * 4 * sizeof(double), ALIGN);
+  L.total = L.off_partials + align_up(L.partial_count * lbmk::NPART * sizeof(double), ALIGN);
   return L;
 }
 
@@ -513,6 +513,41 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
 
 namespace {
 
+// Fixed-order finish of `count` per-tile records (lbmk::NPART doubles each):
+// max of max|u| and of the non-finite flag, compensated (Neumaier) sums of
+// mass, kinetic energy and momentum, tiles in order.  Returns true when the
+// state holds a non-finite value or rho <= 0.
+bool finish_partials(const double* part, size_t count, int64_t step, lbm_observation* obs) {
+  double umax = 0.0, bad = 0.0;
+  double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, comp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  auto neumaier = [](double& s, double& c, double v) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  };
+  for (size_t b = 0; b < count; ++b) {
+    const double* q = part + lbmk::NPART * b;
+    umax = std::max(umax, q[0]);
+    bad = std::max(bad, q[3]);
+    neumaier(sum[0], comp[0], q[1]);
+    neumaier(sum[1], comp[1], q[2]);
+    for (int a = 0; a < 3; ++a) neumaier(sum[2 + a], comp[2 + a], q[4 + a]);
+    if (!is_finite(q[1]) || !is_finite(q[2])) bad = 1.0;
+  }
+  if (obs) {
+    obs->step = step;
+    obs->max_u = umax;
+    obs->mass = sum[0] + comp[0];
+    obs->kinetic_energy = sum[1] + comp[1];
+    obs->nonfinite = bad != 0.0;
+    for (int a = 0; a < 3; ++a) obs->momentum[a] = sum[2 + a] + comp[2 + a];
+  }
+  return bad != 0.0;
+}
+
 lbm_status observe_impl(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, double* mu,
                         lbm_observation* obs) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
@@ -551,35 +586,12 @@ lbm_status observe_impl(lbm_ctx* c, double* rho, double* ux, double* uy, double*
   if (uy) HIPCHK(c, hipMemcpyAsync(uy, st + 2 * n, fb, hipMemcpyDeviceToHost, c->stream));
   if (uz) HIPCHK(c, hipMemcpyAsync(uz, st + 3 * n, fb, hipMemcpyDeviceToHost, c->stream));
   if (mu) HIPCHK(c, hipMemcpyAsync(mu, st_mu, fb, hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> part((size_t)nb * 4);
+  std::vector<double> part((size_t)nb * lbmk::NPART);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->partials(), part.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  // fixed-order finish: blocks in order, compensated sums
-  double umax = 0.0, bad = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0;
-  auto neumaier = [](double& s, double& comp, double v) {
-    const double t = s + v;
-    if (std::fabs(s) >= std::fabs(v))
-      comp += (s - t) + v;
-    else
-      comp += (v - t) + s;
-    s = t;
-  };
-  for (int b = 0; b < nb; ++b) {
-    umax = std::max(umax, part[4 * b]);
-    neumaier(ms, mc, part[4 * b + 1]);
-    neumaier(es, ec, part[4 * b + 2]);
-    bad = std::max(bad, part[4 * b + 3]);
-    if (!is_finite(part[4 * b + 1]) || !is_finite(part[4 * b + 2])) bad = 1.0;
-  }
-  if (obs) {
-    obs->step = c->step;
-    obs->max_u = umax;
-    obs->mass = ms + mc;
-    obs->kinetic_energy = es + ec;
-    obs->nonfinite = bad != 0.0;
-  }
-  if (bad != 0.0) return fail(c, LBM_ENONFINITE, "state holds NaN/Inf or rho <= 0");
+  const bool bad = finish_partials(part.data(), (size_t)nb, c->step, obs);
+  if (bad) return fail(c, LBM_ENONFINITE, "state holds NaN/Inf or rho <= 0");
   return LBM_OK;
 }
 
@@ -885,7 +897,7 @@ lbm_status upload_tables(lbm_batch* b) {
         d.buf[1] = c->buf(1);
         d.cur = c->cur;
         d.tile0 = tiles;
-        d.partials = b->partials() + 4 * (part + tiles);
+        d.partials = b->partials() + lbmk::NPART * (part + tiles);
         sl.part_index = part + tiles;
         sl.tiles = c->tl.blocks();
         tiles += sl.tiles;
@@ -993,7 +1005,7 @@ size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
   return kGroups * kLanes * stride +
-         align_up(part_capacity(arena_bytes) * 4 * sizeof(double), ALIGN);
+         align_up(part_capacity(arena_bytes) * lbmk::NPART * sizeof(double), ALIGN);
 }
 
 lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* stream,
@@ -1165,7 +1177,7 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
       BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g, lane),
                                  b->tiles_of[lane][g], 0, b->stream));
     }
-  std::vector<double> part(total * 4);
+  std::vector<double> part(total * lbmk::NPART);
   BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),
                          hipMemcpyDeviceToHost, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
@@ -1174,30 +1186,11 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (size_t i = 0; i < b->slots.size(); ++i) {
     lbm_batch::Slot& s = b->slots[i];
     if (s.status != LBM_SLOT_ACTIVE) continue;
-    double umax = 0.0, bad = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0;
-    auto neumaier = [](double& sum, double& comp, double v) {
-      const double t = sum + v;
-      if (std::fabs(sum) >= std::fabs(v))
-        comp += (sum - t) + v;
-      else
-        comp += (v - t) + sum;
-      sum = t;
-    };
-    for (int t = 0; t < s.tiles; ++t) {
-      const double* q = &part[4 * (s.part_index + t)];
-      umax = std::max(umax, q[0]);
-      neumaier(ms, mc, q[1]);
-      neumaier(es, ec, q[2]);
-      bad = std::max(bad, q[3]);
-      if (!is_finite(q[1]) || !is_finite(q[2])) bad = 1.0;
-    }
-    s.last.step = s.ctx->step;
-    s.last.max_u = umax;
-    s.last.mass = ms + mc;
-    s.last.kinetic_energy = es + ec;
-    s.last.nonfinite = bad != 0.0;
+    const bool bad = finish_partials(&part[lbmk::NPART * s.part_index], (size_t)s.tiles,
+                                     s.ctx->step, &s.last);
+    const double umax = s.last.max_u;
     int st = LBM_SLOT_ACTIVE;
-    if (bad != 0.0)
+    if (bad)
       st = LBM_SLOT_DIVERGED;
     else if (s.tol > 0.0 && umax < s.tol)
       st = LBM_SLOT_CONVERGED;

@@ -31,11 +31,62 @@ struct Physics {
 struct Tiling {
   int block;   // threads per block (multiple of 64)
   int rows;    // output rows per block
-  int strips;  // blocks across x: ceil(nx / (block - 4))
+  int strips;  // blocks across x: ceil(nx / block)
   int chunks;  // blocks along y: ceil(ny / rows)
   int depth;   // rows of populations in flight per thread (1..3)
   int blocks() const { return strips * chunks; }
 };
+
+// Per-block (per-tile) record of an observe pass, NPART doubles: max|u|,
+// mass, kinetic energy E, non-finite flag, momentum x, y, z (z is 0 in 2-D),
+// and one unused slot.
+constexpr int NPART = 8;
+
+// Node sums of one thread -> the block's NPART-double record at `out`:
+// butterfly within each 64-lane wave, then the waves in order (a fixed
+// summation order).  Every thread of the block must call it.
+struct NodeSums {
+  double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+};
+template <int NW>
+__device__ __forceinline__ void write_block_partials(NodeSums v, double* out) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.umax = fmax(v.umax, __shfl_xor(v.umax, off));
+    v.bad = fmax(v.bad, __shfl_xor(v.bad, off));
+    v.mass += __shfl_xor(v.mass, off);
+    v.ekin += __shfl_xor(v.ekin, off);
+    v.px += __shfl_xor(v.px, off);
+    v.py += __shfl_xor(v.py, off);
+    v.pz += __shfl_xor(v.pz, off);
+  }
+  __shared__ double red[NW][NPART];
+  const int t = threadIdx.x, wv = t >> 6;
+  if ((t & 63) == 0) {
+    red[wv][0] = v.umax;
+    red[wv][1] = v.mass;
+    red[wv][2] = v.ekin;
+    red[wv][3] = v.bad;
+    red[wv][4] = v.px;
+    red[wv][5] = v.py;
+    red[wv][6] = v.pz;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double r[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < NW; ++w) {
+      r[0] = fmax(r[0], red[w][0]);
+      r[3] = fmax(r[3], red[w][3]);
+      r[1] += red[w][1];
+      r[2] += red[w][2];
+      r[4] += red[w][4];
+      r[5] += red[w][5];
+      r[6] += red[w][6];
+    }
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) out[k] = r[k];
+  }
+}
 
 // Outputs of an observe pass (all optional).
 struct ObserveOut {
@@ -43,7 +94,7 @@ struct ObserveOut {
   double* ux;
   double* uy;
   double* mu;
-  double* partials;  // 4 doubles per block: max|u|, mass, E, nonfinite flag
+  double* partials;  // NPART doubles per block (see NPART)
 };
 
 // STANDARD_EQF: the standard LBE (equilibrium Eq. 3, force Eq. 6) with the
@@ -57,7 +108,7 @@ struct BatchSlot {
   Physics ph;
   Tiling tl;
   void* buf[2];      // the two population copies
-  double* partials;  // 4 doubles per tile, for observe launches
+  double* partials;  // NPART doubles per tile, for observe launches
   int cur;           // buffer holding the state at parity 0
   int tile0;         // first work item of this slot in the concatenated list
 };

@@ -223,7 +223,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
     if (hl) dst = fin[hplane + (long long)wrapy(row_of(k) - hcy) * g.pitch + hsx];
   };
 
-  double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
+  NodeSums acc;
 
   // One row step: prefetch row k+D into `nxt`; publish rho of row k (`cur`,
   // which then parks in LDS for two rows); mu of row k-1; update the node of
@@ -304,10 +304,12 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
         if (obs.mu) obs.mu[o] = (double)ms[m0][t + 1];
         const double u2 = dux * dux + duy * duy;
         const double um = sqrt(u2);
-        if (!(isfinite(drho) && drho > 0.0 && isfinite(um))) bad = 1.0;
-        umax = fmax(umax, um);
-        mass += drho;
-        ekin += 0.5 * drho * u2;
+        if (!(isfinite(drho) && drho > 0.0 && isfinite(um))) acc.bad = 1.0;
+        acc.umax = fmax(acc.umax, um);
+        acc.mass += drho;
+        acc.ekin += 0.5 * drho * u2;
+        acc.px += drho * dux;
+        acc.py += drho * duy;
       }
     }
   };
@@ -346,39 +348,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
     }
   }
 
-  if (OBSERVE && obs.partials) {
-    // wave butterfly, then waves in order: a fixed summation order
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      umax = fmax(umax, __shfl_xor(umax, off));
-      bad = fmax(bad, __shfl_xor(bad, off));
-      mass += __shfl_xor(mass, off);
-      ekin += __shfl_xor(ekin, off);
-    }
-    __shared__ double red[BW / 64][4];
-    const int wv = t >> 6;
-    if ((t & 63) == 0) {
-      red[wv][0] = umax;
-      red[wv][1] = mass;
-      red[wv][2] = ekin;
-      red[wv][3] = bad;
-    }
-    __syncthreads();
-    if (t == 0) {
-      double a = 0.0, m = 0.0, e = 0.0, z = 0.0;
-      for (int w = 0; w < BW / 64; ++w) {
-        a = fmax(a, red[w][0]);
-        m += red[w][1];
-        e += red[w][2];
-        z = fmax(z, red[w][3]);
-      }
-      double* out = obs.partials + 4LL * tile;
-      out[0] = a;
-      out[1] = m;
-      out[2] = e;
-      out[3] = z;
-    }
-  }
+  if (OBSERVE && obs.partials) write_block_partials<BW / 64>(acc, obs.partials + (long long)NPART * tile);
 }
 
 // Tiles are assigned so that each XCD (blocks b, b+8, ...) walks a contiguous
@@ -545,7 +515,7 @@ __global__ void __launch_bounds__(S4X * S4Y)
   }
   __syncthreads();
   const int x = x0 + tx, y = y0 + ty;
-  double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
+  NodeSums acc;
   if (x < g.nx && y < g.ny) {
     R f[Q];
 #pragma unroll
@@ -568,43 +538,16 @@ __global__ void __launch_bounds__(S4X * S4Y)
     if (obs.uy) obs.uy[o] = uy;
     const double u2 = ux * ux + uy * uy;
     const double um = sqrt(u2);
-    if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
-    umax = um;
-    mass = r;
-    ekin = 0.5 * r * u2;
+    if (!(isfinite(r) && r > 0.0 && isfinite(um))) acc.bad = 1.0;
+    acc.umax = um;
+    acc.mass = r;
+    acc.ekin = 0.5 * r * u2;
+    acc.px = r * ux;
+    acc.py = r * uy;
   }
-  if (obs.partials) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      umax = fmax(umax, __shfl_xor(umax, off));
-      bad = fmax(bad, __shfl_xor(bad, off));
-      mass += __shfl_xor(mass, off);
-      ekin += __shfl_xor(ekin, off);
-    }
-    __shared__ double red[S4Y][4];
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-      red[wv][0] = umax;
-      red[wv][1] = mass;
-      red[wv][2] = ekin;
-      red[wv][3] = bad;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0.0, m = 0.0, e = 0.0, z = 0.0;
-      for (int w = 0; w < S4Y; ++w) {
-        a = fmax(a, red[w][0]);
-        m += red[w][1];
-        e += red[w][2];
-        z = fmax(z, red[w][3]);
-      }
-      double* out = obs.partials + 4LL * ((long long)blockIdx.y * gridDim.x + blockIdx.x);
-      out[0] = a;
-      out[1] = m;
-      out[2] = e;
-      out[3] = z;
-    }
-  }
+  if (obs.partials)
+    write_block_partials<S4Y * S4X / 64>(
+        acc, obs.partials + (long long)NPART * ((long long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // Fused step of the force-stencil variant (FP64): one HBM pass per step, as

@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256)
 constexpr int T3X = 32, T3Y = 4, T3Z = 2;  // observe block (threads)
 
 // Fields and per-block partials (max|u|, mass, kinetic energy, non-finite
-// flag) of the state f, from dense rho and mu.
+// flag, momentum) of the state f, from dense rho and mu.
 template <typename T, int SCHEME>
 __global__ void __launch_bounds__(T3X * T3Y * T3Z)
     observe3_kernel(Geometry3 g, const Global<T>* __restrict__ fin,
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
   }
   __syncthreads();
   const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-  double umax = 0.0, mass = 0.0, ekin = 0.0, bad = 0.0;
+  NodeSums acc;
   if (x < g.nx && y < g.ny && z < g.nz) {
     R f[Q3];
 #pragma unroll
@@ -484,44 +484,17 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
     if (obs.uz) obs.uz[o] = uz;
     const double u2 = ux * ux + uy * uy + uz * uz;
     const double um = sqrt(u2);
-    if (!(isfinite(r) && r > 0.0 && isfinite(um))) bad = 1.0;
-    umax = um;
-    mass = r;
-    ekin = 0.5 * r * u2;
+    if (!(isfinite(r) && r > 0.0 && isfinite(um))) acc.bad = 1.0;
+    acc.umax = um;
+    acc.mass = r;
+    acc.ekin = 0.5 * r * u2;
+    acc.px = r * ux;
+    acc.py = r * uy;
+    acc.pz = r * uz;
   }
   if (obs.partials) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      umax = fmax(umax, __shfl_xor(umax, off));
-      bad = fmax(bad, __shfl_xor(bad, off));
-      mass += __shfl_xor(mass, off);
-      ekin += __shfl_xor(ekin, off);
-    }
-    constexpr int NW = T3X * T3Y * T3Z / 64;
-    __shared__ double red[NW][4];
-    const int wv = tid >> 6;
-    if ((tid & 63) == 0) {
-      red[wv][0] = umax;
-      red[wv][1] = mass;
-      red[wv][2] = ekin;
-      red[wv][3] = bad;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double a = 0.0, m = 0.0, e = 0.0, zb = 0.0;
-      for (int w = 0; w < NW; ++w) {
-        a = fmax(a, red[w][0]);
-        m += red[w][1];
-        e += red[w][2];
-        zb = fmax(zb, red[w][3]);
-      }
-      const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-      double* out = obs.partials + 4 * b;
-      out[0] = a;
-      out[1] = m;
-      out[2] = e;
-      out[3] = zb;
-    }
+    const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    write_block_partials<T3X * T3Y * T3Z / 64>(acc, obs.partials + (long long)NPART * b);
   }
 }
 

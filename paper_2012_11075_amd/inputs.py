@@ -156,9 +156,11 @@ PAPER_DROPLET_4096 = Problem("paper_droplet_4096", 4096, 4096, PAPER_PHYS, "drop
 DROPLET_512_RATIO100 = Problem("droplet_512_ratio100", 512, 512, THROUGHPUT_PHYS, "droplet",
                                5.0, 128.0, 0.0, 1e-3, "mul", 3, 1_000)
 # The paper's own runs (Sec. IV.A, IV.B).
-# Sec. IV.A writes the perturbed profile as rho(y) = (1 + eps r) rho_0(y): one
-# random number per row.
-PAPER_FLAT = Problem("paper_flat_21x101", 21, 101, PAPER_PHYS, "slab_y", 4.0, 25.0, 75.0,
+# Sec. IV.A puts the liquid on the rows 25 <= y <= 75: the interfaces of
+# Eq. (38) sit half-way between the last liquid and the first vapour row,
+# y1 = 24.5 and y2 = 75.5.  It writes the perturbed profile as
+# rho(y) = (1 + eps r) rho_0(y): one random number per row.
+PAPER_FLAT = Problem("paper_flat_21x101", 21, 101, PAPER_PHYS, "slab_y", 4.0, 24.5, 75.5,
                      1e-2, "mul_normal", 11, 0)
 PAPER_DROPLET = Problem("paper_droplet_100", 100, 100, PAPER_PHYS, "droplet", 4.0, 25.0, 0.0,
                         1e-2, "mul", 12, 0)

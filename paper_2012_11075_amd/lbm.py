@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
 
 class Observation(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("max_u", ctypes.c_double), ("mass", ctypes.c_double),
-                ("kinetic_energy", ctypes.c_double), ("nonfinite", ctypes.c_int32)]
+                ("kinetic_energy", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+                ("momentum", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -111,6 +112,14 @@ def load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def _obs_dict(ob: Observation, nz: int) -> dict:
+    """Scalars of an observation; momentum has two components in 2-D."""
+    mom = tuple(ob.momentum[:3 if nz else 2])
+    return {"step": ob.step, "max_u": ob.max_u, "mass": ob.mass,
+            "kinetic_energy": ob.kinetic_energy, "nonfinite": bool(ob.nonfinite),
+            "momentum": mom}
 
 
 def _dptr(a: Optional[np.ndarray]):
@@ -217,8 +226,7 @@ class Solver:
                                       _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(obs))
         if st != -4 or raise_nonfinite:
             self._check(st)
-        out.update(step=obs.step, max_u=obs.max_u, mass=obs.mass,
-                   kinetic_energy=obs.kinetic_energy, nonfinite=bool(obs.nonfinite))
+        out.update(_obs_dict(obs, self.nz))
         return out
 
     def get_populations(self) -> np.ndarray:
@@ -324,9 +332,7 @@ class Batch:
     def info(self, slot: int):
         st, ob = ctypes.c_int32(), Observation()
         self._check(self.lib.lbm_batch_slot_info(self.b, int(slot), ctypes.byref(st), ctypes.byref(ob)))
-        return SLOT_STATUS[st.value], {"step": ob.step, "max_u": ob.max_u, "mass": ob.mass,
-                                       "kinetic_energy": ob.kinetic_energy,
-                                       "nonfinite": bool(ob.nonfinite)}
+        return SLOT_STATUS[st.value], _obs_dict(ob, 0)
 
     def fetch(self, slot: int, fields=("rho", "ux", "uy", "mu")) -> dict:
         ny, nx = self.shapes[slot]
@@ -336,8 +342,7 @@ class Batch:
                                       _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(ob))
         if st not in (0, -4):
             self._check(st)
-        out.update(step=ob.step, max_u=ob.max_u, mass=ob.mass, kinetic_energy=ob.kinetic_energy,
-                   nonfinite=bool(ob.nonfinite))
+        out.update(_obs_dict(ob, 0))
         return out
 
     def get_populations(self, slot: int) -> np.ndarray:

@@ -63,6 +63,8 @@ def test_parity_3d(orc, lbm, nx, ny, nz, steps, scheme):
     # |dE| <= TOL sqrt(2 mass E) + TOL^2 mass / 2 (plus the rho error's share)
     E, M = oo["kinetic_energy"], oo["mass"]
     assert abs(ob["kinetic_energy"] - E) <= TOL * np.sqrt(2 * M * E) + 0.5 * TOL ** 2 * M + 1e-9 * E
+    assert len(ob["momentum"]) == 3
+    np.testing.assert_allclose(ob["momentum"], oo["momentum"], rtol=0, atol=TOL * M + 1e-12)
 
 
 def test_initial_velocity_3d(orc, lbm):

@@ -109,6 +109,18 @@ def test_batch_fp64_slots_match_oracle(orc, lbm):
         assert np.abs(fg - fo).max() <= 1e-11
         ob = b.fetch(sl)
         assert ob["step"] == 300
+        oo = orc.observe(s, op, fo)
+        np.testing.assert_allclose(ob["momentum"], oo["momentum"], rtol=0, atol=1e-11 * oo["mass"])
+    # the poll's per-slot scalars come from the batched observe launch and its
+    # fixed-order finish; they agree with the single-lattice observe of fetch
+    b.poll()
+    for sl in slots:
+        st, info = b.info(sl)
+        ob = b.fetch(sl, fields=())
+        assert info["step"] == ob["step"] == 300
+        for k in ("max_u", "mass", "kinetic_energy"):
+            assert abs(info[k] - ob[k]) <= 1e-12 * max(1.0, abs(ob[k])), (k, info[k], ob[k])
+        np.testing.assert_allclose(info["momentum"], ob["momentum"], rtol=0, atol=1e-12 * ob["mass"])
     b.close()
 
 

@@ -65,6 +65,11 @@ def compare(orc, L, prob, scheme, steps, tile=None):
     assert np.abs(ob["ux"] - uxo).max() <= TOL
     assert np.abs(ob["uy"] - uyo).max() <= TOL
     assert np.abs(ob["mu"] - muo).max() <= 1e-9 * max(1.0, np.abs(muo).max())
+    # total momentum sum rho u: each node's rho u is within ~TOL (rho + |u|) of
+    # the oracle's, so the sums agree to TOL times the mass (plus round-off)
+    oo = orc.observe(scheme, p, fo)
+    dP = np.abs(np.array(ob["momentum"]) - np.array(oo["momentum"])).max()
+    assert dP <= TOL * oo["mass"] + 1e-12, (ob["momentum"], oo["momentum"])
     return fo, ob
 
 
@@ -225,6 +230,8 @@ def test_observe_scalars(orc, lbm):
     assert abs(ob["mass"] - oo["mass"]) <= 1e-12 * oo["mass"]
     assert abs(ob["kinetic_energy"] - oo["kinetic_energy"]) <= 1e-9 * oo["kinetic_energy"]
     assert not ob["nonfinite"]
+    assert len(ob["momentum"]) == 2 and np.abs(oo["momentum"]).max() > 1e-9
+    np.testing.assert_allclose(ob["momentum"], oo["momentum"], rtol=0, atol=TOL * oo["mass"])
 
 
 def test_mass_conserved_long_run(lbm):
