@@ -158,6 +158,26 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t n, lbm_scheme scheme);
 lbm_status lbm_observe(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* mu,
                        lbm_observation* obs);
 
+/* For callers that cannot allocate memory or wait on the host (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the scalars of lbm_observe without allocating anything and without
+ * synchronizing.  Enqueues, on the context's stream, the observe pass and a
+ * fixed-order finish whose result is bit-identical to lbm_observe's scalars,
+ * and writes LBM_NOALLOC_DOUBLES doubles to `dev_out`, caller-owned DEVICE
+ * memory: max|u|, mass, kinetic energy, non-finite flag (1.0 / 0.0),
+ * momentum x, y, z (z = 0), and 0.  Read them after synchronizing the stream;
+ * a non-finite state is reported in dev_out[3], not by the return status.
+ * The per-tile records live in a file-scope device array of the library
+ * (8 MiB, at most 131072 tiles: the context's tiling must fit, else
+ * LBM_EINVAL), one copy per GPU, held until the process ends; its device
+ * address is looked up once per GPU at the first call, so call with the
+ * context's device current.  Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (different streams or threads) race.  2-D
+ * lattices with the central force stencil only (others: LBM_EINVAL);
+ * LBM_ESTATE before lbm_init. */
+#define LBM_NOALLOC_DOUBLES 8
+lbm_status lbm_observe_noalloc(lbm_ctx* ctx, double* dev_out);
+
 /* 3-D forms of lbm_init and lbm_observe with the third velocity component
  * (D3Q19 lattices; on a 2-D lattice uz must be NULL and they act as
  * lbm_init / lbm_observe).  lbm_init3d takes ux, uy and uz together or none

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -607,6 +608,66 @@ lbm_status lbm_observe(lbm_ctx* c, double* rho, double* ux, double* uy, double* 
 lbm_status lbm_observe3d(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, double* mu,
                          lbm_observation* obs) {
   return observe_impl(c, rho, ux, uy, uz, mu, obs);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reduction records of lbm_observe_noalloc: one record of lbmk::NPART
+// doubles per tile of the observe launch, kNoallocTiles at most (8 MiB).
+// Every GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress (noalloc_scratch below).
+constexpr int kNoallocTiles = 131072;
+static __device__ __align__(256) double scratch[(size_t)kNoallocTiles * lbmk::NPART];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+lbm_status noalloc_scratch(lbm_ctx* c, double** out) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, LBM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(c, LBM_EHIP, "hipGetSymbolAddress returned no address");
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_observe_noalloc(lbm_ctx* c, double* dev_out) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!dev_out) return fail(c, LBM_EINVAL, "dev_out is NULL");
+  if (c->d3() || c->prm.force_stencil != 0)
+    return fail(c, LBM_EINVAL,
+                "lbm_observe_noalloc covers 2-D lattices with the central force stencil");
+  const long long nb = c->tl.blocks();
+  if (nb > kNoallocTiles)
+    return fail(c, LBM_EINVAL,
+                "lbm_observe_noalloc holds at most " + std::to_string(kNoallocTiles) +
+                    " tiles; this tiling has " + std::to_string(nb) + " (use larger tiles)");
+  if (!c->initialised) return fail(c, LBM_ESTATE, "lbm_observe_noalloc before lbm_init");
+  double* part = nullptr;
+  lbm_status st = noalloc_scratch(c, &part);
+  if (st != LBM_OK) return st;
+  // every tile writes its whole record, so nothing needs clearing first
+  const lbmk::ObserveOut o{nullptr, nullptr, nullptr, nullptr, part};
+  HIPCHK(c, lbmk::launch_observe(c->storage(), c->scheme, c->L.g, make_physics(c->prm, c->scheme),
+                                 c->tl, c->state(), o, c->stream));
+  HIPCHK(c, lbmk::launch_finish_partials(part, (int)nb, dev_out, c->stream));
+  return LBM_OK;
 }
 
 lbm_status lbm_get_populations(lbm_ctx* c, double* f) {

@@ -136,6 +136,11 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,
                           const Tiling& t, const void* f, const ObserveOut& o, hipStream_t s);
 
+// Fixed-order finish of `count` per-tile records on the device, into the
+// NPART doubles at `out`: the same order and compensated (Neumaier) sums as
+// the host finish of lbm_observe, so the results are bit-identical.
+hipError_t launch_finish_partials(const double* part, int count, double* out, hipStream_t s);
+
 // f = feq(rho, u) - shift, from dense device fields (ux, uy may be null).
 hipError_t launch_init(int storage, int scheme, const Geometry& g, const Physics& ph,
                        const double* rho, const double* ux, const double* uy, void* f,

@@ -351,6 +351,40 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
   if (OBSERVE && obs.partials) write_block_partials<BW / 64>(acc, obs.partials + (long long)NPART * tile);
 }
 
+// One thread finishes the per-tile records in tile order: max of max|u| and
+// of the non-finite flag, Neumaier sums of mass, kinetic energy and momentum
+// (additions only, so no multiply-add contraction can change the rounding).
+__global__ void __launch_bounds__(64) finish_partials_kernel(const double* __restrict__ part,
+                                                             int count, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double umax = 0.0, bad = 0.0;
+  double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, comp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < count; ++b) {
+    const double* q = part + (long long)NPART * b;
+    umax = fmax(umax, q[0]);
+    bad = fmax(bad, q[3]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double v = q[k < 2 ? 1 + k : 2 + k];
+      const double t = sum[k] + v;
+      if (fabs(sum[k]) >= fabs(v))
+        comp[k] += (sum[k] - t) + v;
+      else
+        comp[k] += (v - t) + sum[k];
+      sum[k] = t;
+    }
+    if (!isfinite(q[1]) || !isfinite(q[2])) bad = 1.0;
+  }
+  out[0] = umax;
+  out[1] = sum[0] + comp[0];
+  out[2] = sum[1] + comp[1];
+  out[3] = bad;
+  out[4] = sum[2] + comp[2];
+  out[5] = sum[3] + comp[3];
+  out[6] = sum[4] + comp[4];
+  out[7] = 0.0;
+}
+
 // Tiles are assigned so that each XCD (blocks b, b+8, ...) walks a contiguous
 // range of tiles: neighbouring strips share halo lines in L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -932,6 +966,11 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,
                           const Tiling& t, const void* f, const ObserveOut& o, hipStream_t s) {
   return launch_march<true>(storage, scheme, g, ph, t, f, nullptr, o, s);
+}
+
+hipError_t launch_finish_partials(const double* part, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(finish_partials_kernel, dim3(1), dim3(64), 0, s, part, count, out);
+  return hipGetLastError();
 }
 
 int stencil4_blocks(const Geometry& g) {

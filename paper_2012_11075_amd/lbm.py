@@ -82,6 +82,7 @@ def load():
         "lbm_observe": (st, [_VP, _D, _D, _D, _D, O]),
         "lbm_init3d": (st, [_VP, _D, _D, _D, _D, st]),
         "lbm_observe3d": (st, [_VP, _D, _D, _D, _D, _D, O]),
+        "lbm_observe_noalloc": (st, [_VP, _VP]),
         "lbm_get_populations": (st, [_VP, _D]),
         "lbm_set_populations": (st, [_VP, _D, st, i64]),
         "lbm_set_tile": (st, [_VP, i32, i32, i32]),
@@ -228,6 +229,15 @@ class Solver:
             self._check(st)
         out.update(_obs_dict(obs, self.nz))
         return out
+
+    def observe_noalloc(self, out) -> None:
+        """Enqueue lbm_observe_noalloc on the solver's stream: `out` is a CUDA
+        float64 tensor of 8 elements (max|u|, mass, E, non-finite flag,
+        momentum x, y, z, 0), valid once the stream has been synchronized."""
+        import torch
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 8
+        assert out.is_contiguous()
+        self._check(self.lib.lbm_observe_noalloc(self.ctx, ctypes.c_void_p(out.data_ptr())))
 
     def get_populations(self) -> np.ndarray:
         """Populations as (9, ny, nx) doubles (unshifted); 3-D: (19, nz, ny, nx)."""
