@@ -61,6 +61,10 @@ bool valid_params(const lbm_params* p, std::string* why) {
   if (p->force_stencil != 0 && p->force_stencil != 1) return *why = "force_stencil must be 0 or 1", false;
   if (p->force_stencil == 1 && p->ny > 65535)
     return *why = "the fourth-order force stencil needs ny <= 65535", false;
+  // the 2-D kernels hold the row pitch, 9 * nx rounded up to 32 elements, in
+  // an int
+  if (p->nz <= 1 && (long long)Q * (((long long)p->nx + 31) / 32 * 32) > 0x7fffffffLL)
+    return *why = "2-D lattices need 9 * nx (rounded up to 32) <= 2^31 - 1", false;
   if (p->nz > 1) {
     if (p->force_stencil != 0) return *why = "3-D lattices use the central force stencil", false;
     if (p->ny > 65535 || p->nz > 65535) return *why = "3-D lattices need ny, nz <= 65535", false;

@@ -24,7 +24,8 @@ struct Physics {
   double fpre;       // 1 - 1/(2 tau)
   double beta, kappa, rho_l, rho_v;
   double rho_ref;    // storage shift reference (0 for FP64)
-  double geq_c[Q];   // feq_i(rho_ref, 0) - s_i: constant part of the shifted equilibrium
+  double geq_c[Q];   // feq_i(rho_ref, 0) - s_i: constant part of the shifted equilibrium,
+                     // the same for every velocity of a shell
 };
 
 // Tiling of the marching step kernel.

@@ -14,9 +14,11 @@
 //   collide + stream   Eq. (2): f*_i = f_i - (f_i - feq_i)/tau + (1 - 1/2tau) F_i,
 //                      f_i(x + c_i, t+1) = f*_i(x, t), periodic.
 //
-// Design (one HBM pass per step).  Populations live in 9 structure-of-arrays
-// planes, x fastest.  A block of BW threads owns an aligned strip of BW
-// output columns and marches along a chunk of rows.  Each thread loads the 9
+// Design (one HBM pass per step).  Populations are stored row-interleaved:
+// lattice row y holds its nine population rows one after another (element
+// (x, y, q) at y * pitch + q * plane + x, plane = nx rounded up to 32,
+// pitch = 9 * plane), x fastest within each.  A block of BW threads owns an
+// aligned strip of BW output columns and marches along a chunk of rows.  Each thread loads the 9
 // populations of one column per row (coalesced along x) one row ahead of use,
 // keeps the last three rows in registers, and publishes rho of the row to a 5-row LDS ring; mu of
 // the previous row goes to a 3-row LDS ring.  The 2-column x-halo of rho is
@@ -38,7 +40,7 @@ namespace {
 template <typename R>
 struct PhysR {
   R omega, fpre, beta, kappa, rho_l, rho_v, rho_ref;
-  R c[Q];
+  R c[3];  // feq_i(rho_ref, 0) - s_i of the rest, axis and diagonal shells
 };
 
 template <typename R>
@@ -51,8 +53,9 @@ __device__ __forceinline__ PhysR<R> to_r(const Physics& p) {
   q.rho_l = (R)p.rho_l;
   q.rho_v = (R)p.rho_v;
   q.rho_ref = (R)p.rho_ref;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) q.c[i] = (R)p.geq_c[i];
+  q.c[0] = (R)p.geq_c[0];
+  q.c[1] = (R)p.geq_c[1];
+  q.c[2] = (R)p.geq_c[5];
   return q;
 }
 
@@ -77,7 +80,8 @@ __device__ __forceinline__ void velocity(const R (&f)[Q], R rho, R Fx, R Fy, R& 
   uy = (jy + (R)0.5 * Fy) * inv;
 }
 
-// Shifted equilibrium geq_i = feq_i(rho, u) - s_i and forcing term F_i.
+// Collision of Eq. (2), f*_i = f_i - omega (f_i - geq_i) + fpre F_i, with the
+// shifted equilibrium geq_i = feq_i(rho, u) - s_i and the forcing term F_i:
 //   standard: feq_i = w_i rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)     (Eq. 3)
 //             F_i   = w_i (3 c.F + 9 (c.u)(c.F) - 3 u.F)              (Eq. 5)
 //   STANDARD_EQF: feq_i as above, F_i = 3 (c - u).F feq_i / rho
@@ -87,13 +91,17 @@ __device__ __forceinline__ void velocity(const R (&f)[Q], R rho, R Fx, R Fy, R& 
 //             F_i   = w_i (3 c.F + 9 (c.u)(c.G) - 3 u.G
 //                          + (3|c_i|^2 - 2)/2 (u.grad rho)),  G = F + grad(rho)/3  (Eq. 26)
 // feq_i(rho, u) - feq_i(rho_ref, 0) is evaluated from drho = rho - rho_ref
-// (the rho0 terms cancel); the constant feq_i(rho_ref, 0) - s_i is p.c[i].
+// (the rho0 terms cancel); feq_i(rho_ref, 0) - s_i is the shell constant
+// p.c.  A velocity c_i and its opposite share every term of geq and F_i that
+// is even in c_i, so each pair evaluates its even and odd parts once.  The
+// relaxation keeps the form f - omega (f - geq), whose rounding stays
+// proportional to the small non-equilibrium part (mass is conserved to
+// round-off of that part, whatever the rounding of omega).
 template <typename R, int SCHEME>
 __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R Fx, R Fy, R grx,
                                         R gry, const PhysR<R>& p) {
-  const R w0 = (R)4 / (R)9, w1 = (R)1 / (R)9, w5 = (R)1 / (R)36;
-  const R uu = ux * ux + uy * uy;
-  const R u15 = (R)1.5 * uu;
+  const R w0 = (R)4 / (R)9, w1 = (R)1 / (R)9, w2 = (R)1 / (R)36;
+  const R u15 = (R)1.5 * (ux * ux + uy * uy);
   R Gx = Fx, Gy = Fy;
   if (SCHEME == WELL_BALANCED) {
     Gx = Fx + grx * ((R)1 / (R)3);
@@ -101,29 +109,46 @@ __device__ __forceinline__ void collide(R (&f)[Q], R drho, R rho, R ux, R uy, R 
   }
   const R uG3 = (R)3 * (ux * Gx + uy * Gy);
   const R ugr = ux * grx + uy * gry;
-  // c_i . u, c_i . F, c_i . G for i = 1..8 (paper numbering)
-  const R cu[Q] = {(R)0, ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
-  const R cF[Q] = {(R)0, Fx, Fy, -Fx, -Fy, Fx + Fy, Fy - Fx, -Fx - Fy, Fx - Fy};
-  const R cG[Q] = {(R)0, Gx, Gy, -Gx, -Gy, Gx + Gy, Gy - Gx, -Gx - Gy, Gx - Gy};
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R w = (i == 0) ? w0 : (i < 5 ? w1 : w5);
-    const R poly = (R)3 * cu[i] + (R)4.5 * cu[i] * cu[i] - u15;
-    R geq, Fi;
-    if (SCHEME == STANDARD) {
-      geq = w * (drho + rho * poly);
-      Fi = w * ((R)3 * cF[i] + (R)9 * cu[i] * cF[i] - uG3);
-    } else if (SCHEME == STANDARD_EQF) {
-      geq = w * (drho + rho * poly);
-      Fi = w * ((R)1 + poly) * ((R)3 * cF[i] - uG3);  // G = F here
-    } else {
-      geq = (i == 0) ? drho - w0 * rho * u15 : w * rho * poly;
-      const R k = (i == 0) ? (R)-1 : (i < 5 ? (R)0.5 : (R)2);
-      Fi = w * ((R)3 * cF[i] + (R)9 * cu[i] * cG[i] - uG3 + k * ugr);
-    }
-    geq += p.c[i];
-    f[i] = f[i] - p.omega * (f[i] - geq) + p.fpre * Fi;
+  const R om = p.omega, fp = p.fpre;
+  // even forcing constant of a shell: k_i u.grad(rho) - 3 u.G (k = 1/2, 2 for WB)
+  R ev1 = -uG3, ev2 = -uG3;
+  if (SCHEME == WELL_BALANCED) {
+    ev1 = (R)0.5 * ugr - uG3;
+    ev2 = (R)2 * ugr - uG3;
   }
+  auto pair = [&](int i, int j, R cu, R cF, R cG, R w, R c, R ev) {
+    const R ep = (R)4.5 * (cu * cu) - u15;  // even part of poly_i
+    const R wr = w * rho;
+    // even and odd parts of geq_i, then of fpre F_i
+    const R E = (SCHEME == WELL_BALANCED ? wr * ep : w * drho + wr * ep) + c;
+    const R O = (R)3 * wr * cu;
+    R Fe, Fo;
+    if (SCHEME == STANDARD_EQF) {  // F_i = w (1 + ep + 3 cu)(3 cF - uG3)
+      const R e1 = (R)1 + ep;
+      Fe = w * ((R)9 * cu * cF + e1 * ev);
+      Fo = (R)3 * w * (e1 * cF - cu * uG3);
+    } else {
+      Fe = w * ((R)9 * cu * (SCHEME == WELL_BALANCED ? cG : cF) + ev);
+      Fo = (R)3 * w * cF;
+    }
+    const R Fp = fp * (Fe + Fo), Fm = fp * (Fe - Fo);
+    f[i] = f[i] - om * ((f[i] - E) - O) + Fp;
+    f[j] = f[j] - om * ((f[j] - E) + O) + Fm;
+  };
+  pair(1, 3, ux, Fx, Gx, w1, p.c[1], ev1);
+  pair(2, 4, uy, Fy, Gy, w1, p.c[1], ev1);
+  pair(5, 7, ux + uy, Fx + Fy, Gx + Gy, w2, p.c[2], ev2);
+  pair(6, 8, uy - ux, Fy - Fx, Gy - Gx, w2, p.c[2], ev2);
+  // rest population (c_0 = 0)
+  R g0, F0;
+  if (SCHEME == WELL_BALANCED) {
+    g0 = (drho - w0 * rho * u15) + p.c[0];
+    F0 = -w0 * (uG3 + ugr);
+  } else {
+    g0 = w0 * (drho - rho * u15) + p.c[0];
+    F0 = SCHEME == STANDARD ? -w0 * uG3 : -w0 * ((R)1 - u15) * uG3;
+  }
+  f[0] = f[0] - om * (f[0] - g0) + fp * F0;
 }
 
 // Populations are addressed through global-address-space pointers.  A
@@ -175,26 +200,43 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
   };
   auto row_of = [&](int k) { return wrapy(up ? y0 + H + 1 - k : y0 - 2 + k); };
 
+  // Rows advance by one per stage in the march direction: the row loaded
+  // next and the row of the node updated at the current stage are carried
+  // from stage to stage (no division per stage).
+  auto next_row = [&](int y) {
+    y += up ? -1 : 1;
+    return y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+  };
+  auto row_above = [&](int y) { return (y == 0) ? g.ny - 1 : y - 1; };
+  auto row_below = [&](int y) { return (y + 1 == g.ny) ? 0 : y + 1; };
+
   // Pull streaming: the buffers hold post-collision populations, so f_i at
-  // (x, y) is read from (x - c_ix, y - c_iy) of the previous step.
+  // (x, y) is read from (x - c_ix, y - c_iy) of the previous step.  Each
+  // access is a row base common to the wave (population q of lattice row y)
+  // plus this lane's byte offset within that population row, which stays
+  // below 2^32 (nx * 8 bytes), so loads and stores take a scalar base and a
+  // 32-bit lane offset.
   const int xw = (xc == 0) ? g.nx - 1 : xc - 1;
   const int xe = (xc + 1 == g.nx) ? 0 : xc + 1;
-  auto load_row = [&](int k, R(&dst)[Q]) {
-    const int y = row_of(k);
-    const int yu = (y == 0) ? g.ny - 1 : y - 1;
-    const int yd = (y + 1 == g.ny) ? 0 : y + 1;
+  const unsigned bc = (unsigned)xc * (unsigned)sizeof(T), bw = (unsigned)xw * (unsigned)sizeof(T),
+                 be = (unsigned)xe * (unsigned)sizeof(T);
+  auto at = [](const Global<T>* row, unsigned b) -> T {
+    return *(const Global<T>*)((const Global<char>*)row + b);
+  };
+  auto load_row = [&](int y, R(&dst)[Q]) {
     const long long P = g.plane;
-    const long long r0 = (long long)y * g.pitch, ru = (long long)yu * g.pitch,
-                    rd = (long long)yd * g.pitch;
-    dst[0] = fin[r0 + xc];
-    dst[1] = fin[P + r0 + xw];
-    dst[2] = fin[2 * P + ru + xc];
-    dst[3] = fin[3 * P + r0 + xe];
-    dst[4] = fin[4 * P + rd + xc];
-    dst[5] = fin[5 * P + ru + xw];
-    dst[6] = fin[6 * P + ru + xe];
-    dst[7] = fin[7 * P + rd + xe];
-    dst[8] = fin[8 * P + rd + xw];
+    const Global<T>* r0 = fin + (long long)y * g.pitch;
+    const Global<T>* ru = fin + (long long)row_above(y) * g.pitch;
+    const Global<T>* rd = fin + (long long)row_below(y) * g.pitch;
+    dst[0] = at(r0, bc);
+    dst[1] = at(r0 + P, bw);
+    dst[2] = at(ru + 2 * P, bc);
+    dst[3] = at(r0 + 3 * P, be);
+    dst[4] = at(rd + 4 * P, bc);
+    dst[5] = at(ru + 5 * P, bw);
+    dst[6] = at(ru + 6 * P, be);
+    dst[7] = at(rd + 7 * P, be);
+    dst[8] = at(rd + 8 * P, bw);
   };
 
   // The four halo columns x0-2, x0-1, x0+BW, x0+BW+1 need rho only.  Lane
@@ -219,9 +261,14 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
     hcy = cyq;
     hplane = (long long)hq * g.plane;
   }
-  auto load_halo = [&](int k, R& dst) {
-    if (hl) dst = fin[hplane + (long long)wrapy(row_of(k) - hcy) * g.pitch + hsx];
+  auto load_halo = [&](int y, R& dst) {
+    if (hl) {
+      const int hy = hcy > 0 ? row_above(y) : (hcy < 0 ? row_below(y) : y);
+      dst = fin[hplane + (long long)hy * g.pitch + hsx];
+    }
   };
+  int yload = row_of(0);  // row of the next population load
+  int yupd = row_of(-2);  // row of the node updated at the current stage
 
   NodeSums acc;
 
@@ -229,8 +276,9 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
   // which then parks in LDS for two rows); mu of row k-1; update the node of
   // row k-2.
   auto stage = [&](int k, R(&nxt)[Q], R(&cur)[Q], R& hnxt, R& hcur) {
-    load_row(k + D, nxt);  // rows past the chunk are valid (periodic) and unused
-    load_halo(k + D, hnxt);
+    load_row(yload, nxt);  // rows past the chunk are valid (periodic) and unused
+    load_halo(yload, hnxt);
+    yload = next_row(yload);
     const int sk = k % 5;
     rs[sk][t + 2] = p.rho_ref + sum9(cur);
     if (t < 64) {
@@ -287,14 +335,17 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
       }
       R ux, uy;
       velocity(out, rho, Fx, Fy, ux, uy);
-      const int y = row_of(k - 2);
+      const int y = yupd;
       if (!OBSERVE) {
         const R drho = sum9(out);
         collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
         // post-collision populations stay at their node (aligned, streaming stores)
-        Global<T>* dst = fout + (long long)y * g.pitch + x;
+        Global<T>* dst = fout + (long long)y * g.pitch;
+        const unsigned bx = (unsigned)x * (unsigned)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(out[i], dst + (long long)i * g.plane);
+        for (int i = 0; i < Q; ++i)
+          __builtin_nontemporal_store(
+              out[i], (Global<T>*)((Global<char>*)(dst + (long long)i * g.plane) + bx));
       } else {
         const long long o = (long long)y * g.nx + x;
         const double drho = (double)rho, dux = (double)ux, duy = (double)uy;
@@ -312,6 +363,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
         acc.py += drho * duy;
       }
     }
+    yupd = next_row(yupd);
   };
 
   // Row r lives in register set r % (D+1).  The loop is unrolled by D+1 and
@@ -322,15 +374,18 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
   R h0 = (R)0, h1 = (R)0, h2 = (R)0, h3 = (R)0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) s0[i] = s1[i] = s2[i] = s3[i] = (R)0;
-  load_row(0, s0);
-  load_halo(0, h0);
+  load_row(yload, s0);
+  load_halo(yload, h0);
+  yload = next_row(yload);
   if (D >= 2) {
-    load_row(1, s1);
-    load_halo(1, h1);
+    load_row(yload, s1);
+    load_halo(yload, h1);
+    yload = next_row(yload);
   }
   if (D >= 3) {
-    load_row(2, s2);
-    load_halo(2, h2);
+    load_row(yload, s2);
+    load_halo(yload, h2);
+    yload = next_row(yload);
   }
   for (int k = 0; k < K; k += D + 1) {
     if (D == 1) {

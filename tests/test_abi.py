@@ -61,6 +61,22 @@ def test_workspace_bytes_rejects_bad_params(lib):
         assert lib.lbm_workspace_bytes(ctypes.byref(good)) > 0
 
 
+def test_row_pitch_overflow_rejected(lib):
+    """A 2-D lattice whose row pitch (9 * nx rounded up to 32 elements) does
+    not fit in 32 bits is rejected before any memory is touched, although it
+    is under the 2^31-node limit."""
+    P = lbm.make_params
+    bad = P(300_000_000, 2, 1.0, 0.1, 0.02, 1, 0.1)
+    assert lib.lbm_workspace_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(bad), 0x100000, 1 << 40, None, ctypes.byref(h)) == -1
+    assert b"2^31" in lib.lbm_last_error(None) and not h.value
+    # the widest accepted row: 9 * 238,609,280 = 2,147,483,520 elements
+    ok = P(238_609_280, 2, 1.0, 0.1, 0.02, 1, 0.1)
+    assert lib.lbm_workspace_bytes(ctypes.byref(ok)) > 0
+    assert lib.lbm_workspace_bytes(ctypes.byref(P(238_609_312, 2, 1.0, 0.1, 0.02, 1, 0.1))) == 0
+
+
 def test_params_struct_matches_header(lib):
     """lbm_params as ctypes lays it out: the field order of include/lbm.h."""
     import re
