@@ -70,12 +70,25 @@ __device__ __forceinline__ R sum9(const R (&f)[Q]) {
   return (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) + f[8];
 }
 
+// 1/rho: the hardware reciprocal refined by two Newton steps (relative error
+// a few units in the last place, far below the step's tolerances; the same
+// function serves the step and the observe pass).
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = r * (2.0 - a * r);
+  return r * (2.0 - a * r);
+}
+__device__ __forceinline__ float recip(float a) {
+  float r = __builtin_amdgcn_rcpf(a);
+  return r * (2.0f - a * r);
+}
+
 // Velocity of Eq. (4): u = (sum_i c_i f_i + F/2) / rho.
 template <typename R>
 __device__ __forceinline__ void velocity(const R (&f)[Q], R rho, R Fx, R Fy, R& ux, R& uy) {
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const R inv = (R)1 / rho;
+  const R inv = recip(rho);
   ux = (jx + (R)0.5 * Fx) * inv;
   uy = (jy + (R)0.5 * Fy) * inv;
 }
@@ -337,7 +350,8 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
       velocity(out, rho, Fx, Fy, ux, uy);
       const int y = yupd;
       if (!OBSERVE) {
-        const R drho = sum9(out);
+        // FP64 storage carries no shift: rho = 0 + sum9 of the same values
+        const R drho = sizeof(T) == 8 ? rho : sum9(out);
         collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
         // post-collision populations stay at their node (aligned, streaming stores)
         Global<T>* dst = fout + (long long)y * g.pitch;
