@@ -64,13 +64,16 @@ __device__ __forceinline__ R mu0_3(R r, const Physics3& p) {
 
 // Equilibrium (Eq. 3 / Eq. 24) and forcing term (Eq. 5 / Eq. 26 with D = 3:
 // the last term's coefficient (|c|^2/cs2 - 3)/2 is -3/2, 0, 3/2 for the
-// rest, axis and edge directions), then BGK; emit(i, f*_i) receives each
-// post-collision population as soon as it is known.  A scheduling barrier
-// after every G directions keeps the compiler from computing all 19 at once
-// (each result then dies at its store instead of holding a register).
-// FP32 storage holds g_i = f_i - s_i: the equilibrium is then taken as
-// feq_i(rho, u) - feq_i(rho_ref, 0) from drho = rho - rho_ref, plus the
-// constant c_i = feq_i(rho_ref, 0) - s_i (the rho0 terms cancel).
+// rest, axis and edge directions), then BGK, f*_i = f_i - omega (f_i - feq_i)
+// + fpre F_i; emit(i, f*_i) receives each post-collision population as soon
+// as it is known.  The velocities come in opposite pairs (1,2), (3,4), ...,
+// (17,18); every term of feq_i and F_i is even or odd in c_i, so a pair
+// evaluates its even and odd parts once.  A scheduling barrier after every G
+// pairs keeps the compiler from computing all 19 at once (each result then
+// dies at its store instead of holding a register).  FP32 storage holds
+// g_i = f_i - s_i: the equilibrium is then taken as feq_i(rho, u) -
+// feq_i(rho_ref, 0) from drho = rho - rho_ref, plus the constant
+// c_i = feq_i(rho_ref, 0) - s_i (the rho0 terms cancel).
 template <int SCHEME, int G, typename R, typename E>
 __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, R uy, R uz, R Fx,
                                          R Fy, R Fz, R grx, R gry, R grz, const Physics3& p,
@@ -86,34 +89,67 @@ __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, 
   const R uG3 = (R)3 * (ux * Gx + uy * Gy + uz * Gz);
   const R ugr = ux * grx + uy * gry + uz * grz;
   const R omega = (R)p.omega, fpre = (R)p.fpre, rho0 = (R)p.rho0;
-#pragma unroll
-  for (int i = 0; i < Q3; ++i) {
-    int cx, cy, cz;
-    c3(i, cx, cy, cz);
-    const R w = i == 0 ? (R)1 / (R)3 : (i < 7 ? (R)1 / (R)18 : (R)1 / (R)36);
-    const R cu = cx * ux + cy * uy + cz * uz;
-    const R cF = cx * Fx + cy * Fy + cz * Fz;
-    const R cG = cx * Gx + cy * Gy + cz * Gz;
-    const R poly = (R)3 * cu + (R)4.5 * cu * cu - u15;
-    R feq, Fi;
-    if (SCHEME == STANDARD) {
-      feq = SHIFTED ? w * (drho + rho * poly) + (R)p.c[i] : w * rho * ((R)1 + poly);
-      Fi = w * ((R)3 * cF + (R)9 * cu * cG - uG3);
-    } else if (SCHEME == STANDARD_EQF) {
-      // F_i = (c_i - u).F feq_i / (cs2 rho) with feq_i / rho = w (1 + poly); G = F here
-      feq = SHIFTED ? w * (drho + rho * poly) + (R)p.c[i] : w * rho * ((R)1 + poly);
-      Fi = w * ((R)1 + poly) * ((R)3 * cF - uG3);
+  // even forcing constant of a shell: k u.grad(rho) - 3 u.G (WB: k = 0 on the
+  // axes, 3/2 on the edges)
+  const R ev_axis = -uG3;
+  const R ev_edge = SCHEME == WELL_BALANCED ? (R)1.5 * ugr - uG3 : -uG3;
+  auto pair = [&](int i, R cu, R cF, R cG, R w, R ev) {
+    const R ep = (R)4.5 * (cu * cu) - u15;  // even part of poly_i
+    const R wr = w * rho;
+    R Ev;  // even part of the (shifted) equilibrium
+    if (SCHEME == WELL_BALANCED)
+      Ev = SHIFTED ? wr * ep + (R)p.c[i] : w * rho0 + wr * ep;
+    else
+      Ev = SHIFTED ? (w * drho + wr * ep) + (R)p.c[i] : wr + wr * ep;
+    const R O = (R)3 * wr * cu;
+    R Fe, Fo;
+    if (SCHEME == STANDARD_EQF) {  // F_i = w (1 + ep + 3 cu)(3 cF - uG3)
+      const R e1 = (R)1 + ep;
+      Fe = w * ((R)9 * cu * cF + e1 * ev);
+      Fo = (R)3 * w * (e1 * cF - cu * uG3);
     } else {
-      if (SHIFTED)
-        feq = (i == 0 ? drho - w * rho * u15 : w * rho * poly) + (R)p.c[i];
-      else
-        feq = i == 0 ? rho - ((R)1 - w) * rho0 - w * rho * u15 : w * (rho0 + rho * poly);
-      const R k = i == 0 ? (R)-1.5 : (i < 7 ? (R)0 : (R)1.5);
-      Fi = w * ((R)3 * cF + (R)9 * cu * cG - uG3 + k * ugr);
+      Fe = w * ((R)9 * cu * (SCHEME == WELL_BALANCED ? cG : cF) + ev);
+      Fo = (R)3 * w * cF;
     }
-    emit(i, f[i] - omega * (f[i] - feq) + fpre * Fi);
-    if (G > 0 && i % G == G - 1) __builtin_amdgcn_sched_barrier(0);
+    const R Fp = fpre * (Fe + Fo), Fm = fpre * (Fe - Fo);
+    emit(i, f[i] - omega * ((f[i] - Ev) - O) + Fp);
+    emit(i + 1, f[i + 1] - omega * ((f[i + 1] - Ev) + O) + Fm);
+  };
+  int np = 0;
+  auto sched = [&]() {
+    if (G > 0 && ++np % G == 0) __builtin_amdgcn_sched_barrier(0);
+  };
+  const R wa = (R)1 / (R)18, we = (R)1 / (R)36;
+  // rest population (c_0 = 0)
+  {
+    const R w0 = (R)1 / (R)3;
+    R feq0, F0;
+    if (SCHEME == WELL_BALANCED) {
+      feq0 = SHIFTED ? (drho - w0 * rho * u15) + (R)p.c[0] : rho - ((R)1 - w0) * rho0 - w0 * rho * u15;
+      F0 = -w0 * (uG3 + (R)1.5 * ugr);
+    } else {
+      feq0 = SHIFTED ? w0 * (drho - rho * u15) + (R)p.c[0] : w0 * rho * ((R)1 - u15);
+      F0 = SCHEME == STANDARD ? -w0 * uG3 : -w0 * ((R)1 - u15) * uG3;
+    }
+    emit(0, f[0] - omega * (f[0] - feq0) + fpre * F0);
   }
+  pair(1, ux, Fx, Gx, wa, ev_axis);
+  sched();
+  pair(3, uy, Fy, Gy, wa, ev_axis);
+  sched();
+  pair(5, uz, Fz, Gz, wa, ev_axis);
+  sched();
+  pair(7, ux + uy, Fx + Fy, Gx + Gy, we, ev_edge);
+  sched();
+  pair(9, ux - uy, Fx - Fy, Gx - Gy, we, ev_edge);
+  sched();
+  pair(11, ux + uz, Fx + Fz, Gx + Gz, we, ev_edge);
+  sched();
+  pair(13, ux - uz, Fx - Fz, Gx - Gz, we, ev_edge);
+  sched();
+  pair(15, uy + uz, Fy + Fz, Gy + Gz, we, ev_edge);
+  sched();
+  pair(17, uy - uz, Fy - Fz, Gy - Gz, we, ev_edge);
 }
 
 // rho = sum_i f_i in a fixed order (every kernel sums a node the same way).
@@ -266,7 +302,7 @@ __device__ __forceinline__ void load19(const __amdgpu_buffer_rsrc_t (&b)[3], uns
 
 // Fused step: one block per (32 x TY column, chunk of tl.zc planes).  D:
 // planes of populations loaded ahead of the plane being summed (0 = none).
-constexpr int CG = 3;  // directions per scheduling region of the collision
+constexpr int CG = 1;  // velocity pairs per scheduling region of the collision
 template <typename T, int SCHEME, int TY, int D>
 __global__ void __launch_bounds__(M3X * TY)
     march3(Geometry3 g, Physics3 p, Tiling3 tl, const T* __restrict__ fin, T* __restrict__ fout) {
