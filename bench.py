@@ -168,7 +168,7 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
             "active_at_end": count - len(retired)}
 
 
-def serve_stream(n_requests=24, rate_hz=None, arena_gb=8.0, k=250):
+def serve_stream(n_requests=100, rate_hz=None, arena_gb=8.0, k=250):
     """Served stream: Poisson arrivals of run-to-equilibrium requests (side
     log-uniform 64..2048, density ratio 10..1000, FP32-shifted by default and
     FP64 for one request in ten), continuous batching over one arena."""
@@ -194,8 +194,12 @@ def serve_stream(n_requests=24, rate_hz=None, arena_gb=8.0, k=250):
              max_concurrent=max(sum(1 for e in srv.log[:i + 1] if e[0] == "admit") -
                                 sum(1 for e in srv.log[:i + 1] if e[0] == "retire")
                                 for i in range(len(srv.log))))
-    for key in ("p50_latency_s", "p99_latency_s", "mean_latency_s", "aggregate_mlups", "wall_s"):
+    for key in ("p50_latency_s", "p99_latency_s", "mean_latency_s", "aggregate_mlups", "wall_s",
+                "converged_fraction"):
         s[key] = round(s[key], 4)
+    for v in s["by_outcome"].values():
+        for key in ("p50_latency_s", "p99_latency_s", "mean_latency_s"):
+            v[key] = round(v[key], 4)
     return s
 
 
@@ -524,7 +528,7 @@ def main():
     ap.add_argument("--no-largest", action="store_true")
     ap.add_argument("--no-d3", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5000)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the step runs on a single device "

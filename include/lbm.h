@@ -195,6 +195,14 @@ lbm_status lbm_observe3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, doub
  * lbm_set_populations makes the context initialised with `scheme` and sets
  * the step counter to `step`. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
+/* The populations of a window of a 2-D lattice, columns x0 .. x0+w-1 and
+ * rows y0 .. y0+h-1 (periodic: the window may wrap past the last column or
+ * row), as host double[9][h][w] in the convention of lbm_get_populations.
+ * For inspecting part of a lattice too large to copy whole.  Requires
+ * 0 <= x0 < nx, 0 <= y0 < ny, 1 <= w <= nx and 1 <= h <= ny, else
+ * LBM_EINVAL; LBM_ESTATE before lbm_init.  Synchronous. */
+lbm_status lbm_get_populations_window(lbm_ctx* ctx, int32_t x0, int32_t y0, int32_t w, int32_t h,
+                                      double* f);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme, int64_t step);
 
 /* Tile shape of the step kernel: block width in threads (64, 128, 192, 256,

@@ -674,6 +674,31 @@ lbm_status lbm_observe_noalloc(lbm_ctx* c, double* dev_out) {
   return LBM_OK;
 }
 
+lbm_status lbm_get_populations_window(lbm_ctx* c, int32_t x0, int32_t y0, int32_t w, int32_t h,
+                                      double* f) {
+  if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+  if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+  if (c->d3()) return fail(c, LBM_EINVAL, "windows are read from 2-D lattices");
+  if (x0 < 0 || y0 < 0 || x0 >= c->prm.nx || y0 >= c->prm.ny)
+    return fail(c, LBM_EINVAL, "window origin outside the lattice");
+  if (w < 1 || h < 1 || w > c->prm.nx || h > c->prm.ny)
+    return fail(c, LBM_EINVAL, "window size must be 1..nx by 1..ny");
+  if (!c->initialised) return fail(c, LBM_ESTATE, "no state yet");
+  double s[Q];
+  shift_of(c->prm, c->scheme, s);
+  // through the staging area (4 dense fields) in groups of up to 4 populations
+  const size_t n = (size_t)w * h;
+  for (int q0 = 0; q0 < Q; q0 += 4) {
+    const int m = std::min(4, Q - q0);
+    HIPCHK(c, lbmk::launch_unpack_window(c->storage(), c->L.g, s, c->state(), x0, y0, w, h, q0,
+                                         m, c->staging(), c->stream));
+    HIPCHK(c, hipMemcpyAsync(f + (size_t)q0 * n, c->staging(), (size_t)m * n * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_get_populations(lbm_ctx* c, double* f) {
   if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
   if (!f) return fail(c, LBM_EINVAL, "f is NULL");

@@ -155,6 +155,12 @@ hipError_t launch_pack(int storage, const Geometry& g, const double* shift, cons
 hipError_t launch_unpack(int storage, const Geometry& g, const double* shift, const void* f,
                          int q0, int m, double* dense, hipStream_t s);
 
+// The same for the window x0 .. x0+w-1, y0 .. y0+h-1 (periodic, 0 <= x0 < nx,
+// 0 <= y0 < ny), as dense planes [m][h][w] of populations q0 .. q0+m-1.
+hipError_t launch_unpack_window(int storage, const Geometry& g, const double* shift,
+                                const void* f, int x0, int y0, int w, int h, int q0, int m,
+                                double* dense, hipStream_t s);
+
 // g_i += delta_i on every node (conversion of the FP32 storage shift).
 hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, void* f,
                           hipStream_t s);

@@ -888,6 +888,21 @@ __global__ void unpack_kernel(Geometry g, Shift shift, const T* __restrict__ f, 
   dense[(long long)m * n + k] = (double)f[(long long)q * g.plane + src_offset(g, q, x, y)] + s;
 }
 
+// Window (x0 .. x0+w-1, y0 .. y0+h-1, periodic) of populations q0 .. q0+m-1
+// (one per blockIdx.y) as dense double planes [m][h][w], shift added back.
+template <typename T>
+__global__ void unpack_window_kernel(Geometry g, Shift shift, const T* __restrict__ f, int x0,
+                                     int y0, int w, int h, int q0, double* __restrict__ dense) {
+  const long long n = (long long)w * h;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int j = (int)(k / w), i = (int)(k - (long long)j * w);
+  const int x = (int)(((long long)x0 + i) % g.nx), y = (int)(((long long)y0 + j) % g.ny);
+  const int q = q0 + (int)blockIdx.y;
+  dense[(long long)blockIdx.y * n + k] =
+      (double)f[(long long)q * g.plane + src_offset(g, q, x, y)] + shift.s[q];
+}
+
 template <typename T>
 __global__ void reshift_kernel(Geometry g, Physics d, T* __restrict__ f) {
   const long long n = (long long)g.nx * g.ny;
@@ -1160,6 +1175,19 @@ hipError_t launch_unpack(int storage, const Geometry& g, const double* shift, co
   else
     hipLaunchKernelGGL(unpack_kernel<float>, dim3(grid1(n), m), dim3(256), 0, s, g,
                        make_shift(shift), (const float*)f, q0, dense);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_window(int storage, const Geometry& g, const double* shift,
+                                const void* f, int x0, int y0, int w, int h, int q0, int m,
+                                double* dense, hipStream_t s) {
+  const long long n = (long long)w * h;
+  if (storage == FP64)
+    hipLaunchKernelGGL(unpack_window_kernel<double>, dim3(grid1(n), m), dim3(256), 0, s, g,
+                       make_shift(shift), (const double*)f, x0, y0, w, h, q0, dense);
+  else
+    hipLaunchKernelGGL(unpack_window_kernel<float>, dim3(grid1(n), m), dim3(256), 0, s, g,
+                       make_shift(shift), (const float*)f, x0, y0, w, h, q0, dense);
   return hipGetLastError();
 }
 

@@ -84,6 +84,7 @@ def load():
         "lbm_observe3d": (st, [_VP, _D, _D, _D, _D, _D, O]),
         "lbm_observe_noalloc": (st, [_VP, _VP]),
         "lbm_get_populations": (st, [_VP, _D]),
+        "lbm_get_populations_window": (st, [_VP, i32, i32, i32, i32, _D]),
         "lbm_set_populations": (st, [_VP, _D, st, i64]),
         "lbm_set_tile": (st, [_VP, i32, i32, i32]),
         "lbm_get_tile": (st, [_VP, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
@@ -238,6 +239,14 @@ class Solver:
         assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 8
         assert out.is_contiguous()
         self._check(self.lib.lbm_observe_noalloc(self.ctx, ctypes.c_void_p(out.data_ptr())))
+
+    def get_populations_window(self, x0, y0, w, h) -> np.ndarray:
+        """Populations of the (periodic) window at columns x0.., rows y0.. as
+        (9, h, w) doubles (2-D lattices)."""
+        f = np.empty((9, int(h), int(w)))
+        self._check(self.lib.lbm_get_populations_window(self.ctx, int(x0), int(y0), int(w),
+                                                        int(h), _dptr(f)))
+        return f
 
     def get_populations(self) -> np.ndarray:
         """Populations as (9, ny, nx) doubles (unshifted); 3-D: (19, nz, ny, nx)."""

@@ -157,14 +157,21 @@ class Server:
 
 
 def summarise(outcomes, wall_s: float) -> dict:
+    """Latency percentiles over all requests and per outcome (converged,
+    capped, diverged), the converged fraction, and the aggregate rate."""
     lat = np.array([o.latency for o in outcomes]) if outcomes else np.zeros(1)
     node_steps = sum(o.nodes * o.steps for o in outcomes)
     by = {}
     for o in outcomes:
-        by[o.status] = by.get(o.status, 0) + 1
+        by.setdefault(o.status, []).append(o.latency)
+    per = {st: {"count": len(v), "p50_latency_s": float(np.percentile(v, 50)),
+                "p99_latency_s": float(np.percentile(v, 99)), "mean_latency_s": float(np.mean(v))}
+           for st, v in sorted(by.items())}
     return {"requests": len(outcomes), "wall_s": wall_s,
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(lat.mean()),
             "aggregate_mlups": node_steps / wall_s / 1e6 if wall_s > 0 else 0.0,
-            "outcomes": by}
+            "outcomes": {st: v["count"] for st, v in per.items()},
+            "converged_fraction": (len(by.get("converged", [])) / len(outcomes)) if outcomes else 0.0,
+            "by_outcome": per}

@@ -234,6 +234,24 @@ def test_observe_scalars(orc, lbm):
     np.testing.assert_allclose(ob["momentum"], oo["momentum"], rtol=0, atol=TOL * oo["mass"])
 
 
+def test_population_window_matches_full_copy(lbm):
+    """lbm_get_populations_window returns the slice of lbm_get_populations,
+    also for windows that wrap past the last column and row, in FP64 and in
+    FP32-shifted storage; bad windows are rejected."""
+    prob = I.with_size(I.PAPER_DROPLET, 70, 45)
+    for prec in ("fp64", "fp32s"):
+        s = run_gpu(lbm, prob, "well_balanced", 37, precision=prec)
+        full = s.get_populations()
+        for x0, y0, w, h in [(0, 0, 70, 45), (65, 40, 12, 9), (3, 44, 70, 1), (69, 0, 1, 45)]:
+            got = s.get_populations_window(x0, y0, w, h)
+            want = full[:, (y0 + np.arange(h)) % 45][:, :, (x0 + np.arange(w)) % 70]
+            assert np.array_equal(got, want), (prec, x0, y0, w, h)
+        for bad in [(70, 0, 1, 1), (0, -1, 1, 1), (0, 0, 71, 1), (0, 0, 1, 0)]:
+            with pytest.raises(lbm.LbmError):
+                s.get_populations_window(*bad)
+        s.close()
+
+
 def test_mass_conserved_long_run(lbm):
     prob = I.DROPLET_256
     s = run_gpu(lbm, prob, "well_balanced", 0)

@@ -49,3 +49,37 @@ def test_served_results_equal_alone():
             assert o.max_u < req.tol
         elif o.status == "capped":
             assert o.steps >= req.step_cap
+
+
+def test_served_large_sides_equal_alone():
+    """The served size range reaches 2048: requests with sides of 1024 and
+    more, in FP64 and in FP32-shifted storage, served together for 300 steps
+    (tolerance never met, so each retires at its cap), give the populations
+    of the same request run alone, bit for bit."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2012_11075_amd import lbm
+    from paper_2012_11075_amd.serve import BatchExecutor, Server
+    reqs = I.request_stream(6, rate_hz=400.0, seed=33, side_lo=512, side_hi=2048, step_cap=300,
+                            fp64_fraction=0.5)
+    big = [r for r in reqs if r.problem.nx >= 1024]
+    assert {r.precision for r in big} == {"fp64", "fp32s"}, [(r.problem.nx, r.precision) for r in reqs]
+    print("served sides", [(r.problem.nx, r.precision) for r in reqs], flush=True)
+    ex = BatchExecutor(int(12e9), max_slots=16, graph_steps=20, capture=True)
+    srv = Server(ex, k=100)
+    out = srv.serve(reqs)
+    ex.close()
+    assert sorted(o.rid for o in out) == list(range(len(reqs)))
+    for o in out:
+        req = reqs[o.rid]
+        assert o.status == "capped" and o.steps == 300, (o.rid, o.status, o.steps)
+        ph = req.problem.physics
+        sv = lbm.Solver(req.problem.nx, req.problem.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l,
+                        ph.rho_v, ph.rho0, precision=req.precision)
+        sv.init(req.problem.rho(), scheme="well_balanced")
+        sv.step(o.steps, "well_balanced")
+        f = sv.get_populations()
+        sv.close()
+        assert np.array_equal(f, o.result["populations"], equal_nan=True), (o.rid, req.problem.nx)
+        del f
+        o.result = None
