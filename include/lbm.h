@@ -65,8 +65,8 @@ typedef enum {
  * LBM_STANDARD_EQ_FORCING: the standard LBE with the other forcing term the
  * paper names after Eq. (5), F_i = (c_i - u).F feq_i / (cs2 rho); same
  * equilibrium, force, observe pass and FP32 shift as LBM_STANDARD.  Single
- * lattices, 2-D (either force stencil) and 3-D, in either precision;
- * lbm_batch_admit rejects it with LBM_EINVAL. */
+ * lattices, 2-D (either force stencil) and 3-D, and batch slots, in either
+ * precision. */
 typedef enum {
   LBM_STANDARD = 0,
   LBM_WELL_BALANCED = 1,
@@ -264,7 +264,8 @@ lbm_status lbm_batch_create(void* dev_arena, size_t bytes, int32_t max_slots, vo
                             lbm_batch** out);
 
 /* Admit a lattice: allocate its workspace in the arena, set f(0) = feq(rho, 0)
- * (as lbm_init) and mark it active.  It retires at the first lbm_batch_poll
+ * (as lbm_init) and mark it active; every scheme of lbm_scheme is accepted,
+ * and each slot steps with the scheme it was admitted with.  It retires at the first lbm_batch_poll
  * that finds max|u| < tol (tol <= 0: never) or step >= step_cap (<= 0: no
  * cap), or a non-finite state.  LBM_EBUSY if no slot or arena range is free
  * (nothing changes).  Synchronous. */

@@ -837,7 +837,7 @@ int32_t lbm_kernels_per_step(const lbm_ctx* c) {
 namespace {
 
 constexpr int kBatchBlocks[3] = {64, 128, 256};
-constexpr int kGroups = 2 * 2 * 3 * 3;  // storage x scheme x block x depth
+constexpr int kGroups = 2 * 3 * 3 * 3;  // storage x scheme x block x depth
 static_assert(kGroups <= 64, "group masks are 64-bit");
 // Each group's slots are split into two lanes (even and odd slot index), each
 // with its own table, launched on its own stream: the lanes hold disjoint
@@ -919,7 +919,7 @@ lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
 
 int group_of(const lbm_ctx* c, int scheme) {
   const int bi = block_index(c->tl.block);
-  return ((c->storage() * 2 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
+  return ((c->storage() * 3 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
 }
 
 void group_decode(int g, int* storage, int* scheme, int* block, int* depth) {
@@ -927,8 +927,8 @@ void group_decode(int g, int* storage, int* scheme, int* block, int* depth) {
   g /= 3;
   *block = kBatchBlocks[g % 3];
   g /= 3;
-  *scheme = g % 2;
-  *storage = g / 2;
+  *scheme = g % 3;
+  *storage = g / 3;
 }
 
 size_t part_capacity(size_t arena_bytes) { return arena_bytes / 8192 + 1024; }
@@ -1141,8 +1141,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
                            double tol, int64_t cap, int32_t* slot) {
   if (!b) return bfail(nullptr, LBM_EINVAL, "batch is NULL");
   if (!slot || !rho) return bfail(b, LBM_EINVAL, "slot and rho must not be NULL");
-  if (scheme != LBM_STANDARD && scheme != LBM_WELL_BALANCED)
-    return bfail(b, LBM_EINVAL, "batches run the standard (Eq. 5) and well-balanced schemes");
+  if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
   if (p->force_stencil != 0) return bfail(b, LBM_EINVAL, "batches use the central force stencil");

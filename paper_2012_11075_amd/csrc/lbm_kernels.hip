@@ -1014,18 +1014,23 @@ const void* batch_kernel_t(int block, int depth) {
 }
 
 const void* batch_kernel(int storage, int scheme, int block, int depth, bool observe) {
-  if (scheme != STANDARD && scheme != WELL_BALANCED) return nullptr;  // batches: Eq. 5 / Eq. 26
-  if (observe) depth = 1;
+  if (scheme != STANDARD && scheme != WELL_BALANCED && scheme != STANDARD_EQF) return nullptr;
+  if (observe) {
+    depth = 1;
+    if (scheme == STANDARD_EQF) scheme = STANDARD;  // same force, velocity and fields
+  }
   if (storage == FP64) {
     if (scheme == STANDARD)
       return observe ? batch_kernel_t<double, STANDARD, true>(block, depth)
                      : batch_kernel_t<double, STANDARD, false>(block, depth);
+    if (scheme == STANDARD_EQF) return batch_kernel_t<double, STANDARD_EQF, false>(block, depth);
     return observe ? batch_kernel_t<double, WELL_BALANCED, true>(block, depth)
                    : batch_kernel_t<double, WELL_BALANCED, false>(block, depth);
   }
   if (scheme == STANDARD)
     return observe ? batch_kernel_t<float, STANDARD, true>(block, depth)
                    : batch_kernel_t<float, STANDARD, false>(block, depth);
+  if (scheme == STANDARD_EQF) return batch_kernel_t<float, STANDARD_EQF, false>(block, depth);
   return observe ? batch_kernel_t<float, WELL_BALANCED, true>(block, depth)
                  : batch_kernel_t<float, WELL_BALANCED, false>(block, depth);
 }

@@ -217,6 +217,7 @@ class Request:
     precision: str             # "fp32s" or "fp64"
     tol: float                 # retire when max|u| < tol
     step_cap: int
+    scheme: str = "well_balanced"  # the scheme the request is stepped with
 
 
 def request_stream(n: int, rate_hz: float, seed: int = 5, side_lo: int = 64,

@@ -63,7 +63,8 @@ class BatchExecutor:
         return self.lbm.Batch.slot_bytes(self.params(req))
 
     def admit(self, req):
-        slot = self.batch.try_admit(self.params(req), req.problem.rho(), "well_balanced",
+        slot = self.batch.try_admit(self.params(req), req.problem.rho(),
+                                    getattr(req, "scheme", "well_balanced"),
                                     tol=req.tol, step_cap=req.step_cap)
         if slot is not None and self.tiles is not None:
             tile = self.tiles(req.problem.nx, req.problem.ny, req.precision)

@@ -178,16 +178,37 @@ def test_switching_between_forcing_terms(orc, lbm, prec):
     assert np.abs(fg - fo).max() <= (TOL if prec == "fp64" else 5e-5)
 
 
-def test_eq_forcing_rejected_in_batches(lbm):
-    """Batches run only the Eq. (5) and Eq. (26) forcing terms: admitting a
-    lattice with the other one is refused with LBM_EINVAL."""
+def test_eq_forcing_in_batches(orc, lbm):
+    """Batch slots run the other forcing term too: slots of the three schemes
+    in one batch (FP64 and FP32-shifted) give the populations of the same
+    lattices run alone, bit for bit, and the FP64 ones match the oracle."""
     ph = I.PAPER_PHYS
-    prob = I.with_size(I.PAPER_DROPLET, 32, 32)
-    b = lbm.Batch(1 << 26, max_slots=4)
-    prm = lbm.make_params(32, 32, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v)
-    with pytest.raises(lbm.LbmError) as e:
-        b.admit(prm, prob.rho(), EQF)
-    assert e.value.status == -1
+    cases = [(I.with_size(I.PAPER_DROPLET, 48, 40), EQF, "fp64"),
+             (I.with_size(I.PAPER_DROPLET, 70, 33), EQF, "fp32s"),
+             (I.with_size(I.PAPER_DROPLET, 40, 40), "standard", "fp64"),
+             (I.with_size(I.PAPER_DROPLET, 33, 50), "well_balanced", "fp64")]
+    b = lbm.Batch(1 << 28, max_slots=8)
+    b.set_graph_steps(10)
+    slots = []
+    for prob, sch, prec in cases:
+        prm = lbm.make_params(prob.nx, prob.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v,
+                              precision=prec)
+        slots.append(b.admit(prm, prob.rho(), sch))
+    b.run(120)
+    p = oparams(orc, ph, 0)
+    for (prob, sch, prec), sl in zip(cases, slots):
+        got = b.get_populations(sl)
+        s = lbm.Solver.for_problem(prob, precision=prec)
+        s.init(prob.rho(), scheme=sch)
+        s.step(120, sch)
+        assert np.array_equal(got, s.get_populations(), equal_nan=True), (sch, prec)
+        s.close()
+        if prec == "fp64":
+            fo = orc.step(sch, p, orc.init(sch, p, prob.rho()), 120)
+            assert np.abs(to_oracle(got) - fo).max() <= TOL, sch
+    st, info = b.info(slots[0])
+    b.poll()
+    assert b.info(slots[0])[1]["step"] == 120
     b.close()
 
 
