@@ -1,17 +1,19 @@
 /*
  * lbm_oracle3d.c -- TEST INFRASTRUCTURE, not product code.
  *
- * The three-dimensional form of the step on the D3Q19 lattice: the same
+ * The three-dimensional form of the step on the D3Q19 lattice (and, compiled
+ * from lbm_oracle3d27.c, on the D3Q27 lattice): the same
  * equations as lbm_oracle.c (Z. Guo, arXiv:2012.11075, Sec. II for the
  * standard LBE, Sec. III for the well-balanced one, Sec. IV for the double
  * well), written for D = 3.  Eq. (24) and Eq. (26) are stated for general
  * dimension; in Eq. (26) the last term carries (|c_i|^2/cs2 - D) with D = 3.
  *
  * Conventions (lattice units, cs2 = 1/3, periodic in x, y and z):
- *   - populations array-of-structures, f[((z*ny + y)*nx + x)*19 + i];
+ *   - populations array-of-structures, f[((z*ny + y)*nx + x)*Q + i];
  *   - fields phi[(z*ny + y)*nx + x];
  *   - velocities: rest, the 6 axis directions (weight 1/18) and the 12 edge
- *     directions (weight 1/36), in the order listed below;
+ *     directions (weight 1/36), in the order listed below; on D3Q27 the 8
+ *     corner directions follow, and the weights are 8/27, 2/27, 1/54, 1/216;
  *   - gradient (1/cs2) sum_i w_i c_i phi(x + c_i), Laplacian
  *     (2/cs2) sum_i w_i [phi(x + c_i) - phi(x)]: for a field that varies
  *     along one axis only they are the central difference and the 3-point
@@ -32,10 +34,13 @@
  * would cost more than the work); the arithmetic is the same either way. */
 #define ORC_OMP_MIN_NODES 16384L
 
-#define Q3 19
 #define CS2 (1.0 / 3.0)
 #define DIM 3.0
 
+#ifndef ORC3_D3Q27
+/* D3Q19: functions orc3_*. */
+#define Q3 19
+#define ORC3(name) orc3_##name
 static const int CX3[Q3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 static const int CY3[Q3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 static const int CZ3[Q3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -43,6 +48,25 @@ static const double WT3[Q3] = {1.0 / 3.0,
                                1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+#else
+/* D3Q27 (lbm_oracle3d27.c): rest (8/27), the 6 axis directions (2/27), the
+ * 12 edge directions (1/54) in the D3Q19 order, then the 8 corners (1/216)
+ * in opposite pairs.  Functions orc27_*. */
+#define Q3 27
+#define ORC3(name) orc27_##name
+static const int CX3[Q3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                            1, -1, 1, -1, 1, -1, -1, 1};
+static const int CY3[Q3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                            1, -1, 1, -1, -1, 1, 1, -1};
+static const int CZ3[Q3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                            1, -1, -1, 1, 1, -1, 1, -1};
+static const double WT3[Q3] = {8.0 / 27.0,
+                               2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+                               1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+                               1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0, 1.0 / 54.0,
+                               1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0,
+                               1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0, 1.0 / 216.0};
+#endif
 
 enum { ORC3_STANDARD = 0, ORC3_WELL_BALANCED = 1, ORC3_STANDARD_EQF = 2 };
 
@@ -63,7 +87,7 @@ static double mu0_3(const orc3_params *p, double rho) {
 }
 
 /* Equilibrium: Eq. (3) standard, Eq. (24) WB (D = 3). */
-void orc3_feq(int scheme, const orc3_params *p, double rho, double ux, double uy,
+void ORC3(feq)(int scheme, const orc3_params *p, double rho, double ux, double uy,
               double uz, double *feq) {
   double uu = ux * ux + uy * uy + uz * uz;
   for (int i = 0; i < Q3; ++i) {
@@ -80,7 +104,7 @@ void orc3_feq(int scheme, const orc3_params *p, double rho, double ux, double uy
 
 /* The standard LBE's other forcing term, named after Eq. (5):
  *   F_i = (c_i - u).F feq_i / (cs2 rho), feq of Eq. (3) at (rho, u). */
-void orc3_forcing_eq(const double *feq, double rho, double ux, double uy, double uz,
+void ORC3(forcing_eq)(const double *feq, double rho, double ux, double uy, double uz,
                      double Fx, double Fy, double Fz, double *Fi) {
   for (int i = 0; i < Q3; ++i) {
     double cmuF = (CX3[i] - ux) * Fx + (CY3[i] - uy) * Fy + (CZ3[i] - uz) * Fz;
@@ -90,7 +114,7 @@ void orc3_forcing_eq(const double *feq, double rho, double ux, double uy, double
 
 /* Forcing term: Eq. (5) standard; Eq. (26) WB with G = F + cs2 grad rho and
  * the term (1/2)(|c|^2/cs2 - D)(u . grad rho), D = 3. */
-void orc3_forcing(int scheme, double ux, double uy, double uz, double Fx, double Fy,
+void ORC3(forcing)(int scheme, double ux, double uy, double uz, double Fx, double Fy,
                   double Fz, double grx, double gry, double grz, double *Fi) {
   double Gx = Fx, Gy = Fy, Gz = Fz;
   if (scheme == ORC3_WELL_BALANCED) {
@@ -118,7 +142,7 @@ static inline size_t idx3(int x, int y, int z, int nx, int ny) {
 }
 
 /* Isotropic central gradient, periodic. */
-void orc3_gradient(int nx, int ny, int nz, const double *phi, double *gx, double *gy,
+void ORC3(gradient)(int nx, int ny, int nz, const double *phi, double *gx, double *gy,
                    double *gz) {
 #pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
   for (int z = 0; z < nz; ++z)
@@ -139,7 +163,7 @@ void orc3_gradient(int nx, int ny, int nz, const double *phi, double *gx, double
 }
 
 /* Isotropic Laplacian, periodic. */
-void orc3_laplacian(int nx, int ny, int nz, const double *phi, double *lap) {
+void ORC3(laplacian)(int nx, int ny, int nz, const double *phi, double *lap) {
 #pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
   for (int z = 0; z < nz; ++z)
     for (int y = 0; y < ny; ++y)
@@ -155,7 +179,7 @@ void orc3_laplacian(int nx, int ny, int nz, const double *phi, double *lap) {
 }
 
 /* rho, u, mu, F and grad rho of the state f (Eqs. 4, 6, 25 in 3-D). */
-void orc3_macro(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *f,
+void ORC3(macro)(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *f,
                 double *rho, double *ux, double *uy, double *uz, double *mu, double *Fx,
                 double *Fy, double *Fz, double *grx, double *gry, double *grz) {
   size_t n = (size_t)nx * ny * nz;
@@ -167,10 +191,10 @@ void orc3_macro(int scheme, const orc3_params *p, int nx, int ny, int nz, const 
     for (int i = 0; i < Q3; ++i) s += f[k * Q3 + i];
     rho[k] = s;
   }
-  orc3_laplacian(nx, ny, nz, rho, lap);
+  ORC3(laplacian)(nx, ny, nz, rho, lap);
   for (size_t k = 0; k < n; ++k) mu[k] = mu0_3(p, rho[k]) - p->kappa * lap[k];
-  orc3_gradient(nx, ny, nz, mu, gmx, gmy, gmz);
-  orc3_gradient(nx, ny, nz, rho, grx, gry, grz);
+  ORC3(gradient)(nx, ny, nz, mu, gmx, gmy, gmz);
+  ORC3(gradient)(nx, ny, nz, rho, grx, gry, grz);
   for (size_t k = 0; k < n; ++k) {
     double fx = -rho[k] * gmx[k], fy = -rho[k] * gmy[k], fz = -rho[k] * gmz[k];
     if (scheme != ORC3_WELL_BALANCED) {
@@ -196,15 +220,15 @@ void orc3_macro(int scheme, const orc3_params *p, int nx, int ny, int nz, const 
 }
 
 /* f_i = feq_i(rho, u); any of ux, uy, uz NULL means 0. */
-void orc3_init(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *rho,
+void ORC3(init)(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *rho,
                const double *ux, const double *uy, const double *uz, double *f) {
   size_t n = (size_t)nx * ny * nz;
   for (size_t k = 0; k < n; ++k)
-    orc3_feq(scheme, p, rho[k], ux ? ux[k] : 0.0, uy ? uy[k] : 0.0, uz ? uz[k] : 0.0, f + k * Q3);
+    ORC3(feq)(scheme, p, rho[k], ux ? ux[k] : 0.0, uy ? uy[k] : 0.0, uz ? uz[k] : 0.0, f + k * Q3);
 }
 
 /* n steps of Eq. (2): collide, then stream to x + c_i; f in place. */
-void orc3_step(int scheme, const orc3_params *p, int nx, int ny, int nz, double *f,
+void ORC3(step)(int scheme, const orc3_params *p, int nx, int ny, int nz, double *f,
                int64_t nsteps) {
   size_t n = (size_t)nx * ny * nz;
   double *buf = (double *)malloc(11 * n * sizeof(double));
@@ -214,18 +238,18 @@ void orc3_step(int scheme, const orc3_params *p, int nx, int ny, int nz, double 
   double *g = (double *)malloc(n * Q3 * sizeof(double));
   double omega = 1.0 / p->tau, fpre = 1.0 - 0.5 / p->tau;
   for (int64_t s = 0; s < nsteps; ++s) {
-    orc3_macro(scheme, p, nx, ny, nz, f, rho, ux, uy, uz, mu, Fx, Fy, Fz, grx, gry, grz);
+    ORC3(macro)(scheme, p, nx, ny, nz, f, rho, ux, uy, uz, mu, Fx, Fy, Fz, grx, gry, grz);
 #pragma omp parallel for schedule(static) if ((long)nx * ny * nz >= ORC_OMP_MIN_NODES)
     for (int z = 0; z < nz; ++z)
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
           size_t k = idx3(x, y, z, nx, ny);
           double feq[Q3], Fi[Q3];
-          orc3_feq(scheme, p, rho[k], ux[k], uy[k], uz[k], feq);
+          ORC3(feq)(scheme, p, rho[k], ux[k], uy[k], uz[k], feq);
           if (scheme == ORC3_STANDARD_EQF)
-            orc3_forcing_eq(feq, rho[k], ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], Fi);
+            ORC3(forcing_eq)(feq, rho[k], ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], Fi);
           else
-            orc3_forcing(scheme, ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], grx[k], gry[k], grz[k],
+            ORC3(forcing)(scheme, ux[k], uy[k], uz[k], Fx[k], Fy[k], Fz[k], grx[k], gry[k], grz[k],
                          Fi);
           for (int i = 0; i < Q3; ++i) {
             double fs = f[k * Q3 + i] - omega * (f[k * Q3 + i] - feq[i]) + fpre * Fi[i];
@@ -251,11 +275,11 @@ static inline void neumaier3(double *sum, double *comp, double v) {
 /* out[0] max|u|, out[1] mass (compensated), out[2] kinetic energy
  * (compensated), out[3] 1 if any rho or u is non-finite or rho <= 0,
  * out[4..6] total momentum sum rho u (compensated, half-force u of Eq. 4). */
-void orc3_observe(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *f,
+void ORC3(observe)(int scheme, const orc3_params *p, int nx, int ny, int nz, const double *f,
                   double *out) {
   size_t n = (size_t)nx * ny * nz;
   double *b = (double *)malloc(11 * n * sizeof(double));
-  orc3_macro(scheme, p, nx, ny, nz, f, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n,
+  ORC3(macro)(scheme, p, nx, ny, nz, f, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n,
              b + 6 * n, b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n);
   double umax = 0.0, ms = 0.0, mc = 0.0, es = 0.0, ec = 0.0, bad = 0.0;
   double ps[3] = {0.0, 0.0, 0.0}, pc[3] = {0.0, 0.0, 0.0};

@@ -26,6 +26,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 SRC3 = os.path.join(HERE, "lbm_oracle3d.c")
+SRC27 = os.path.join(HERE, "lbm_oracle3d27.c")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD_DIR, "liboracle.so")
 
@@ -44,12 +45,12 @@ CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fused multiply-add, OpenMP rows)."""
     if not force and os.path.exists(LIB) and \
-            os.path.getmtime(LIB) >= max(os.path.getmtime(SRC), os.path.getmtime(SRC3)):
+            os.path.getmtime(LIB) >= max(os.path.getmtime(x) for x in (SRC, SRC3, SRC27)):
         return LIB
     os.makedirs(BUILD_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, SRC3, "-lm"]
+           "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, SRC3, SRC27, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -115,6 +116,15 @@ def _load():
             "orc3_init": (None, [i, P, i, i, i, _D, _D, _D, _D, _D]),
             "orc3_step": (None, [i, P, i, i, i, _D, i64]),
             "orc3_observe": (None, [i, P, i, i, i, _D, _D]),
+            "orc27_feq": (None, [i, P, d, d, d, d, _D]),
+            "orc27_forcing": (None, [i] + [d] * 9 + [_D]),
+            "orc27_forcing_eq": (None, [_D] + [d] * 7 + [_D]),
+            "orc27_gradient": (None, [i, i, i, _D, _D, _D, _D]),
+            "orc27_laplacian": (None, [i, i, i, _D, _D]),
+            "orc27_macro": (None, [i, P, i, i, i, _D] + [_D] * 11),
+            "orc27_init": (None, [i, P, i, i, i, _D, _D, _D, _D, _D]),
+            "orc27_step": (None, [i, P, i, i, i, _D, i64]),
+            "orc27_observe": (None, [i, P, i, i, i, _D, _D]),
             "orc_set_threads": (None, [i]),
             "orc_get_threads": (i, []),
         }
@@ -313,88 +323,98 @@ def droplet_diagnostics(p: Params, rho: np.ndarray, cx: float, cy: float) -> dic
     }
 
 
-# ------------------------------------------------------- three dimensions (D3Q19)
-# Populations: shape (nz, ny, nx, 19); fields: (nz, ny, nx).  Velocities:
-# rest, the six axis directions, the twelve edge directions (order of C3).
+# ------------------------------------------- three dimensions (D3Q19, D3Q27)
+# Populations: shape (nz, ny, nx, q); fields: (nz, ny, nx).  q = 19: rest,
+# the six axis directions, the twelve edge directions (order of C3); q = 27
+# adds the eight corner directions (order of C27).  Every 3-D function takes
+# q=19 (default) or q=27.
 C3 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
                [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
                [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+C27 = np.concatenate([C3, np.array([[1, 1, 1], [-1, -1, -1], [1, 1, -1], [-1, -1, 1],
+                                    [1, -1, 1], [-1, 1, -1], [-1, 1, 1], [1, -1, -1]])])
 
 
-def feq3(scheme, p: Params, rho, ux, uy, uz) -> np.ndarray:
-    """D3Q19 equilibrium: Eq. (3) standard, Eq. (24) well-balanced."""
-    out = np.zeros(19)
-    _load().orc3_feq(_scheme3(scheme), ctypes.byref(p.c()), rho, ux, uy, uz, _ptr(out))
+def _fn3(name, q):
+    if q not in (19, 27):
+        raise ValueError("q must be 19 or 27")
+    return getattr(_load(), ("orc3_" if q == 19 else "orc27_") + name)
+
+
+def feq3(scheme, p: Params, rho, ux, uy, uz, q=19) -> np.ndarray:
+    """3-D equilibrium: Eq. (3) standard, Eq. (24) well-balanced."""
+    out = np.zeros(q)
+    _fn3("feq", q)(_scheme3(scheme), ctypes.byref(p.c()), rho, ux, uy, uz, _ptr(out))
     return out
 
 
-def forcing3(scheme, u, F, gr=(0.0, 0.0, 0.0)) -> np.ndarray:
-    """D3Q19 forcing term: Eq. (5) standard, Eq. (26) with D = 3 (the
+def forcing3(scheme, u, F, gr=(0.0, 0.0, 0.0), q=19) -> np.ndarray:
+    """3-D forcing term: Eq. (5) standard, Eq. (26) with D = 3 (the
     equilibrium-proportional form is ``forcing_eq3``)."""
     k = _scheme3(scheme)
     if k == STANDARD_EQF:
         raise ValueError("forcing3(): use forcing_eq3 for the standard_eq_forcing scheme")
-    out = np.zeros(19)
-    _load().orc3_forcing(k, *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
+    out = np.zeros(q)
+    _fn3("forcing", q)(k, *map(float, u), *map(float, F), *map(float, gr), _ptr(out))
     return out
 
 
-def forcing_eq3(p: Params, rho, u, F) -> np.ndarray:
-    """D3Q19 form of the forcing term named after Eq. (5):
+def forcing_eq3(p: Params, rho, u, F, q=19) -> np.ndarray:
+    """3-D form of the forcing term named after Eq. (5):
     F_i = (c_i - u).F feq_i / (cs2 rho), feq of Eq. (3)."""
-    fe = feq3(STANDARD, p, rho, *map(float, u))
-    out = np.zeros(19)
-    _load().orc3_forcing_eq(_ptr(fe), float(rho), *map(float, u), *map(float, F), _ptr(out))
+    fe = feq3(STANDARD, p, rho, *map(float, u), q=q)
+    out = np.zeros(q)
+    _fn3("forcing_eq", q)(_ptr(fe), float(rho), *map(float, u), *map(float, F), _ptr(out))
     return out
 
 
-def gradient3(phi: np.ndarray):
+def gradient3(phi: np.ndarray, q=19):
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     nz, ny, nx = phi.shape
     g = [np.empty_like(phi) for _ in range(3)]
-    _load().orc3_gradient(nx, ny, nz, _ptr(phi), *[_ptr(a) for a in g])
+    _fn3("gradient", q)(nx, ny, nz, _ptr(phi), *[_ptr(a) for a in g])
     return tuple(g)
 
 
-def laplacian3(phi: np.ndarray) -> np.ndarray:
+def laplacian3(phi: np.ndarray, q=19) -> np.ndarray:
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     nz, ny, nx = phi.shape
     out = np.empty_like(phi)
-    _load().orc3_laplacian(nx, ny, nz, _ptr(phi), _ptr(out))
+    _fn3("laplacian", q)(nx, ny, nz, _ptr(phi), _ptr(out))
     return out
 
 
 def macro3(scheme, p: Params, f: np.ndarray) -> dict:
     f = np.ascontiguousarray(f, dtype=np.float64)
-    nz, ny, nx, _ = f.shape
+    nz, ny, nx, q = f.shape
     names = ["rho", "ux", "uy", "uz", "mu", "Fx", "Fy", "Fz", "grx", "gry", "grz"]
     out = {k: np.empty((nz, ny, nx)) for k in names}
-    _load().orc3_macro(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f),
-                       *[_ptr(out[k]) for k in names])
+    _fn3("macro", q)(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f),
+                     *[_ptr(out[k]) for k in names])
     return out
 
 
-def init3(scheme, p: Params, rho: np.ndarray, u=None) -> np.ndarray:
+def init3(scheme, p: Params, rho: np.ndarray, u=None, q=19) -> np.ndarray:
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     nz, ny, nx = rho.shape
     comps = [None, None, None] if u is None else [np.ascontiguousarray(a, dtype=np.float64) for a in u]
-    f = np.empty((nz, ny, nx, 19))
-    _load().orc3_init(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(rho),
-                      *[_ptr(a) for a in comps], _ptr(f))
+    f = np.empty((nz, ny, nx, q))
+    _fn3("init", q)(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(rho),
+                    *[_ptr(a) for a in comps], _ptr(f))
     return f
 
 
 def step3(scheme, p: Params, f: np.ndarray, n: int = 1) -> np.ndarray:
     g = np.array(f, dtype=np.float64, order="C", copy=True)
-    nz, ny, nx, _ = g.shape
-    _load().orc3_step(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(g), int(n))
+    nz, ny, nx, q = g.shape
+    _fn3("step", q)(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(g), int(n))
     return g
 
 
 def observe3(scheme, p: Params, f: np.ndarray) -> dict:
     f = np.ascontiguousarray(f, dtype=np.float64)
-    nz, ny, nx, _ = f.shape
+    nz, ny, nx, q = f.shape
     out = np.zeros(7)
-    _load().orc3_observe(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
+    _fn3("observe", q)(_scheme3(scheme), ctypes.byref(p.c()), nx, ny, nz, _ptr(f), _ptr(out))
     return {"max_u": out[0], "mass": out[1], "kinetic_energy": out[2], "nonfinite": bool(out[3]),
             "momentum": (out[4], out[5], out[6])}
