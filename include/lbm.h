@@ -99,15 +99,21 @@ typedef struct {
                           * Eq. (23) (FP64 or FP32-shifted, ny <= 65535, not
                           * in batches, block widths 256 and 512) */
   int32_t nz;            /* lattice depth: 0 or 1 for the 2-D D2Q9 lattice;
-                          * > 1 for the 3-D D3Q19 lattice of the same method
-                          * (Eqs. 24 and 26 hold for general dimension; here
-                          * D = 3).  3-D lattices run in FP64 or
+                          * > 1 for the 3-D lattice (D3Q19 or D3Q27, see
+                          * lattice3) of the same method (Eqs. 24 and 26
+                          * hold for general dimension; here D = 3).  3-D lattices run in FP64 or
                           * FP32-shifted storage with the central force
                           * stencil, single lattices only, ny and
                           * nz <= 65535, a z-plane of populations
-                          * (19 * ny * nx * element bytes, nx rounded up to
-                          * 32) below 4 GiB; one kernel per step.  Fields
+                          * (q * ny * nx * element bytes, q = 19 or 27, nx
+                          * rounded up to 32) below 4 GiB; one kernel per step.  Fields
                           * are then double[nz][ny][nx]. */
+  int32_t lattice3;      /* velocity set of a 3-D lattice: 0 or 19 for
+                          * D3Q19, 27 for D3Q27 (the 19 velocities and the
+                          * 8 corners (+-1, +-1, +-1); weights 8/27, 2/27,
+                          * 1/54, 1/216, and the gradient and Laplacian
+                          * weighted with them).  Must be 0 on 2-D
+                          * lattices.  D3Q27 tiles: block 256, depth 1..2. */
 } lbm_params;
 
 typedef struct {
@@ -179,7 +185,7 @@ lbm_status lbm_observe(lbm_ctx* ctx, double* rho, double* ux, double* uy, double
 lbm_status lbm_observe_noalloc(lbm_ctx* ctx, double* dev_out);
 
 /* 3-D forms of lbm_init and lbm_observe with the third velocity component
- * (D3Q19 lattices; on a 2-D lattice uz must be NULL and they act as
+ * (3-D lattices; on a 2-D lattice uz must be NULL and they act as
  * lbm_init / lbm_observe).  lbm_init3d takes ux, uy and uz together or none
  * of them; lbm_init on a 3-D lattice accepts only u = 0. */
 lbm_status lbm_init3d(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy,
@@ -188,10 +194,11 @@ lbm_status lbm_observe3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, doub
                          double* mu, lbm_observation* obs);
 
 /* Copy the populations f_i (unshifted, double) to / from host
- * double[9][ny][nx] (3-D: double[19][nz][ny][nx], velocities in the order
+ * double[9][ny][nx] (3-D: double[q][nz][ny][nx], velocities in the order
  * rest, +x, -x, +y, -y, +z, -z, then the edges (1,1,0), (-1,-1,0), (1,-1,0),
  * (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1),
- * (0,1,-1), (0,-1,1)).  Used for checkpoints and tests.  Synchronous.
+ * (0,1,-1), (0,-1,1), and on D3Q27 the corners (1,1,1), (-1,-1,-1),
+ * (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1), (1,-1,-1)).  Used for checkpoints and tests.  Synchronous.
  * lbm_set_populations makes the context initialised with `scheme` and sets
  * the step counter to `step`. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f);
@@ -210,8 +217,9 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme,
  * per block (>= 4) and prefetch depth (rows of populations each thread keeps
  * in flight, 1..3).  3-D lattices (nz > 1): block width 256 or 512 threads
  * (tiles of 32 x 8 or 32 x 16 nodes), rows = z planes each block marches
- * through (>= 1), depth = planes of populations in flight (1..3 with 256
- * threads, 1..2 with 512; 1 is the fastest measured).  Any valid shape gives
+ * through (>= 1), depth = planes of populations in flight (D3Q19: 1..3 with
+ * 256 threads, 1..2 with 512; D3Q27: 256 threads, depth 1..2; 1 is the
+ * fastest measured).  Any valid shape gives
  * bit-identical populations.
  * 0 keeps the current value.  A new 2-D context starts from a default
  * chosen from the lattice size (64-wide strips with short chunks up to

@@ -37,13 +37,16 @@ struct Layout {
   lbmk::Geometry g;
   lbmk::Geometry3 g3;   // 3-D lattices (nz > 1) only
   bool d3 = false;
-  int q = Q;            // populations per node: 9 (D2Q9) or 19 (D3Q19)
+  int q = Q;            // populations per node: 9 (D2Q9), 19 (D3Q19) or 27 (D3Q27)
   size_t elem;
   size_t state_bytes;   // one population copy
   size_t staging_bytes; // dense double fields: 4 (2-D: rho, ux, uy, mu) or 5 (3-D: + uz)
   size_t partial_count; // blocks of the smallest tiling
   size_t off_a, off_b, off_staging, off_partials, total;
 };
+
+// Velocities of a 3-D lattice: 19 (D3Q19, lattice3 = 0 or 19) or 27.
+int q3_of(const lbm_params& p) { return p.lattice3 == lbmk::Q27 ? lbmk::Q27 : lbmk::Q3; }
 
 bool valid_params(const lbm_params* p, std::string* why) {
   if (!p) return *why = "params is NULL", false;
@@ -65,14 +68,17 @@ bool valid_params(const lbm_params* p, std::string* why) {
   // an int
   if (p->nz <= 1 && (long long)Q * (((long long)p->nx + 31) / 32 * 32) > 0x7fffffffLL)
     return *why = "2-D lattices need 9 * nx (rounded up to 32) <= 2^31 - 1", false;
+  if (p->lattice3 != 0 && p->lattice3 != lbmk::Q3 && p->lattice3 != lbmk::Q27)
+    return *why = "lattice3 must be 0, 19 or 27", false;
+  if (p->nz <= 1 && p->lattice3 != 0) return *why = "lattice3 applies to 3-D lattices (nz > 1)", false;
   if (p->nz > 1) {
     if (p->force_stencil != 0) return *why = "3-D lattices use the central force stencil", false;
     if (p->ny > 65535 || p->nz > 65535) return *why = "3-D lattices need ny, nz <= 65535", false;
     // the fused step addresses one z-plane of populations with 32-bit offsets
     const long long px = ((long long)p->nx + 31) / 32 * 32;
     const long long elem = p->precision == LBM_FP64 ? 8 : 4;
-    if ((long long)p->ny * lbmk::Q3 * px * elem > 0xffffffffLL)
-      return *why = "3-D lattices need a z-plane of populations (19 * ny * nx * element bytes) "
+    if ((long long)p->ny * q3_of(*p) * px * elem > 0xffffffffLL)
+      return *why = "3-D lattices need a z-plane of populations (q * ny * nx * element bytes) "
                     "below 4 GiB",
              false;
   }
@@ -96,18 +102,19 @@ Layout make_layout(const lbm_params& p) {
   const size_t chunks = (p.ny + MIN_ROWS - 1) / MIN_ROWS;
   L.partial_count = strips * chunks;
   if (p.nz > 1) {
-    // D3Q19, f[z][y][q][x]: the 19 population rows of a lattice row are
-    // contiguous, as in two dimensions
+    // D3Q19 or D3Q27, f[z][y][q][x]: the q population rows of a lattice row
+    // are contiguous, as in two dimensions
     L.d3 = true;
-    L.q = lbmk::Q3;
+    L.q = q3_of(p);
     L.g3.nx = p.nx;
     L.g3.ny = p.ny;
     L.g3.nz = p.nz;
+    L.g3.q = L.q;
     L.g3.plane = (long long)px;
-    L.g3.pitch = (long long)lbmk::Q3 * px;
+    L.g3.pitch = (long long)L.q * px;
     L.g3.slab = L.g3.pitch * p.ny;
     const size_t n = (size_t)p.nx * p.ny * p.nz;
-    L.state_bytes = align_up((size_t)p.nz * p.ny * lbmk::Q3 * px * L.elem, ALIGN);
+    L.state_bytes = align_up((size_t)p.nz * p.ny * L.q * px * L.elem, ALIGN);
     L.staging_bytes = align_up(5 * n * sizeof(double), ALIGN);
     L.partial_count = (size_t)lbmk::blocks3(L.g3);
   }
@@ -160,24 +167,32 @@ lbmk::Physics make_physics(const lbm_params& p, int scheme) {
   return ph;
 }
 
-// D3Q19 weights in the kernels' velocity order: rest, 6 axis, 12 edge.
-double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// 3-D weights in the kernels' velocity order: rest, 6 axis, 12 edge and
+// (D3Q27) 8 corner directions.
+double w3(int q, int i) {
+  if (q == lbmk::Q3) return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+}
 
-// The 3-D counterparts of feq_rest and shift_of.
+// The 3-D counterparts of feq_rest and shift_of (q3_of(p) entries; the
+// arrays hold QMAX3).
 void feq3_rest(const lbm_params& p, int scheme, double rho, double* f) {
-  for (int i = 0; i < lbmk::Q3; ++i) {
+  const int q = q3_of(p);
+  for (int i = 0; i < lbmk::QMAX3; ++i) f[i] = 0.0;
+  for (int i = 0; i < q; ++i) {
     if (scheme != LBM_WELL_BALANCED)
-      f[i] = w3(i) * rho;
+      f[i] = w3(q, i) * rho;
     else
-      f[i] = (i == 0) ? rho - (1.0 - w3(0)) * p.rho0 : w3(i) * p.rho0;
+      f[i] = (i == 0) ? rho - (1.0 - w3(q, 0)) * p.rho0 : w3(q, i) * p.rho0;
   }
 }
 
 void shift3_of(const lbm_params& p, int scheme, double* s) {
-  for (int i = 0; i < lbmk::Q3; ++i) s[i] = 0.0;
+  const int q = q3_of(p);
+  for (int i = 0; i < lbmk::QMAX3; ++i) s[i] = 0.0;
   if (p.precision == LBM_FP64) return;
   if (p.shift_all) {
-    for (int i = 0; i < lbmk::Q3; ++i) s[i] = w3(i) * p.rho_ref;
+    for (int i = 0; i < q; ++i) s[i] = w3(q, i) * p.rho_ref;
   } else {
     feq3_rest(p, scheme, p.rho_ref, s);
   }
@@ -193,10 +208,10 @@ lbmk::Physics3 make_physics3(const lbm_params& p, int scheme) {
   ph.rho_v = p.rho_v;
   ph.rho0 = p.rho0;
   ph.rho_ref = p.precision == LBM_FP64 ? 0.0 : p.rho_ref;
-  double fr[lbmk::Q3];
+  double fr[lbmk::QMAX3];
   shift3_of(p, scheme, ph.s);
   feq3_rest(p, scheme, ph.rho_ref, fr);
-  for (int i = 0; i < lbmk::Q3; ++i) ph.c[i] = fr[i] - ph.s[i];
+  for (int i = 0; i < lbmk::QMAX3; ++i) ph.c[i] = fr[i] - ph.s[i];
   return ph;
 }
 
@@ -353,11 +368,11 @@ lbm_status convert_shift(lbm_ctx* c, int to_scheme) {
   }
   if (c->d3()) {
     lbmk::Physics3 d{};
-    double so[lbmk::Q3], sn[lbmk::Q3];
+    double so[lbmk::QMAX3], sn[lbmk::QMAX3];
     shift3_of(c->prm, c->scheme, so);
     shift3_of(c->prm, to_scheme, sn);
     bool same = true;
-    for (int i = 0; i < lbmk::Q3; ++i) {
+    for (int i = 0; i < lbmk::QMAX3; ++i) {
       d.s[i] = so[i] - sn[i];
       same = same && d.s[i] == 0.0;
     }
@@ -758,8 +773,11 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
     // depth = planes of populations in flight per thread
     const int ty = block == 0 ? c->tl3.ty : (block % lbmk::M3X ? 0 : block / lbmk::M3X);
     const int d = depth == 0 ? c->tl3.depth : depth;
-    if (!lbmk::tiling3_supported(ty, d))
-      return fail(c, LBM_EINVAL, "3-D tiles: block 256 with depth 1..3 or block 512 with depth 1..2");
+    if (!lbmk::tiling3_supported(c->L.q, ty, d))
+      return fail(c, LBM_EINVAL,
+                  c->L.q == lbmk::Q3
+                      ? "D3Q19 tiles: block 256 with depth 1..3 or block 512 with depth 1..2"
+                      : "D3Q27 tiles: block 256 with depth 1..2");
     if (rows < 0) return fail(c, LBM_EINVAL, "rows (planes per chunk) must be >= 1");
     const lbmk::Tiling3 t = lbmk::make_tiling3(c->L.g3, ty, rows == 0 ? c->tl3.zc : rows, d, 0);
     if (lbmk::blocks_of(t) > 0x7fffffffLL) return fail(c, LBM_EINVAL, "too many blocks");

@@ -1,6 +1,6 @@
 // lbm_kernels3d.h -- internal interface between the host library
-// (lbm_api.cpp) and the D3Q19 kernels (lbm_kernels3d.hip).  Not part of the
-// public ABI.
+// (lbm_api.cpp) and the D3Q19 / D3Q27 kernels (lbm_kernels3d.hip).  Not
+// part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,11 +9,14 @@
 
 namespace lbmk {
 
-// Three-dimensional lattice (D3Q19), populations f[z][y][q][x]: element
-// (x, y, z, q) at z*slab + y*pitch + q*plane + x.
+// Three-dimensional lattice, D3Q19 (q = 19) or D3Q27 (q = 27), populations
+// f[z][y][q][x]: element (x, y, z, q) at z*slab + y*pitch + q*plane + x.
+// D3Q27's velocities are D3Q19's followed by the 8 corner directions.
 constexpr int Q3 = 19;
+constexpr int Q27 = 27;
+constexpr int QMAX3 = 27;
 struct Geometry3 {
-  int nx, ny, nz;
+  int nx, ny, nz, q;
   long long plane, pitch, slab;
 };
 
@@ -23,8 +26,8 @@ struct Geometry3 {
 struct Physics3 {
   double omega, fpre, beta, kappa, rho_l, rho_v, rho0;
   double rho_ref;
-  double c[Q3];
-  double s[Q3];
+  double c[QMAX3];  // first q entries used
+  double s[QMAX3];
 };
 
 // Outputs of the 3-D observe pass (any field may be null).
@@ -41,13 +44,13 @@ struct Tiling3 {
   int ty, zc, depth;
   int tiles_x, tiles_y, chunks;
 };
-// ty: 8 (depth 1..3) or 16 (depth 1..2); zc <= 0 picks the chunk length for
-// about `target` blocks.
+// ty: 8 (depth 1..3 on D3Q19, 1..2 on D3Q27) or 16 (D3Q19 only, depth 1..2);
+// zc <= 0 picks the chunk length for about `target` blocks.
 Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth, int target);
-bool tiling3_supported(int ty, int depth);
+bool tiling3_supported(int q, int ty, int depth);
 long long blocks_of(const Tiling3& t);
 
-// Three dimensions (D3Q19, FP64 or FP32-shifted storage `storage`): init from
+// Three dimensions (g.q = 19 or 27, FP64 or FP32-shifted storage `storage`): init from
 // dense fields (u may be null),
 // pack/unpack m populations from q0 through a dense staging area, one step
 // (one fused pass fin -> fout), and the observe pass (density into `rho`,

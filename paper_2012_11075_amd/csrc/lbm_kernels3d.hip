@@ -1,13 +1,16 @@
-// lbm_kernels3d.hip -- gfx950 kernels of the D3Q19 form of the two-phase
-// LBE step (Eqs. 24 and 26 are stated for general D; here D = 3).
+// lbm_kernels3d.hip -- gfx950 kernels of the three-dimensional form of the
+// two-phase LBE step (Eqs. 24 and 26 are stated for general D; here D = 3),
+// on the D3Q19 and the D3Q27 lattice (template parameter Q).
 //
-// Velocities: rest, the 6 axis directions (weight 1/18), the 12 edge
-// directions (weight 1/36).  Gradient (1/cs2) sum w_i c_i phi(x+c_i) and
-// Laplacian (2/cs2) sum w_i [phi(x+c_i) - phi(x)], as in 2-D.  FP64.
+// Velocities: rest, the 6 axis directions, the 12 edge directions and (D3Q27
+// only) the 8 corner directions; weights 1/3, 1/18, 1/36 (D3Q19) or 8/27,
+// 2/27, 1/54, 1/216 (D3Q27).  Gradient (1/cs2) sum w_i c_i phi(x+c_i) and
+// Laplacian (2/cs2) sum w_i [phi(x+c_i) - phi(x)] with the lattice's
+// weights, as in 2-D.  FP64 or FP32-shifted storage.
 //
 // Step (one HBM pass, `march3`).  A block of 32 x TY threads owns a 32 x TY
 // column of nodes and marches along z through a chunk of planes.  Each
-// plane's populations are loaded once: a thread pulls the 19 populations of
+// plane's populations are loaded once: a thread pulls the Q populations of
 // its own node and keeps them in registers for the two planes until that
 // node's update; the 2-node ring of halo nodes around the tile, whose
 // populations are needed for rho only, is spread over the waves (one node
@@ -35,14 +38,32 @@ namespace {
 template <typename T>
 using Global = __attribute__((address_space(1))) T;
 
+// Velocity c_i: indices 0..18 are D3Q19's, 19..26 the corners D3Q27 adds.
 __device__ __forceinline__ void c3(int i, int& cx, int& cy, int& cz) {
-  const int X[Q3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-  const int Y[Q3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-  const int Z[Q3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  const int X[QMAX3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1,
+                        -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, -1, 1};
+  const int Y[QMAX3] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0,
+                        0, 1, -1, 1, -1, 1, -1, 1, -1, -1, 1, 1, -1};
+  const int Z[QMAX3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1,
+                        1, 1, -1, -1, 1, 1, -1, -1, 1, 1, -1, 1, -1};
   cx = X[i];
   cy = Y[i];
   cz = Z[i];
 }
+
+// Weight of a shell (0 rest, 1 axis, 2 edge, 3 corner) on the Q-velocity
+// lattice, divided in the arithmetic type R.
+template <int Q, typename R>
+__device__ __forceinline__ R wshell(int shell) {
+  if constexpr (Q == 19)
+    return shell == 0 ? (R)1 / (R)3 : shell == 1 ? (R)1 / (R)18 : (R)1 / (R)36;
+  else
+    return shell == 0   ? (R)8 / (R)27
+           : shell == 1 ? (R)2 / (R)27
+           : shell == 2 ? (R)1 / (R)54
+                        : (R)1 / (R)216;
+}
+__device__ __forceinline__ int shell_of(int i) { return i == 0 ? 0 : i < 7 ? 1 : i < 19 ? 2 : 3; }
 
 // Element offset (without the q * plane term) that the pull of population q
 // of node (x, y, z) reads: the node (x, y, z) - c_q, periodic.
@@ -63,19 +84,19 @@ __device__ __forceinline__ R mu0_3(R r, const Physics3& p) {
 }
 
 // Equilibrium (Eq. 3 / Eq. 24) and forcing term (Eq. 5 / Eq. 26 with D = 3:
-// the last term's coefficient (|c|^2/cs2 - 3)/2 is -3/2, 0, 3/2 for the
-// rest, axis and edge directions), then BGK, f*_i = f_i - omega (f_i - feq_i)
-// + fpre F_i; emit(i, f*_i) receives each post-collision population as soon
-// as it is known.  The velocities come in opposite pairs (1,2), (3,4), ...,
-// (17,18); every term of feq_i and F_i is even or odd in c_i, so a pair
-// evaluates its even and odd parts once.  A scheduling barrier after every G
-// pairs keeps the compiler from computing all 19 at once (each result then
-// dies at its store instead of holding a register).  FP32 storage holds
+// the last term's coefficient (|c|^2/cs2 - 3)/2 is -3/2, 0, 3/2, 3 for the
+// rest, axis, edge and corner directions), then BGK, f*_i = f_i - omega
+// (f_i - feq_i) + fpre F_i; emit(i, f*_i) receives each post-collision
+// population as soon as it is known.  The velocities come in opposite pairs
+// (1,2), (3,4), ..., (Q-2,Q-1); every term of feq_i and F_i is even or odd
+// in c_i, so a pair evaluates its even and odd parts once.  A scheduling
+// barrier after every G pairs keeps the compiler from computing all Q at
+// once (each result then dies at its store instead of holding a register).  FP32 storage holds
 // g_i = f_i - s_i: the equilibrium is then taken as feq_i(rho, u) -
 // feq_i(rho_ref, 0) from drho = rho - rho_ref, plus the constant
 // c_i = feq_i(rho_ref, 0) - s_i (the rho0 terms cancel).
-template <int SCHEME, int G, typename R, typename E>
-__device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, R uy, R uz, R Fx,
+template <int Q, int SCHEME, int G, typename R, typename E>
+__device__ __forceinline__ void collide3(const R (&f)[Q], R drho, R rho, R ux, R uy, R uz, R Fx,
                                          R Fy, R Fz, R grx, R gry, R grz, const Physics3& p,
                                          E&& emit) {
   constexpr bool SHIFTED = sizeof(R) == 4;
@@ -90,9 +111,10 @@ __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, 
   const R ugr = ux * grx + uy * gry + uz * grz;
   const R omega = (R)p.omega, fpre = (R)p.fpre, rho0 = (R)p.rho0;
   // even forcing constant of a shell: k u.grad(rho) - 3 u.G (WB: k = 0 on the
-  // axes, 3/2 on the edges)
+  // axes, 3/2 on the edges, 3 at the corners)
   const R ev_axis = -uG3;
   const R ev_edge = SCHEME == WELL_BALANCED ? (R)1.5 * ugr - uG3 : -uG3;
+  const R ev_corner = SCHEME == WELL_BALANCED ? (R)3 * ugr - uG3 : -uG3;
   auto pair = [&](int i, R cu, R cF, R cG, R w, R ev) {
     const R ep = (R)4.5 * (cu * cu) - u15;  // even part of poly_i
     const R wr = w * rho;
@@ -119,10 +141,10 @@ __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, 
   auto sched = [&]() {
     if (G > 0 && ++np % G == 0) __builtin_amdgcn_sched_barrier(0);
   };
-  const R wa = (R)1 / (R)18, we = (R)1 / (R)36;
+  const R wa = wshell<Q, R>(1), we = wshell<Q, R>(2);
   // rest population (c_0 = 0)
   {
-    const R w0 = (R)1 / (R)3;
+    const R w0 = wshell<Q, R>(0);
     R feq0, F0;
     if (SCHEME == WELL_BALANCED) {
       feq0 = SHIFTED ? (drho - w0 * rho * u15) + (R)p.c[0] : rho - ((R)1 - w0) * rho0 - w0 * rho * u15;
@@ -150,54 +172,87 @@ __device__ __forceinline__ void collide3(const R (&f)[Q3], R drho, R rho, R ux, 
   pair(15, uy + uz, Fy + Fz, Gy + Gz, we, ev_edge);
   sched();
   pair(17, uy - uz, Fy - Fz, Gy - Gz, we, ev_edge);
+  if constexpr (Q == 27) {
+    const R wc = wshell<Q, R>(3);
+    sched();
+    pair(19, (ux + uy) + uz, (Fx + Fy) + Fz, (Gx + Gy) + Gz, wc, ev_corner);
+    sched();
+    pair(21, (ux + uy) - uz, (Fx + Fy) - Fz, (Gx + Gy) - Gz, wc, ev_corner);
+    sched();
+    pair(23, (ux - uy) + uz, (Fx - Fy) + Fz, (Gx - Gy) + Gz, wc, ev_corner);
+    sched();
+    pair(25, (uy + uz) - ux, (Fy + Fz) - Fx, (Gy + Gz) - Gx, wc, ev_corner);
+  }
 }
 
 // rho = sum_i f_i in a fixed order (every kernel sums a node the same way).
-template <typename R>
-__device__ __forceinline__ R sum19(const R (&f)[Q3]) {
+template <int Q, typename R>
+__device__ __forceinline__ R sumq(const R (&f)[Q]) {
   R s = (R)0;
 #pragma unroll
-  for (int i = 0; i < Q3; ++i) s += f[i];
+  for (int i = 0; i < Q; ++i) s += f[i];
   return s;
 }
 
-// 19-point Laplacian (2/cs2) sum_i w_i [phi(x + c_i) - phi(x)] from
-// at(dx, dy, dz) = phi(x + (dx, dy, dz)); the sums pair +z with -z.
-template <typename R, typename A>
-__device__ __forceinline__ R lap19(const A& at, R c) {
+// Isotropic Laplacian (2/cs2) sum_i w_i [phi(x + c_i) - phi(x)] from
+// at(dx, dy, dz) = phi(x + (dx, dy, dz)); the sums pair +z with -z.  D3Q19:
+// (2 axis + edge - 24 phi)/6; D3Q27: (16 axis + 4 edge + corner - 152 phi)/36.
+template <int Q, typename R, typename A>
+__device__ __forceinline__ R lapq(const A& at, R c) {
   const R ax = ((at(1, 0, 0) + at(-1, 0, 0)) + (at(0, 1, 0) + at(0, -1, 0))) +
                (at(0, 0, 1) + at(0, 0, -1));
   const R xy = (at(1, 1, 0) + at(-1, -1, 0)) + (at(1, -1, 0) + at(-1, 1, 0));
   const R xz = (at(1, 0, 1) + at(1, 0, -1)) + (at(-1, 0, -1) + at(-1, 0, 1));
   const R yz = (at(0, 1, 1) + at(0, 1, -1)) + (at(0, -1, -1) + at(0, -1, 1));
-  return ((R)2 * ax + ((xy + xz) + yz) - (R)24 * c) * ((R)1 / (R)6);
+  if constexpr (Q == 19) {
+    return ((R)2 * ax + ((xy + xz) + yz) - (R)24 * c) * ((R)1 / (R)6);
+  } else {
+    const R co = ((at(1, 1, 1) + at(1, 1, -1)) + (at(-1, -1, -1) + at(-1, -1, 1))) +
+                 ((at(1, -1, 1) + at(1, -1, -1)) + (at(-1, 1, -1) + at(-1, 1, 1)));
+    return (((R)16 * ax + (R)4 * ((xy + xz) + yz)) + (co - (R)152 * c)) * ((R)1 / (R)36);
+  }
 }
 
 // Isotropic central gradient (1/cs2) sum_i w_i c_i phi(x + c_i) at row j,
 // column i of the LDS plane a0, with am and ap the planes at z - 1 and z + 1.
 // Swapping am and ap negates gz exactly and leaves gx, gy unchanged.
-template <int W, typename R>
+// Coefficients 3 w: D3Q19 axis 1/6, edge 1/12; D3Q27 axis 2/9, edge 1/18,
+// corner 1/72.
+template <int Q, int W, typename R>
 __device__ __forceinline__ void grad3p(const R (*am)[W], const R (*a0)[W], const R (*ap)[W], int j,
                                        int i, R& gx, R& gy, R& gz) {
-  const R s6 = (R)1 / (R)6, s12 = (R)1 / (R)12;
-  gx = (a0[j][i + 1] - a0[j][i - 1]) * s6 +
+  const R sa = Q == 19 ? (R)1 / (R)6 : (R)2 / (R)9;
+  const R se = Q == 19 ? (R)1 / (R)12 : (R)1 / (R)18;
+  gx = (a0[j][i + 1] - a0[j][i - 1]) * sa +
        (((a0[j + 1][i + 1] - a0[j + 1][i - 1]) + (a0[j - 1][i + 1] - a0[j - 1][i - 1])) +
         ((ap[j][i + 1] - ap[j][i - 1]) + (am[j][i + 1] - am[j][i - 1]))) *
-           s12;
-  gy = (a0[j + 1][i] - a0[j - 1][i]) * s6 +
+           se;
+  gy = (a0[j + 1][i] - a0[j - 1][i]) * sa +
        (((a0[j + 1][i + 1] - a0[j - 1][i + 1]) + (a0[j + 1][i - 1] - a0[j - 1][i - 1])) +
         ((ap[j + 1][i] - ap[j - 1][i]) + (am[j + 1][i] - am[j - 1][i]))) *
-           s12;
-  gz = (ap[j][i] - am[j][i]) * s6 +
+           se;
+  gz = (ap[j][i] - am[j][i]) * sa +
        (((ap[j][i + 1] - am[j][i + 1]) + (ap[j][i - 1] - am[j][i - 1])) +
         ((ap[j + 1][i] - am[j + 1][i]) + (ap[j - 1][i] - am[j - 1][i]))) *
-           s12;
+           se;
+  if constexpr (Q == 27) {
+    const R sc = (R)1 / (R)72;
+    gx += (((ap[j + 1][i + 1] - ap[j + 1][i - 1]) + (am[j + 1][i + 1] - am[j + 1][i - 1])) +
+           ((ap[j - 1][i + 1] - ap[j - 1][i - 1]) + (am[j - 1][i + 1] - am[j - 1][i - 1]))) *
+          sc;
+    gy += (((ap[j + 1][i + 1] - ap[j - 1][i + 1]) + (am[j + 1][i + 1] - am[j - 1][i + 1])) +
+           ((ap[j + 1][i - 1] - ap[j - 1][i - 1]) + (am[j + 1][i - 1] - am[j - 1][i - 1]))) *
+          sc;
+    gz += (((ap[j + 1][i + 1] - am[j + 1][i + 1]) + (ap[j + 1][i - 1] - am[j + 1][i - 1])) +
+           ((ap[j - 1][i + 1] - am[j - 1][i + 1]) + (ap[j - 1][i - 1] - am[j - 1][i - 1]))) *
+          sc;
+  }
 }
 
 // Force (F = -rho grad mu for WB, Eq. 25; plus grad(rho)/3 for the standard
 // scheme, Eq. 6) and the half-force velocity of Eq. (4).
-template <int SCHEME, typename R>
-__device__ __forceinline__ void force_velocity3(const R (&f)[Q3], R r, R grx, R gry, R grz, R gmx,
+template <int Q, int SCHEME, typename R>
+__device__ __forceinline__ void force_velocity3(const R (&f)[Q], R r, R grx, R gry, R grz, R gmx,
                                                 R gmy, R gmz, R& Fx, R& Fy, R& Fz, R& ux, R& uy,
                                                 R& uz) {
   Fx = -r * gmx;
@@ -210,7 +265,7 @@ __device__ __forceinline__ void force_velocity3(const R (&f)[Q3], R r, R grx, R 
   }
   R jx = (R)0, jy = (R)0, jz = (R)0;
 #pragma unroll
-  for (int i = 0; i < Q3; ++i) {
+  for (int i = 0; i < Q; ++i) {
     int cx, cy, cz;
     c3(i, cx, cy, cz);
     if (cx) jx += cx > 0 ? f[i] : -f[i];
@@ -287,13 +342,13 @@ __device__ __forceinline__ Pull3 pull_of(const Geometry3& g, int x, int y) {
   return s;
 }
 
-// The 19 pulled populations of node s on a plane; b[c_z + 1] is the plane
+// The Q pulled populations of node s on a plane; b[c_z + 1] is the plane
 // z - c_z, pb the bytes between populations.
-template <typename T>
-__device__ __forceinline__ void load19(const __amdgpu_buffer_rsrc_t (&b)[3], unsigned pb,
-                                       const Pull3& s, T (&f)[Q3]) {
+template <int Q, typename T>
+__device__ __forceinline__ void loadq(const __amdgpu_buffer_rsrc_t (&b)[3], unsigned pb,
+                                      const Pull3& s, T (&f)[Q]) {
 #pragma unroll
-  for (int q = 0; q < Q3; ++q) {
+  for (int q = 0; q < Q; ++q) {
     int cx, cy, cz;
     c3(q, cx, cy, cz);
     f[q] = buf_load<T>(b[cz + 1], s.off[cy + 1][cx + 1], q * pb);
@@ -303,7 +358,7 @@ __device__ __forceinline__ void load19(const __amdgpu_buffer_rsrc_t (&b)[3], uns
 // Fused step: one block per (32 x TY column, chunk of tl.zc planes).  D:
 // planes of populations loaded ahead of the plane being summed (0 = none).
 constexpr int CG = 1;  // velocity pairs per scheduling region of the collision
-template <typename T, int SCHEME, int TY, int D>
+template <typename T, int SCHEME, int TY, int D, int Q>
 __global__ void __launch_bounds__(M3X * TY)
     march3(Geometry3 g, Physics3 p, Tiling3 tl, const T* __restrict__ fin, T* __restrict__ fout) {
   using R = T;
@@ -317,7 +372,7 @@ __global__ void __launch_bounds__(M3X * TY)
   // (each thread its own column); halo of planes k .. k+D-1.
   constexpr int RP = 2 + D, RH = D > 0 ? D : 1;
   constexpr int U = (RP % RH == 0) ? RP : RP * RH;  // unroll: slots are compile-time
-  __shared__ R pk[Q3][NT];
+  __shared__ R pk[Q][NT];
   __shared__ R rs[5][RY][RX];  // region (i, j) is lattice (x0 - 2 + i, y0 - 2 + j)
   __shared__ R ms[3][MY][MX];  // region (i, j) is lattice (x0 - 1 + i, y0 - 1 + j)
   const int t = threadIdx.x;
@@ -365,24 +420,24 @@ __global__ void __launch_bounds__(M3X * TY)
       (unsigned)(((long long)(y0 + ty) * g.pitch + (x0 + tx)) * (long long)sizeof(T));
 
   // Loads of plane k.
-  auto load_plane = [&](int k, R(&Pl)[Q3], R(&Hl)[Q3]) {
+  auto load_plane = [&](int k, R(&Pl)[Q], R(&Hl)[Q]) {
     const int z = plane_of(k);
     __amdgpu_buffer_rsrc_t b[3];
 #pragma unroll
     for (int c = -1; c <= 1; ++c)
       b[c + 1] = plane_buffer<T>(fin + (long long)wrapi(z - c, g.nz) * g.slab, slab_bytes);
-    load19<T>(b, pb, si, Pl);
-    if (hl) load19<T>(b, pb, sh, Hl);
+    loadq<Q, T>(b, pb, si, Pl);
+    if (hl) loadq<Q, T>(b, pb, sh, Hl);
   };
 
   // Plane step k: publish rho of plane k (populations in Pk, halo in Hk),
   // start the loads of plane k+D (into Pn, Hk), mu of plane k-1, update the
   // nodes of plane k-2 (populations parked in LDS), park plane k-1 (Pm).
-  auto stage = [&](int k, R(&Pk)[Q3], R(&Hk)[Q3], R(&Pn)[Q3], R(&Pm)[Q3]) {
+  auto stage = [&](int k, R(&Pk)[Q], R(&Hk)[Q], R(&Pn)[Q], R(&Pm)[Q]) {
     if (D == 0) load_plane(k, Pk, Hk);
     const int sk = k % 5;
-    rs[sk][ty + 2][tx + 2] = rho_ref + sum19(Pk);
-    if (hl) rs[sk][hj][hi] = rho_ref + sum19(Hk);
+    rs[sk][ty + 2][tx + 2] = rho_ref + sumq<Q>(Pk);
+    if (hl) rs[sk][hj][hi] = rho_ref + sumq<Q>(Hk);
     if (D > 0 && k + D < K) load_plane(k + D, Pn, Hk);
     __syncthreads();
     if (k >= 2) {
@@ -394,7 +449,7 @@ __global__ void __launch_bounds__(M3X * TY)
           return rs[dz < 0 ? sm : (dz > 0 ? sk : s0)][j + dy][i + dx];
         };
         const R r0 = rs[s0][j][i];
-        ms[mk][mj][mi] = mu0_3(r0, p) - kappa * lap19(at, r0);
+        ms[mk][mj][mi] = mu0_3(r0, p) - kappa * lapq<Q>(at, r0);
       }
     }
     __syncthreads();
@@ -407,19 +462,19 @@ __global__ void __launch_bounds__(M3X * TY)
       if (k >= 4) {
         const int sM = (c - 1) % 5, s0 = c % 5, sP = (c + 1) % 5;
         const int mM = (c - 1) % 3, m0 = c % 3, mP = (c + 1) % 3;
-        grad3p<RX>(rs[sM], rs[s0], rs[sP], ty + 2, tx + 2, grx, gry, grz);
-        grad3p<MX>(ms[mM], ms[m0], ms[mP], ty + 1, tx + 1, gmx, gmy, gmz);
+        grad3p<Q, RX>(rs[sM], rs[s0], rs[sP], ty + 2, tx + 2, grx, gry, grz);
+        grad3p<Q, MX>(ms[mM], ms[m0], ms[mP], ty + 1, tx + 1, gmx, gmy, gmz);
         r = rs[s0][ty + 2][tx + 2];
       }
       __builtin_amdgcn_sched_barrier(0);
-      R f[Q3];
+      R f[Q];
       if (k >= 4) {
 #pragma unroll
-        for (int q = 0; q < Q3; ++q) f[q] = pk[q][t];
+        for (int q = 0; q < Q; ++q) f[q] = pk[q][t];
       }
       if (k >= 3) {
 #pragma unroll
-        for (int q = 0; q < Q3; ++q) pk[q][t] = Pm[q];
+        for (int q = 0; q < Q; ++q) pk[q][t] = Pm[q];
       }
       __builtin_amdgcn_sched_barrier(0);
       if (k >= 4) {
@@ -428,17 +483,17 @@ __global__ void __launch_bounds__(M3X * TY)
           gmz = -gmz;
         }
         R Fx, Fy, Fz, ux, uy, uz;
-        force_velocity3<SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
+        force_velocity3<Q, SCHEME>(f, r, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, ux, uy, uz);
         const __amdgpu_buffer_rsrc_t o =
             plane_buffer<T>(fout + (long long)plane_of(c) * g.slab, slab_bytes);
-        const R drho = sum19(f);
-        collide3<SCHEME, CG>(f, drho, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p,
+        const R drho = sumq<Q>(f);
+        collide3<Q, SCHEME, CG>(f, drho, r, ux, uy, uz, Fx, Fy, Fz, grx, gry, grz, p,
                              [&](int q, R v) { buf_store_nt<T>(v, o, own_off, q * pb); });
       }
     }
   };
 
-  R P[RP][Q3], H[RH][Q3];
+  R P[RP][Q], H[RH][Q];
 #pragma unroll
   for (int k = 0; k < D; ++k) load_plane(k, P[k], H[k % RH]);
   for (int k0 = 0; k0 < K; k0 += U) {
@@ -451,18 +506,18 @@ __global__ void __launch_bounds__(M3X * TY)
 
 // Observe pass, in the storage type's arithmetic as the step (FP32 storage:
 // rho = rho_ref + sum_i g_i, then every stencil in FP32); fields as double.
-template <typename T>
+template <typename T, int Q>
 __global__ void __launch_bounds__(256)
     density3(Geometry3 g, Physics3 p, const Global<T>* __restrict__ fin, double* __restrict__ rho) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
-  T f[Q3];
+  T f[Q];
 #pragma unroll
-  for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
-  rho[((long long)z * g.ny + y) * g.nx + x] = (double)((T)p.rho_ref + sum19(f));
+  for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
+  rho[((long long)z * g.ny + y) * g.nx + x] = (double)((T)p.rho_ref + sumq<Q>(f));
 }
 
-template <typename T>
+template <typename T, int Q>
 __global__ void __launch_bounds__(256)
     potential3(Geometry3 g, Physics3 p, const double* __restrict__ rho, double* __restrict__ mu) {
   using R = T;
@@ -473,14 +528,14 @@ __global__ void __launch_bounds__(256)
     return (R)rho[((long long)c * g.ny + b) * g.nx + a];
   };
   const R c = at(0, 0, 0);
-  mu[((long long)z * g.ny + y) * g.nx + x] = (double)(mu0_3(c, p) - (R)p.kappa * lap19(at, c));
+  mu[((long long)z * g.ny + y) * g.nx + x] = (double)(mu0_3(c, p) - (R)p.kappa * lapq<Q>(at, c));
 }
 
 constexpr int T3X = 32, T3Y = 4, T3Z = 2;  // observe block (threads)
 
 // Fields and per-block partials (max|u|, mass, kinetic energy, non-finite
 // flag, momentum) of the state f, from dense rho and mu.
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, int Q>
 __global__ void __launch_bounds__(T3X * T3Y * T3Z)
     observe3_kernel(Geometry3 g, const Global<T>* __restrict__ fin,
                     const double* __restrict__ rho, const double* __restrict__ mu,
@@ -504,15 +559,15 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
   const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
   NodeSums acc;
   if (x < g.nx && y < g.ny && z < g.nz) {
-    R f[Q3];
+    R f[Q];
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
+    for (int i = 0; i < Q; ++i) f[i] = fin[(long long)i * g.plane + src3(g, i, x, y, z)];
     const R rr = rt[tz + 1][ty + 1][tx + 1];
     R grx, gry, grz, gmx, gmy, gmz;
-    grad3p<T3X + 2>(rt[tz], rt[tz + 1], rt[tz + 2], ty + 1, tx + 1, grx, gry, grz);
-    grad3p<T3X + 2>(mt[tz], mt[tz + 1], mt[tz + 2], ty + 1, tx + 1, gmx, gmy, gmz);
+    grad3p<Q, T3X + 2>(rt[tz], rt[tz + 1], rt[tz + 2], ty + 1, tx + 1, grx, gry, grz);
+    grad3p<Q, T3X + 2>(mt[tz], mt[tz + 1], mt[tz + 2], ty + 1, tx + 1, gmx, gmy, gmz);
     R Fx, Fy, Fz, uxr, uyr, uzr;
-    force_velocity3<SCHEME>(f, rr, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, uxr, uyr, uzr);
+    force_velocity3<Q, SCHEME>(f, rr, grx, gry, grz, gmx, gmy, gmz, Fx, Fy, Fz, uxr, uyr, uzr);
     const double r = (double)rr, ux = (double)uxr, uy = (double)uyr, uz = (double)uzr;
     const long long o = ((long long)z * g.ny + y) * g.nx + x;
     if (obs.ux) obs.ux[o] = ux;
@@ -536,7 +591,7 @@ __global__ void __launch_bounds__(T3X * T3Y * T3Z)
 
 // f = feq(rho, u) of every node (in double), stored minus the storage shift
 // s_i where the next pull reads it.
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, int Q>
 __global__ void __launch_bounds__(256)
     init3_kernel(Geometry3 g, Physics3 p, const double* __restrict__ rho,
                  const double* __restrict__ ux, const double* __restrict__ uy,
@@ -547,10 +602,10 @@ __global__ void __launch_bounds__(256)
   const double r = rho[k];
   const double vx = ux ? ux[k] : 0.0, vy = uy ? uy[k] : 0.0, vz = uz ? uz[k] : 0.0;
   const double u15 = 1.5 * (vx * vx + vy * vy + vz * vz);
-  for (int i = 0; i < Q3; ++i) {
+  for (int i = 0; i < Q; ++i) {
     int cx, cy, cz;
     c3(i, cx, cy, cz);
-    const double w = i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    const double w = wshell<Q, double>(shell_of(i));
     const double cu = cx * vx + cy * vy + cz * vz;
     const double poly = 3.0 * cu + 4.5 * cu * cu - u15;
     double q;
@@ -588,7 +643,7 @@ __global__ void __launch_bounds__(256)
     reshift3_kernel(Geometry3 g, Physics3 d, T* __restrict__ f) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= g.nx) return;
-  for (int q = 0; q < Q3; ++q) {
+  for (int q = 0; q < g.q; ++q) {
     const long long o = (long long)z * g.slab + (long long)y * g.pitch + (long long)q * g.plane + x;
     f[o] = (T)((double)f[o] + d.s[q]);
   }
@@ -606,25 +661,32 @@ int blocks3(const Geometry3& g) {
   return ((g.nx + T3X - 1) / T3X) * ((g.ny + T3Y - 1) / T3Y) * ((g.nz + T3Z - 1) / T3Z);
 }
 
+namespace {
+
+template <typename T, int Q>
+void launch_init3_t(int scheme, const Geometry3& g, const Physics3& ph, const double* rho,
+                    const double* ux, const double* uy, const double* uz, void* f, hipStream_t s) {
+  if (scheme == STANDARD)
+    hipLaunchKernelGGL((init3_kernel<T, STANDARD, Q>), grid_rows3(g), dim3(256), 0, s, g, ph, rho,
+                       ux, uy, uz, (T*)f);
+  else
+    hipLaunchKernelGGL((init3_kernel<T, WELL_BALANCED, Q>), grid_rows3(g), dim3(256), 0, s, g, ph,
+                       rho, ux, uy, uz, (T*)f);
+}
+
+}  // namespace
+
 hipError_t launch_init3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
                         const double* rho, const double* ux, const double* uy, const double* uz,
                         void* f, hipStream_t s) {
   if (scheme == STANDARD_EQF) scheme = STANDARD;  // same equilibrium
-  if (storage == FP64) {
-    if (scheme == STANDARD)
-      hipLaunchKernelGGL((init3_kernel<double, STANDARD>), grid_rows3(g), dim3(256), 0, s, g, ph,
-                         rho, ux, uy, uz, (double*)f);
-    else
-      hipLaunchKernelGGL((init3_kernel<double, WELL_BALANCED>), grid_rows3(g), dim3(256), 0, s, g,
-                         ph, rho, ux, uy, uz, (double*)f);
-  } else {
-    if (scheme == STANDARD)
-      hipLaunchKernelGGL((init3_kernel<float, STANDARD>), grid_rows3(g), dim3(256), 0, s, g, ph,
-                         rho, ux, uy, uz, (float*)f);
-    else
-      hipLaunchKernelGGL((init3_kernel<float, WELL_BALANCED>), grid_rows3(g), dim3(256), 0, s, g,
-                         ph, rho, ux, uy, uz, (float*)f);
-  }
+  if (g.q != Q3 && g.q != Q27) return hipErrorInvalidValue;
+  if (storage == FP64)
+    (g.q == Q3 ? launch_init3_t<double, Q3> : launch_init3_t<double, Q27>)(scheme, g, ph, rho, ux,
+                                                                          uy, uz, f, s);
+  else
+    (g.q == Q3 ? launch_init3_t<float, Q3> : launch_init3_t<float, Q27>)(scheme, g, ph, rho, ux,
+                                                                        uy, uz, f, s);
   return hipGetLastError();
 }
 
@@ -685,54 +747,74 @@ Tiling3 make_tiling3(const Geometry3& g, int ty, int zc, int depth, int target) 
   return t;
 }
 
-bool tiling3_supported(int ty, int depth) {
-  return (ty == 8 && depth >= 1 && depth <= 3) || (ty == 16 && depth >= 1 && depth <= 2);
+bool tiling3_supported(int q, int ty, int depth) {
+  // D3Q27 in FP64 needs the register file and the accumulation registers of
+  // a wave at 256 threads per block; 512 would spill to memory
+  if (q == Q27) return ty == 8 && depth >= 1 && depth <= 2;
+  return q == Q3 &&
+         ((ty == 8 && depth >= 1 && depth <= 3) || (ty == 16 && depth >= 1 && depth <= 2));
 }
 
 long long blocks_of(const Tiling3& t) { return (long long)t.tiles_x * t.tiles_y * t.chunks; }
 
 namespace {
 
-template <typename T, int SCHEME, int TY, int D>
+template <typename T, int SCHEME, int TY, int D, int Q>
 void launch_m3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const T* in, T* out,
                long long nb, hipStream_t s) {
-  hipLaunchKernelGGL((march3<T, SCHEME, TY, D>), dim3((unsigned)nb), dim3(M3X * TY), 0, s, g, ph,
-                     t, in, out);
+  hipLaunchKernelGGL((march3<T, SCHEME, TY, D, Q>), dim3((unsigned)nb), dim3(M3X * TY), 0, s, g,
+                     ph, t, in, out);
 }
 
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, int Q>
 hipError_t launch_march3(const Geometry3& g, const Physics3& ph, const Tiling3& t, const T* in,
                          T* out, hipStream_t s) {
   const long long nb = blocks_of(t);
   if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (!tiling3_supported(Q, t.ty, t.depth)) return hipErrorInvalidValue;
   if (t.ty == 8 && t.depth == 1)
-    launch_m3<T, SCHEME, 8, 0>(g, ph, t, in, out, nb, s);
+    launch_m3<T, SCHEME, 8, 0, Q>(g, ph, t, in, out, nb, s);
   else if (t.ty == 8 && t.depth == 2)
-    launch_m3<T, SCHEME, 8, 1>(g, ph, t, in, out, nb, s);
-  else if (t.ty == 8 && t.depth == 3)
-    launch_m3<T, SCHEME, 8, 2>(g, ph, t, in, out, nb, s);
-  else if (t.ty == 16 && t.depth == 1)
-    launch_m3<T, SCHEME, 16, 0>(g, ph, t, in, out, nb, s);
-  else if (t.ty == 16 && t.depth == 2)
-    launch_m3<T, SCHEME, 16, 1>(g, ph, t, in, out, nb, s);
-  else
+    launch_m3<T, SCHEME, 8, 1, Q>(g, ph, t, in, out, nb, s);
+  else if constexpr (Q == Q3) {
+    if (t.ty == 16 && t.depth == 1)
+      launch_m3<T, SCHEME, 16, 0, Q>(g, ph, t, in, out, nb, s);
+    else if (t.ty == 8 && t.depth == 3)
+      launch_m3<T, SCHEME, 8, 2, Q>(g, ph, t, in, out, nb, s);
+    else if (t.ty == 16 && t.depth == 2)
+      launch_m3<T, SCHEME, 16, 1, Q>(g, ph, t, in, out, nb, s);
+    else
+      return hipErrorInvalidValue;
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int Q>
+hipError_t launch_step3_t(int scheme, const Geometry3& g, const Physics3& ph, const Tiling3& t,
+                          const void* fin, void* fout, hipStream_t s) {
+  const auto* in = (const T*)fin;
+  auto* out = (T*)fout;
+  if (scheme == STANDARD) return launch_march3<T, STANDARD, Q>(g, ph, t, in, out, s);
+  if (scheme == STANDARD_EQF) return launch_march3<T, STANDARD_EQF, Q>(g, ph, t, in, out, s);
+  return launch_march3<T, WELL_BALANCED, Q>(g, ph, t, in, out, s);
+}
+
+template <typename T, int Q>
 hipError_t launch_observe3_t(int scheme, const Geometry3& g, const Physics3& ph, const void* f,
                              double* rho, double* mu, const ObserveOut3& o, hipStream_t s) {
   const auto* in = (const Global<T>*)(const T*)f;
-  hipLaunchKernelGGL(density3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, in, rho);
-  hipLaunchKernelGGL(potential3<T>, grid_rows3(g), dim3(256), 0, s, g, ph, (const double*)rho, mu);
+  hipLaunchKernelGGL((density3<T, Q>), grid_rows3(g), dim3(256), 0, s, g, ph, in, rho);
+  hipLaunchKernelGGL((potential3<T, Q>), grid_rows3(g), dim3(256), 0, s, g, ph,
+                     (const double*)rho, mu);
   const dim3 gc((g.nx + T3X - 1) / T3X, (g.ny + T3Y - 1) / T3Y, (g.nz + T3Z - 1) / T3Z);
   if (scheme != WELL_BALANCED)  // both standard forms: same force and velocity
-    hipLaunchKernelGGL((observe3_kernel<T, STANDARD>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
+    hipLaunchKernelGGL((observe3_kernel<T, STANDARD, Q>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
                        (const double*)rho, (const double*)mu, o);
   else
-    hipLaunchKernelGGL((observe3_kernel<T, WELL_BALANCED>), gc, dim3(T3X * T3Y * T3Z), 0, s, g, in,
-                       (const double*)rho, (const double*)mu, o);
+    hipLaunchKernelGGL((observe3_kernel<T, WELL_BALANCED, Q>), gc, dim3(T3X * T3Y * T3Z), 0, s, g,
+                       in, (const double*)rho, (const double*)mu, o);
   return hipGetLastError();
 }
 
@@ -742,25 +824,25 @@ hipError_t launch_step3(int storage, int scheme, const Geometry3& g, const Physi
                         const Tiling3& t, const void* fin, void* fout, hipStream_t s) {
   const long long elem = storage == FP64 ? 8 : 4;
   if (g.slab * elem > 0xffffffffLL) return hipErrorInvalidValue;
-  if (storage == FP64) {
-    const auto* in = (const double*)fin;
-    auto* out = (double*)fout;
-    if (scheme == STANDARD) return launch_march3<double, STANDARD>(g, ph, t, in, out, s);
-    if (scheme == STANDARD_EQF) return launch_march3<double, STANDARD_EQF>(g, ph, t, in, out, s);
-    return launch_march3<double, WELL_BALANCED>(g, ph, t, in, out, s);
-  }
-  const auto* in = (const float*)fin;
-  auto* out = (float*)fout;
-  if (scheme == STANDARD) return launch_march3<float, STANDARD>(g, ph, t, in, out, s);
-  if (scheme == STANDARD_EQF) return launch_march3<float, STANDARD_EQF>(g, ph, t, in, out, s);
-  return launch_march3<float, WELL_BALANCED>(g, ph, t, in, out, s);
+  if (g.q == Q3)
+    return storage == FP64 ? launch_step3_t<double, Q3>(scheme, g, ph, t, fin, fout, s)
+                           : launch_step3_t<float, Q3>(scheme, g, ph, t, fin, fout, s);
+  if (g.q == Q27)
+    return storage == FP64 ? launch_step3_t<double, Q27>(scheme, g, ph, t, fin, fout, s)
+                           : launch_step3_t<float, Q27>(scheme, g, ph, t, fin, fout, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Physics3& ph,
                            const void* f, double* rho, double* mu, const ObserveOut3& o,
                            hipStream_t s) {
-  return storage == FP64 ? launch_observe3_t<double>(scheme, g, ph, f, rho, mu, o, s)
-                         : launch_observe3_t<float>(scheme, g, ph, f, rho, mu, o, s);
+  if (g.q == Q3)
+    return storage == FP64 ? launch_observe3_t<double, Q3>(scheme, g, ph, f, rho, mu, o, s)
+                           : launch_observe3_t<float, Q3>(scheme, g, ph, f, rho, mu, o, s);
+  if (g.q == Q27)
+    return storage == FP64 ? launch_observe3_t<double, Q27>(scheme, g, ph, f, rho, mu, o, s)
+                           : launch_observe3_t<float, Q27>(scheme, g, ph, f, rho, mu, o, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lbmk

@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
                 ("beta", ctypes.c_double), ("kappa", ctypes.c_double), ("rho_l", ctypes.c_double),
                 ("rho_v", ctypes.c_double), ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("shift_all", ctypes.c_int32),
-                ("force_stencil", ctypes.c_int32), ("nz", ctypes.c_int32)]
+                ("force_stencil", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lattice3", ctypes.c_int32)]
 
 
 class Observation(ctypes.Structure):
@@ -136,16 +137,17 @@ def _scheme(s) -> int:
 
 
 def make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                rho_ref=None, shift_all=False, force_stencil=0, nz=0) -> Params:
+                rho_ref=None, shift_all=False, force_stencil=0, nz=0, q3=19) -> Params:
     """force_stencil: 0 the central gradients of Sec. II in the force, 1 the
-    fourth-order ones (single lattices only).  nz > 1: a 3-D D3Q19 lattice
-    (single lattices).  Both run in FP64 or FP32-shifted storage."""
+    fourth-order ones (single lattices only).  nz > 1: a 3-D lattice (single
+    lattices) with q3 = 19 (D3Q19) or 27 (D3Q27) velocities.  All run in FP64
+    or FP32-shifted storage."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     if rho_ref is None:
         rho_ref = 0.5 * (rho_l + rho_v)
     return Params(int(nx), int(ny), float(tau), float(beta), float(kappa), float(rho_l),
                   float(rho_v), float(rho0), float(rho_ref), prec, int(bool(shift_all)),
-                  int(force_stencil), int(nz))
+                  int(force_stencil), int(nz), int(q3) if int(nz) > 1 else 0)
 
 
 def stream_handle(stream=None) -> int:
@@ -158,17 +160,17 @@ class Solver:
     """One periodic lattice on the current HIP device."""
 
     def __init__(self, nx, ny, tau, beta, kappa, rho_l, rho_v, rho0=0.0, precision="fp64",
-                 rho_ref=None, shift_all=False, stream=None, force_stencil=0, nz=0):
+                 rho_ref=None, shift_all=False, stream=None, force_stencil=0, nz=0, q3=19):
         import torch
         self.lib = load()
         self.params = make_params(nx, ny, tau, beta, kappa, rho_l, rho_v, rho0, precision,
-                                  rho_ref, shift_all, force_stencil, nz)
+                                  rho_ref, shift_all, force_stencil, nz, q3)
         self.nx, self.ny = int(nx), int(ny)
         self.nz = int(nz) if int(nz) > 1 else 0
         # field and population shapes: (ny, nx) and (9, ny, nx) in 2-D,
-        # (nz, ny, nx) and (19, nz, ny, nx) in 3-D
+        # (nz, ny, nx) and (q3, nz, ny, nx) in 3-D
         self.shape = (self.nz, self.ny, self.nx) if self.nz else (self.ny, self.nx)
-        self.q = 19 if self.nz else 9
+        self.q = int(q3) if self.nz else 9
         nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise LbmError(-1, "invalid parameters")
@@ -249,7 +251,7 @@ class Solver:
         return f
 
     def get_populations(self) -> np.ndarray:
-        """Populations as (9, ny, nx) doubles (unshifted); 3-D: (19, nz, ny, nx)."""
+        """Populations as (9, ny, nx) doubles (unshifted); 3-D: (q3, nz, ny, nx)."""
         f = np.empty((self.q,) + self.shape)
         self._check(self.lib.lbm_get_populations(self.ctx, _dptr(f)))
         return f

@@ -77,6 +77,35 @@ def test_row_pitch_overflow_rejected(lib):
     assert lib.lbm_workspace_bytes(ctypes.byref(P(238_609_312, 2, 1.0, 0.1, 0.02, 1, 0.1))) == 0
 
 
+def test_lattice3_selector(lib):
+    """lattice3 picks the 3-D velocity set: 0 or 19 D3Q19, 27 D3Q27 (two
+    population copies of 27 instead of 19 per node); any other value, or a
+    non-zero value on a 2-D lattice, is rejected."""
+    P = lbm.make_params
+    n19 = lib.lbm_workspace_bytes(ctypes.byref(P(64, 64, 1.0, 0.1, 0.02, 1, 0.1, nz=64)))
+    n27 = lib.lbm_workspace_bytes(ctypes.byref(P(64, 64, 1.0, 0.1, 0.02, 1, 0.1, nz=64, q3=27)))
+    p19 = P(64, 64, 1.0, 0.1, 0.02, 1, 0.1, nz=64)
+    p19.lattice3 = 19
+    assert lib.lbm_workspace_bytes(ctypes.byref(p19)) == n19
+    assert n27 - n19 == 2 * 8 * 8 * 64 ** 3
+    for bad in (1, 9, 26, 28, -1):
+        q = P(64, 64, 1.0, 0.1, 0.02, 1, 0.1, nz=64)
+        q.lattice3 = bad
+        assert lib.lbm_workspace_bytes(ctypes.byref(q)) == 0
+    flat = P(64, 64, 1.0, 0.1, 0.02, 1, 0.1)
+    flat.lattice3 = 27
+    assert lib.lbm_workspace_bytes(ctypes.byref(flat)) == 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(flat), 0x100000, 1 << 40, None, ctypes.byref(h)) == -1
+    assert b"lattice3" in lib.lbm_last_error(None)
+    # a z-plane of 27 populations must stay below 4 GiB: 27 * 2048 * 2048 * 8
+    # bytes is 864 MiB; 27 * 65535 * 512 * 8 bytes = 6.7 GiB is rejected
+    assert lib.lbm_workspace_bytes(ctypes.byref(P(512, 65535, 1.0, 0.1, 0.02, 1, 0.1, nz=2,
+                                                  q3=27))) == 0
+    assert lib.lbm_workspace_bytes(ctypes.byref(P(2048, 2048, 1.0, 0.1, 0.02, 1, 0.1, nz=2,
+                                                  q3=27))) > 0
+
+
 def test_params_struct_matches_header(lib):
     """lbm_params as ctypes lays it out: the field order of include/lbm.h."""
     import re
