@@ -361,13 +361,12 @@ def time_largest(steps, warmup, n=32768):
                         "after %d" % (n, steps, warmup)}
 
 
-D3_BYTES = 304         # FP64 bytes per node of the 3-D step: 19 populations read and written
-
-
-def time_d3q19(steps, warmup, side=None, tile=None, precision="fp64"):
-    """The 3-D (D3Q19) WB step on a side^3 droplet (FP64): one fused pass
-    per step, 19 populations read and written = 304 algorithmic bytes per
-    node.  `tile` (block threads, planes per chunk) overrides the default."""
+def time_d3(steps, warmup, side=None, tile=None, precision="fp64", q=19):
+    """The 3-D WB step on a side^3 droplet on the D3Q19 (q = 19) or D3Q27
+    (q = 27) lattice: one fused pass per step, q populations read and written
+    = 16 q algorithmic bytes per node in FP64 (304 for D3Q19, 432 for D3Q27),
+    8 q in FP32-shifted storage.  `tile` (block threads, planes per chunk)
+    overrides the default."""
     import torch
     from paper_2012_11075_amd import inputs as I
     from paper_2012_11075_amd import lbm
@@ -375,7 +374,8 @@ def time_d3q19(steps, warmup, side=None, tile=None, precision="fp64"):
     ph = I.PHYS3
     rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
                              I.equilibrium_width(ph), 1e-3, seed=13)
-    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n, precision=precision)
+    s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n, precision=precision,
+                   q3=q)
     if tile:
         s.set_tile(*tile)
     s.init(rho, scheme="well_balanced")
@@ -397,16 +397,16 @@ def time_d3q19(steps, warmup, side=None, tile=None, precision="fp64"):
     del s
     torch.cuda.empty_cache()
     nodes = n ** 3
-    bpu = D3_BYTES // 2 if precision == "fp32s" else D3_BYTES
+    bpu = (8 if precision == "fp32s" else 16) * q
     gbs = bpu * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
             "precision": precision, "kernels_per_step": kps, "bytes_per_update": bpu,
             "tile": list(used),
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
-            "workload": "D3Q19 droplet %d^3, R=%g, rho_l=1, rho_v=0.1, beta=0.01, kappa=0.0128, tau=1, "
-                        "WB, %s, %d steps" % (n, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
-                                              precision.upper(), steps)}
+            "workload": "D3Q%d droplet %d^3, R=%g, rho_l=1, rho_v=0.1, beta=0.01, kappa=0.0128, "
+                        "tau=1, WB, %s, %d steps" % (q, n, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
+                                                     precision.upper(), steps)}
 
 
 def copy_reference(nx, ny):
@@ -620,10 +620,12 @@ def main():
         progress("largest lattice %s" % out["largest_lattice"].get("ms_per_step",
                                                                    out["largest_lattice"]))
     if not args.no_d3:
-        out["d3q19"] = time_d3q19(100, 50)
-        out["d3q19"]["fp32_shifted"] = time_d3q19(100, 50, precision="fp32s")
-        progress("D3Q19 %.4f ms/step (FP32 %.4f)" % (out["d3q19"]["ms_per_step"],
-                                                     out["d3q19"]["fp32_shifted"]["ms_per_step"]))
+        for q in (19, 27):
+            key = "d3q%d" % q
+            out[key] = time_d3(100, 50, q=q)
+            out[key]["fp32_shifted"] = time_d3(100, 50, precision="fp32s", q=q)
+            progress("D3Q%d %.4f ms/step (FP32 %.4f)" % (q, out[key]["ms_per_step"],
+                                                         out[key]["fp32_shifted"]["ms_per_step"]))
     if not args.no_batch:
         out["batched"] = {}
         for prec in ("fp32s", "fp64"):

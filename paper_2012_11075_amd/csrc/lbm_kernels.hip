@@ -34,6 +34,13 @@
 
 #include "lbm_kernels.h"
 
+// Multiply-adds are fused only within one source expression, never across
+// statements: the fusion is then fixed by the code as written, not by how
+// the compiler lays out a kernel's blocks, so kernels of different shape
+// that evaluate a node with the same expressions (every tile, the observe
+// pass, the batched step) round it the same way, bit for bit.
+#pragma clang fp contract(on)
+
 namespace lbmk {
 namespace {
 
