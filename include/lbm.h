@@ -241,8 +241,10 @@ int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
 
 /* ------------------------------------------------------------------ batch */
 /* Many independent lattices of uneven size advanced together: each step is
- * one launch per group of slots that share precision, scheme, block width
- * and prefetch depth, and per lane (even and odd slot index), with one block
+ * one launch per group of slots that share precision, scheme, force stencil
+ * (the central one of Sec. II or the fourth-order variant discussed after
+ * Eq. 23), block width and prefetch depth, and per lane (even and odd slot
+ * index), with one block
  * per tile of those slots, reading a device-resident slot table.  Lane 0
  * runs on the batch's stream, lane 1 on a second stream of the batch that
  * forks from it and joins it again within each lbm_batch_run, so one lane's
@@ -271,9 +273,10 @@ size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots);
 lbm_status lbm_batch_create(void* dev_arena, size_t bytes, int32_t max_slots, void* hip_stream,
                             lbm_batch** out);
 
-/* Admit a lattice: allocate its workspace in the arena, set f(0) = feq(rho, 0)
- * (as lbm_init) and mark it active; every scheme of lbm_scheme is accepted,
- * and each slot steps with the scheme it was admitted with.  It retires at the first lbm_batch_poll
+/* Admit a 2-D lattice (nz 0 or 1; either force stencil): allocate its
+ * workspace in the arena, set f(0) = feq(rho, 0) (as lbm_init) and mark it
+ * active; every scheme of lbm_scheme is accepted, and each slot steps with
+ * the scheme it was admitted with.  It retires at the first lbm_batch_poll
  * that finds max|u| < tol (tol <= 0: never) or step >= step_cap (<= 0: no
  * cap), or a non-finite state.  LBM_EBUSY if no slot or arena range is free
  * (nothing changes).  Synchronous. */
@@ -285,7 +288,8 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* params, const double*
  * the graph size (lbm_batch_set_graph_steps). */
 lbm_status lbm_batch_run(lbm_batch* b, int32_t k_steps);
 
-/* Observe every active slot (one batched launch per group), retire the slots
+/* Observe every active slot (one batched launch per group of the central
+ * stencil; the fourth-order variant's three-pass observe per slot), retire the slots
  * that meet their criterion and write their indices to retired[0..n) (at most
  * cap).  Synchronous. */
 lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* n_retired);
@@ -302,7 +306,8 @@ lbm_status lbm_batch_fetch(lbm_batch* b, int32_t slot, double* rho, double* ux, 
 lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
 
 /* Tile of a slot's kernels (as lbm_set_tile; block width 64, 128 or 256 and
- * depth 1, 2 or 3 for batches). */
+ * depth 1, 2 or 3 for batches; the fourth-order force stencil's slots run
+ * block width 256 only). */
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block_width, int32_t rows,
                               int32_t depth);
 

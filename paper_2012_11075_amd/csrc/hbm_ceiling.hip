@@ -7,8 +7,12 @@
 // elements), a kernel that reads the nine population rows of every lattice
 // row and writes them to a second buffer with non-temporal stores, in FP64
 // and in FP32, plus a plain vectorised copy of the same number of bytes.
-// Prints one JSON line.  A step that moves 144 (72) bytes per node cannot
-// run faster than the first two figures allow.
+// As checks on those figures from other access patterns it also times a
+// read-only stream of the FP64 buffer (32-byte loads, nothing stored), a
+// write-only stream of it (32-byte stores), and the runtime's own
+// device-to-device copy of it (hipMemcpyAsync).  Prints one JSON line.  A
+// step that moves 144 (72) bytes per node cannot run faster than the first
+// two figures allow.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -64,6 +68,26 @@ __global__ void copy_vec(const double4* __restrict__ a, double4* __restrict__ b,
     b[i] = a[i];
 }
 
+// Reads every element; the store is taken only for a sum no buffer of this
+// program holds (the buffers are zero), so nothing is written, but the
+// loads cannot be dropped.
+__global__ void read_vec(const double4* __restrict__ a, double* __restrict__ out, long long n) {
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double4 v = a[i];
+    s += (v.x + v.y) + (v.z + v.w);
+  }
+  if (s == 1234.5) out[blockIdx.x] = s;
+}
+
+__global__ void write_vec(double4* __restrict__ b, long long n) {
+  const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = z;
+}
+
 template <typename F>
 double time_us(F launch, int iters, hipEvent_t e0, hipEvent_t e1) {
   launch();
@@ -110,12 +134,25 @@ int main(int argc, char** argv) {
   const double usc = time_us([&] {
     copy_vec<<<65536, 256>>>((const double4*)a, (double4*)b, n4);
   }, iters, e0, e1);
+  double* sink = nullptr;
+  CHECK(hipMalloc(&sink, 65536 * sizeof(double)));
+  const double usr = time_us([&] {
+    read_vec<<<65536, 256>>>((const double4*)a, sink, n4);
+  }, iters, e0, e1);
+  const double usw = time_us([&] { write_vec<<<65536, 256>>>((double4*)b, n4); }, iters, e0, e1);
+  const double usd = time_us([&] {
+    CHECK(hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, 0));
+  }, iters, e0, e1);
   CHECK(hipGetLastError());
   const double nodes = (double)nx * ny;
   printf("{\"nx\": %d, \"ny\": %d, \"rows_copy_fp64_us\": %.1f, \"rows_copy_fp64_gbs\": %.0f, "
-         "\"rows_copy_fp32_us\": %.1f, \"rows_copy_fp32_gbs\": %.0f, \"vector_copy_gbs\": %.0f}\n",
+         "\"rows_copy_fp32_us\": %.1f, \"rows_copy_fp32_gbs\": %.0f, \"vector_copy_gbs\": %.0f, "
+         "\"read_only_gbs\": %.0f, \"write_only_gbs\": %.0f, \"runtime_d2d_copy_gbs\": %.0f, "
+         "\"buffer_bytes\": %zu}\n",
          nx, ny, us64, 144.0 * nodes / us64 / 1e3, us32, 72.0 * nodes / us32 / 1e3,
-         2.0 * bytes / usc / 1e3);
+         2.0 * bytes / usc / 1e3, bytes / usr / 1e3, bytes / usw / 1e3, 2.0 * bytes / usd / 1e3,
+         bytes);
+  CHECK(hipFree(sink));
   CHECK(hipFree(a));
   CHECK(hipFree(b));
   return 0;

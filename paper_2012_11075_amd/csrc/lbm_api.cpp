@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <bitset>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -860,8 +861,12 @@ int32_t lbm_kernels_per_step(const lbm_ctx* c) {
 namespace {
 
 constexpr int kBatchBlocks[3] = {64, 128, 256};
-constexpr int kGroups = 2 * 3 * 3 * 3;  // storage x scheme x block x depth
-static_assert(kGroups <= 64, "group masks are 64-bit");
+// Launch groups: storage x scheme x block x depth for the main step, then
+// storage x scheme x depth for the force-stencil variant (block width
+// kBatch4Block).
+constexpr int kPlainGroups = 2 * 3 * 3 * 3;
+constexpr int kGroups = kPlainGroups + 2 * 3 * 3;
+using GroupMask = std::bitset<kGroups>;
 // Each group's slots are split into two lanes (even and odd slot index), each
 // with its own table, launched on its own stream: the lanes hold disjoint
 // lattices, so one lane's next step fills the compute units that the other
@@ -905,12 +910,12 @@ struct lbm_batch {
   std::vector<Range> free_ranges;  // sorted by offset, coalesced
 
   std::vector<std::vector<char>> host_tab;  // per group and lane
-  uint64_t group_mask = 0;                  // groups that have ever held a slot
-  uint64_t active_mask[kLanes] = {};        // per lane: groups with an active slot (launched)
+  GroupMask group_mask;                     // groups that have ever held a slot
+  GroupMask active_mask[kLanes];            // per lane: groups with an active slot (launched)
   bool dirty = true;
   int graph_steps = 0;
   hipGraphExec_t graph[kLanes] = {};
-  uint64_t graph_mask[kLanes] = {};
+  GroupMask graph_mask[kLanes];
   int tiles_of[kLanes][kGroups] = {};     // work items (tiles) of each table, as uploaded
   int graph_tiles[kLanes][kGroups] = {};  // the same when a lane's graph was captured
   hipStream_t side = nullptr;             // the second lane's stream
@@ -941,15 +946,25 @@ lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
   } while (0)
 
 int group_of(const lbm_ctx* c, int scheme) {
+  if (c->prm.force_stencil == 1)
+    return kPlainGroups + (c->storage() * 3 + scheme) * 3 + (c->tl.depth - 1);
   const int bi = block_index(c->tl.block);
   return ((c->storage() * 3 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
 }
 
-void group_decode(int g, int* storage, int* scheme, int* block, int* depth) {
-  *depth = g % 3 + 1;
-  g /= 3;
-  *block = kBatchBlocks[g % 3];
-  g /= 3;
+void group_decode(int g, int* storage, int* scheme, int* block, int* depth, bool* stencil4) {
+  *stencil4 = g >= kPlainGroups;
+  if (*stencil4) {
+    g -= kPlainGroups;
+    *depth = g % 3 + 1;
+    g /= 3;
+    *block = lbmk::kBatch4Block;
+  } else {
+    *depth = g % 3 + 1;
+    g /= 3;
+    *block = kBatchBlocks[g % 3];
+    g /= 3;
+  }
   *scheme = g % 3;
   *storage = g / 3;
 }
@@ -990,9 +1005,9 @@ bool alloc_range(lbm_batch* b, size_t size, Range* out) {
 // Rebuild the group tables from the active slots and upload them.
 lbm_status upload_tables(lbm_batch* b) {
   size_t part = 0;
-  uint64_t active[kLanes] = {};
+  GroupMask active[kLanes];
   for (int g = 0; g < kGroups; ++g) {
-    if (!(b->group_mask >> g & 1)) continue;
+    if (!b->group_mask.test(g)) continue;
     for (int lane = 0; lane < kLanes; ++lane) {
       std::vector<char>& h = b->host_tab[g * kLanes + lane];
       std::fill(h.begin(), h.end(), 0);
@@ -1017,7 +1032,7 @@ lbm_status upload_tables(lbm_batch* b) {
       }
       tab->nslots = n;
       tab->total_tiles = tiles;
-      if (n > 0) active[lane] |= 1ull << g;
+      if (n > 0) active[lane].set(g);
       b->tiles_of[lane][g] = tiles;
       part += tiles;
       if (part > b->part_cap)
@@ -1039,11 +1054,16 @@ lbm_status upload_tables(lbm_batch* b) {
 lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
     for (int g = 0; g < kGroups; ++g) {
-      if (!(b->active_mask[lane] >> g & 1)) continue;
+      if (!b->active_mask[lane].test(g)) continue;
       int storage, scheme, block, depth;
-      group_decode(g, &storage, &scheme, &block, &depth);
-      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g, lane),
-                                 b->tiles_of[lane][g], j & 1, s));
+      bool stencil4;
+      group_decode(g, &storage, &scheme, &block, &depth, &stencil4);
+      if (stencil4)
+        BHIP(b, lbmk::launch_batch4(storage, scheme, depth, b->dev_tab(g, lane),
+                                    b->tiles_of[lane][g], j & 1, s));
+      else
+        BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g, lane),
+                                   b->tiles_of[lane][g], j & 1, s));
     }
   }
   return LBM_OK;
@@ -1167,7 +1187,6 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
-  if (p->force_stencil != 0) return bfail(b, LBM_EINVAL, "batches use the central force stencil");
   if (p->nz > 1) return bfail(b, LBM_EINVAL, "batches hold 2-D lattices");
   int idx = -1;
   for (int i = 0; i < b->max_slots; ++i)
@@ -1186,8 +1205,10 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
     return bfail(b, st, lbm_last_error(nullptr));
   }
   // default tile of a slot (callers normally set a tuned one): block width
-  // by lattice width, 32-row chunks, two rows in flight
-  const int block = p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256);
+  // by lattice width, 32-row chunks, two rows in flight; the force-stencil
+  // variant runs 256-wide blocks
+  const int block =
+      p->force_stencil == 1 ? lbmk::kBatch4Block : (p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256));
   c->tl = make_tiling(c->L.g, block, 32, 2);
   st = lbm_init(c, rho, nullptr, nullptr, scheme);
   if (st != LBM_OK) {
@@ -1204,7 +1225,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   s.tol = tol;
   s.cap = cap;
   s.scheme = scheme;
-  b->group_mask |= 1ull << group_of(c, scheme);
+  b->group_mask.set(group_of(c, scheme));
   b->dirty = true;
   *slot = idx;
   return LBM_OK;
@@ -1214,10 +1235,12 @@ lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t
   lbm_batch::Slot* s = slot_of(b, slot);
   if (!s) return bfail(b, LBM_EINVAL, "no such slot");
   if (block != 0 && block_index(block) < 0) return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
+  if (block != 0 && s->ctx->prm.force_stencil == 1 && block != lbmk::kBatch4Block)
+    return bfail(b, LBM_EINVAL, "force-stencil slots run 256-wide blocks");
   if (depth < 0 || depth > 3) return bfail(b, LBM_EINVAL, "batch depth must be 1, 2 or 3");
   lbm_status st = lbm_set_tile(s->ctx, block, rows, depth);
   if (st != LBM_OK) return bfail(b, st, s->ctx->err);
-  b->group_mask |= 1ull << group_of(s->ctx, s->scheme);
+  b->group_mask.set(group_of(s->ctx, s->scheme));
   b->dirty = true;
   return LBM_OK;
 }
@@ -1244,7 +1267,7 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t k) {
   BHIP(b, hipEventRecord(b->fork, b->stream));
   BHIP(b, hipStreamWaitEvent(b->side, b->fork, 0));
   for (int lane = 0; lane < kLanes; ++lane) {
-    if (!b->active_mask[lane]) continue;
+    if (b->active_mask[lane].none()) continue;
     hipStream_t ls = lane == 0 ? b->stream : b->side;
     int left = k;
     if (b->graph_steps >= 2) {
@@ -1282,10 +1305,11 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
     if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
   if (total == 0) return LBM_OK;
   for (int lane = 0; lane < kLanes; ++lane)
-    for (int g = 0; g < kGroups; ++g) {
-      if (!(b->active_mask[lane] >> g & 1)) continue;
+    for (int g = 0; g < kPlainGroups; ++g) {
+      if (!b->active_mask[lane].test(g)) continue;
       int storage, scheme, block, depth;
-      group_decode(g, &storage, &scheme, &block, &depth);
+      bool stencil4;
+      group_decode(g, &storage, &scheme, &block, &depth, &stencil4);
       BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g, lane),
                                  b->tiles_of[lane][g], 0, b->stream));
     }
@@ -1298,8 +1322,17 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   for (size_t i = 0; i < b->slots.size(); ++i) {
     lbm_batch::Slot& s = b->slots[i];
     if (s.status != LBM_SLOT_ACTIVE) continue;
-    const bool bad = finish_partials(&part[lbmk::NPART * s.part_index], (size_t)s.tiles,
-                                     s.ctx->step, &s.last);
+    bool bad;
+    if (s.ctx->prm.force_stencil == 1) {
+      // the variant's observe pass (three launches into the slot's own
+      // staging and partials), as lbm_observe on the slot alone
+      const lbm_status os = observe_impl(s.ctx, nullptr, nullptr, nullptr, nullptr, nullptr, &s.last);
+      if (os != LBM_OK && os != LBM_ENONFINITE) return bfail(b, os, s.ctx->err);
+      bad = os == LBM_ENONFINITE;
+    } else {
+      bad = finish_partials(&part[lbmk::NPART * s.part_index], (size_t)s.tiles, s.ctx->step,
+                            &s.last);
+    }
     const double umax = s.last.max_u;
     int st = LBM_SLOT_ACTIVE;
     if (bad)

@@ -170,6 +170,13 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
                         const BatchTable* tab, int tiles, int parity, hipStream_t s);
 
+// Batched step of a launch group of force-stencil slots (block width
+// kBatch4Block, depth 1..3): one block per tile, as launch_batch.  The
+// variant's observe pass runs per slot (launch_observe4).
+constexpr int kBatch4Block = 256;
+hipError_t launch_batch4(int storage, int scheme, int depth, const BatchTable* tab, int tiles,
+                         int parity, hipStream_t s);
+
 // Force-stencil variant (FP64 or FP32-shifted storage): one step as one fused
 // launch on the tiling `t` (block width 256 or 512, depth 1..3), and the
 // observe pass of that variant in three launches (density into `rho`,

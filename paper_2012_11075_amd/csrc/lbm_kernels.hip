@@ -485,14 +485,10 @@ __global__ void __launch_bounds__(BW)
 // contiguous range of the list), so horizontally adjacent tiles run together
 // on one XCD and share their halo lines in its L2.  The table lives in
 // device memory; `parity` selects which of each slot's two buffers is read.
-template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
-__global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__ tab, int parity) {
-  const int total = tab->total_tiles;
-  const int ns = tab->nslots;
-  const int item = xcd_tile(blockIdx.x, total);
-  if (item >= total) return;
-  // slot of this item: last slot whose first tile <= item (uniform search)
-  int lo = 0, hi = ns - 1;
+// Slot of work item `item`: the last slot whose first tile <= item (a
+// search uniform over the block).
+__device__ __forceinline__ int slot_of_item(const BatchTable* __restrict__ tab, int item) {
+  int lo = 0, hi = tab->nslots - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (tab->slot[mid].tile0 <= item)
@@ -500,6 +496,15 @@ __global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__
     else
       hi = mid - 1;
   }
+  return lo;
+}
+
+template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
+__global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__ tab, int parity) {
+  const int total = tab->total_tiles;
+  const int item = xcd_tile(blockIdx.x, total);
+  if (item >= total) return;
+  const int lo = slot_of_item(tab, item);
   // The slot's record is copied into locals: read through a reference into
   // the table, its fields would be re-loaded after every population store
   // (the compiler cannot rule out that the stores alias the table), and each
@@ -668,16 +673,16 @@ __global__ void __launch_bounds__(S4X * S4Y)
 // after it is loaded (rows k-3 .. k-1 wait in LDS).  Stencil sums pair the
 // rows above and below, so the march direction changes no bit of the result.
 template <typename T, int SCHEME, int BW, int D>
-__global__ void __launch_bounds__(BW)
-    march4(Geometry g, Physics phys, Tiling tl, const Global<T>* __restrict__ fin,
-           Global<T>* __restrict__ fout) {
+__device__ __forceinline__ void march4_tile(const Geometry& g, const Physics& phys,
+                                            const Tiling& tl, int tile,
+                                            const Global<T>* __restrict__ fin,
+                                            Global<T>* __restrict__ fout) {
   using R = T;
   __shared__ R rs[7][BW + 6];  // column j: lattice column x0 - 3 + j
   __shared__ R ms[5][BW + 4];  // column m: lattice column x0 - 2 + m
   __shared__ R fl[3][Q][BW];   // populations of rows k-3 .. k-1, each thread its own column
   const PhysR<R> p = to_r<R>(phys);
   const int t = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, tl.strips * tl.chunks);
   const int chunk = tile / tl.strips;
   const int strip = tile - chunk * tl.strips;
   const int x0 = strip * BW;
@@ -833,6 +838,30 @@ __global__ void __launch_bounds__(BW)
       stage(k + 3, s2, s3, h2, h3);
     }
   }
+}
+
+template <typename T, int SCHEME, int BW, int D>
+__global__ void __launch_bounds__(BW)
+    march4(Geometry g, Physics phys, Tiling tl, const Global<T>* __restrict__ fin,
+           Global<T>* __restrict__ fout) {
+  march4_tile<T, SCHEME, BW, D>(g, phys, tl, xcd_tile(blockIdx.x, tl.strips * tl.chunks), fin,
+                                fout);
+}
+
+// The force-stencil variant's step over a batch table (as march_batch).
+template <typename T, int SCHEME, int BW, int D>
+__global__ void __launch_bounds__(BW) march4_batch(const BatchTable* __restrict__ tab, int parity) {
+  const int total = tab->total_tiles;
+  const int item = xcd_tile(blockIdx.x, total);
+  if (item >= total) return;
+  const BatchSlot* sp = &tab->slot[slot_of_item(tab, item)];
+  const Geometry g = sp->g;
+  const Physics ph = sp->ph;
+  const Tiling tl = sp->tl;
+  const int which = sp->cur ^ parity;
+  march4_tile<T, SCHEME, BW, D>(g, ph, tl, item - sp->tile0,
+                                (const Global<T>*)(const T*)sp->buf[which],
+                                (Global<T>*)(T*)sp->buf[which ^ 1]);
 }
 
 // f = feq(rho, u) - s from dense fields; arithmetic in double, stored as T.
@@ -1020,6 +1049,23 @@ const void* batch_kernel_t(int block, int depth) {
   return nullptr;
 }
 
+template <typename T, int SCHEME>
+const void* batch4_kernel_t(int depth) {
+  switch (depth) {
+    case 1: return (const void*)march4_batch<T, SCHEME, kBatch4Block, 1>;
+    case 2: return (const void*)march4_batch<T, SCHEME, kBatch4Block, 2>;
+    case 3: return (const void*)march4_batch<T, SCHEME, kBatch4Block, 3>;
+  }
+  return nullptr;
+}
+
+template <typename T>
+const void* batch4_kernel_s(int scheme, int depth) {
+  if (scheme == STANDARD) return batch4_kernel_t<T, STANDARD>(depth);
+  if (scheme == STANDARD_EQF) return batch4_kernel_t<T, STANDARD_EQF>(depth);
+  return batch4_kernel_t<T, WELL_BALANCED>(depth);
+}
+
 const void* batch_kernel(int storage, int scheme, int block, int depth, bool observe) {
   if (scheme != STANDARD && scheme != WELL_BALANCED && scheme != STANDARD_EQF) return nullptr;
   if (observe) {
@@ -1043,6 +1089,16 @@ const void* batch_kernel(int storage, int scheme, int block, int depth, bool obs
 }
 
 }  // namespace
+
+hipError_t launch_batch4(int storage, int scheme, int depth, const BatchTable* tab, int tiles,
+                         int parity, hipStream_t s) {
+  if (scheme != STANDARD && scheme != WELL_BALANCED && scheme != STANDARD_EQF) return hipErrorInvalidValue;
+  const void* fn = storage == FP64 ? batch4_kernel_s<double>(scheme, depth)
+                                   : batch4_kernel_s<float>(scheme, depth);
+  if (!fn || tiles <= 0) return hipErrorInvalidValue;
+  void* args[] = {(void*)&tab, (void*)&parity};
+  return hipLaunchKernel(fn, dim3(tiles), dim3(kBatch4Block), args, 0, s);
+}
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
                         const BatchTable* tab, int tiles, int parity, hipStream_t s) {

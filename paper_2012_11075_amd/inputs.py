@@ -218,6 +218,7 @@ class Request:
     tol: float                 # retire when max|u| < tol
     step_cap: int
     scheme: str = "well_balanced"  # the scheme the request is stepped with
+    force_stencil: int = 0         # 1: the fourth-order gradients of the force
 
 
 def request_stream(n: int, rate_hz: float, seed: int = 5, side_lo: int = 64,

@@ -57,7 +57,8 @@ class BatchExecutor:
     def params(self, req):
         ph = req.problem.physics
         return self.lbm.make_params(req.problem.nx, req.problem.ny, ph.tau, ph.beta, ph.kappa,
-                                    ph.rho_l, ph.rho_v, ph.rho0, precision=req.precision)
+                                    ph.rho_l, ph.rho_v, ph.rho0, precision=req.precision,
+                                    force_stencil=getattr(req, "force_stencil", 0))
 
     def footprint(self, req) -> int:
         return self.lbm.Batch.slot_bytes(self.params(req))
@@ -68,6 +69,8 @@ class BatchExecutor:
                                     tol=req.tol, step_cap=req.step_cap)
         if slot is not None and self.tiles is not None:
             tile = self.tiles(req.problem.nx, req.problem.ny, req.precision)
+            if tile and getattr(req, "force_stencil", 0):
+                tile = (0,) + tuple(tile[1:])   # the variant keeps its 256-wide blocks
             if tile:
                 self.batch.set_tile(slot, *tile)
         return slot
