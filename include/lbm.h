@@ -243,8 +243,8 @@ int32_t lbm_kernels_per_step(const lbm_ctx* ctx);
 /* Many independent lattices of uneven size advanced together: each step is
  * one launch per group of slots that share precision, scheme, force stencil
  * (the central one of Sec. II or the fourth-order variant discussed after
- * Eq. 23), block width and prefetch depth, and per lane (even and odd slot
- * index), with one block
+ * Eq. 23) or 3-D velocity set, block width and prefetch depth, and per lane
+ * (even and odd slot index), with one block
  * per tile of those slots, reading a device-resident slot table.  Lane 0
  * runs on the batch's stream, lane 1 on a second stream of the batch that
  * forks from it and joins it again within each lbm_batch_run, so one lane's
@@ -273,10 +273,11 @@ size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots);
 lbm_status lbm_batch_create(void* dev_arena, size_t bytes, int32_t max_slots, void* hip_stream,
                             lbm_batch** out);
 
-/* Admit a 2-D lattice (nz 0 or 1; either force stencil): allocate its
- * workspace in the arena, set f(0) = feq(rho, 0) (as lbm_init) and mark it
- * active; every scheme of lbm_scheme is accepted, and each slot steps with
- * the scheme it was admitted with.  It retires at the first lbm_batch_poll
+/* Admit a lattice (2-D with either force stencil, or 3-D: D3Q19 or D3Q27,
+ * rho then double[nz][ny][nx]): allocate its workspace in the arena, set
+ * f(0) = feq(rho, 0) (as lbm_init) and mark it active; every scheme of
+ * lbm_scheme is accepted, and each slot steps with the scheme it was
+ * admitted with.  It retires at the first lbm_batch_poll
  * that finds max|u| < tol (tol <= 0: never) or step >= step_cap (<= 0: no
  * cap), or a non-finite state.  LBM_EBUSY if no slot or arena range is free
  * (nothing changes).  Synchronous. */
@@ -288,8 +289,9 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* params, const double*
  * the graph size (lbm_batch_set_graph_steps). */
 lbm_status lbm_batch_run(lbm_batch* b, int32_t k_steps);
 
-/* Observe every active slot (one batched launch per group of the central
- * stencil; the fourth-order variant's three-pass observe per slot), retire the slots
+/* Observe every active slot (one batched launch per group of 2-D slots with
+ * the central stencil; the three-pass observe of lbm_observe per slot for
+ * 3-D slots and the fourth-order variant), retire the slots
  * that meet their criterion and write their indices to retired[0..n) (at most
  * cap).  Synchronous. */
 lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* n_retired);
@@ -298,16 +300,20 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
 lbm_status lbm_batch_slot_info(const lbm_batch* b, int32_t slot, int32_t* status,
                                lbm_observation* obs);
 
-/* Fields of a slot (as lbm_observe); any pointer may be NULL.  Synchronous. */
+/* Fields of a slot (as lbm_observe; 3-D slots: double[nz][ny][nx], the z
+ * velocity through the momentum of obs only); any pointer may be NULL.
+ * Synchronous. */
 lbm_status lbm_batch_fetch(lbm_batch* b, int32_t slot, double* rho, double* ux, double* uy,
                            double* mu, lbm_observation* obs);
 
-/* Populations of a slot as double[9][ny][nx] (as lbm_get_populations). */
+/* Populations of a slot as double[9][ny][nx] (3-D: double[q][nz][ny][nx]),
+ * as lbm_get_populations. */
 lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
 
 /* Tile of a slot's kernels (as lbm_set_tile; block width 64, 128 or 256 and
  * depth 1, 2 or 3 for batches; the fourth-order force stencil's slots run
- * block width 256 only). */
+ * block width 256 only; 3-D slots block 256 (32 x 8 tiles), rows = planes
+ * per chunk, depth 1 or 2). */
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block_width, int32_t rows,
                               int32_t depth);
 

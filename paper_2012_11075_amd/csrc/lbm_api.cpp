@@ -863,10 +863,14 @@ namespace {
 constexpr int kBatchBlocks[3] = {64, 128, 256};
 // Launch groups: storage x scheme x block x depth for the main step, then
 // storage x scheme x depth for the force-stencil variant (block width
-// kBatch4Block).
+// kBatch4Block), then storage x scheme x lattice (D3Q19, D3Q27) x depth
+// (1, 2) for 3-D lattices (tiles of 32 x kBatch3Ty).
 constexpr int kPlainGroups = 2 * 3 * 3 * 3;
-constexpr int kGroups = kPlainGroups + 2 * 3 * 3;
+constexpr int kStencil4Base = kPlainGroups;
+constexpr int k3dBase = kStencil4Base + 2 * 3 * 3;
+constexpr int kGroups = k3dBase + 2 * 3 * 2 * 2;
 using GroupMask = std::bitset<kGroups>;
+enum GroupKind { kMain = 0, kStencil4 = 1, k3d = 2 };
 // Each group's slots are split into two lanes (even and odd slot index), each
 // with its own table, launched on its own stream: the lanes hold disjoint
 // lattices, so one lane's next step fills the compute units that the other
@@ -890,7 +894,9 @@ struct lbm_batch {
   size_t bytes = 0;
   hipStream_t stream = nullptr;
   int max_slots = 0;
-  size_t tab_stride = 0;   // bytes per group table
+  size_t tab_stride = 0;   // bytes per 2-D group table
+  size_t tab3_stride = 0;  // bytes per 3-D group table
+  size_t tab3_off = 0;     // 3-D tables
   size_t part_off = 0;     // partials region
   size_t part_cap = 0;     // tiles it can hold
   size_t heap_off = 0;     // start of the slot heap
@@ -925,6 +931,9 @@ struct lbm_batch {
   lbmk::BatchTable* dev_tab(int g, int lane) const {
     return (lbmk::BatchTable*)(arena + (size_t)(g * kLanes + lane) * tab_stride);
   }
+  lbmk::BatchTable3* dev_tab3(int g, int lane) const {
+    return (lbmk::BatchTable3*)(arena + tab3_off + (size_t)((g - k3dBase) * kLanes + lane) * tab3_stride);
+  }
   double* partials() const { return (double*)(arena + part_off); }
 };
 
@@ -946,28 +955,53 @@ lbm_status bfail(lbm_batch* b, lbm_status s, const std::string& msg) {
   } while (0)
 
 int group_of(const lbm_ctx* c, int scheme) {
+  if (c->d3())
+    return k3dBase + ((c->storage() * 3 + scheme) * 2 + (c->L.q == lbmk::Q27 ? 1 : 0)) * 2 +
+           (c->tl3.depth - 1);
   if (c->prm.force_stencil == 1)
-    return kPlainGroups + (c->storage() * 3 + scheme) * 3 + (c->tl.depth - 1);
+    return kStencil4Base + (c->storage() * 3 + scheme) * 3 + (c->tl.depth - 1);
   const int bi = block_index(c->tl.block);
   return ((c->storage() * 3 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
 }
 
-void group_decode(int g, int* storage, int* scheme, int* block, int* depth, bool* stencil4) {
-  *stencil4 = g >= kPlainGroups;
-  if (*stencil4) {
-    g -= kPlainGroups;
-    *depth = g % 3 + 1;
+// Launch parameters of group g; q is the 3-D velocity count (0 in 2-D).
+struct Group {
+  GroupKind kind;
+  int storage, scheme, block, depth, q;
+};
+
+Group group_decode(int g) {
+  Group d{};
+  if (g >= k3dBase) {
+    g -= k3dBase;
+    d.kind = k3d;
+    d.depth = g % 2 + 1;
+    g /= 2;
+    d.q = g % 2 ? lbmk::Q27 : lbmk::Q3;
+    g /= 2;
+    d.block = lbmk::M3X * lbmk::kBatch3Ty;
+  } else if (g >= kStencil4Base) {
+    g -= kStencil4Base;
+    d.kind = kStencil4;
+    d.depth = g % 3 + 1;
     g /= 3;
-    *block = lbmk::kBatch4Block;
+    d.block = lbmk::kBatch4Block;
   } else {
-    *depth = g % 3 + 1;
+    d.kind = kMain;
+    d.depth = g % 3 + 1;
     g /= 3;
-    *block = kBatchBlocks[g % 3];
+    d.block = kBatchBlocks[g % 3];
     g /= 3;
   }
-  *scheme = g % 3;
-  *storage = g / 3;
+  d.scheme = g % 3;
+  d.storage = g / 3;
+  return d;
 }
+
+// Slots observed one by one at a poll (their own observe passes) rather
+// than by a batched observe launch: 3-D lattices and the force-stencil
+// variant.
+bool polled_alone(const lbm_ctx* c) { return c->d3() || c->prm.force_stencil == 1; }
 
 size_t part_capacity(size_t arena_bytes) { return arena_bytes / 8192 + 1024; }
 
@@ -1011,6 +1045,35 @@ lbm_status upload_tables(lbm_batch* b) {
     for (int lane = 0; lane < kLanes; ++lane) {
       std::vector<char>& h = b->host_tab[g * kLanes + lane];
       std::fill(h.begin(), h.end(), 0);
+      if (g >= k3dBase) {
+        auto* tab = (lbmk::BatchTable3*)h.data();
+        int n = 0, tiles = 0;
+        for (size_t s = lane; s < b->slots.size(); s += kLanes) {
+          lbm_batch::Slot& sl = b->slots[s];
+          if (sl.status != LBM_SLOT_ACTIVE || group_of(sl.ctx, sl.scheme) != g) continue;
+          lbm_ctx* c = sl.ctx;
+          lbmk::BatchSlot3& d = tab->slot[n++];
+          d.g = c->L.g3;
+          d.ph = make_physics3(c->prm, sl.scheme);
+          d.tl = c->tl3;
+          d.buf[0] = c->buf(0);
+          d.buf[1] = c->buf(1);
+          d.cur = c->cur;
+          d.tile0 = tiles;
+          sl.part_index = 0;
+          sl.tiles = (int)lbmk::blocks_of(c->tl3);
+          tiles += sl.tiles;
+        }
+        tab->nslots = n;
+        tab->total_tiles = tiles;
+        if (n > 0) active[lane].set(g);
+        b->tiles_of[lane][g] = tiles;
+        const size_t used =
+            sizeof(lbmk::BatchTable3) + (size_t)(n > 1 ? n - 1 : 0) * sizeof(lbmk::BatchSlot3);
+        BHIP(b, hipMemcpyAsync(b->dev_tab3(g, lane), h.data(), used, hipMemcpyHostToDevice,
+                               b->stream));
+        continue;
+      }
       auto* tab = (lbmk::BatchTable*)h.data();
       int n = 0, tiles = 0;
       for (size_t s = lane; s < b->slots.size(); s += kLanes) {
@@ -1055,15 +1118,17 @@ lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s) {
   for (int j = 0; j < steps; ++j) {
     for (int g = 0; g < kGroups; ++g) {
       if (!b->active_mask[lane].test(g)) continue;
-      int storage, scheme, block, depth;
-      bool stencil4;
-      group_decode(g, &storage, &scheme, &block, &depth, &stencil4);
-      if (stencil4)
-        BHIP(b, lbmk::launch_batch4(storage, scheme, depth, b->dev_tab(g, lane),
-                                    b->tiles_of[lane][g], j & 1, s));
+      const Group d = group_decode(g);
+      const int tiles = b->tiles_of[lane][g];
+      if (d.kind == k3d)
+        BHIP(b, lbmk::launch_batch3(d.storage, d.scheme, d.q, d.depth, b->dev_tab3(g, lane), tiles,
+                                    j & 1, s));
+      else if (d.kind == kStencil4)
+        BHIP(b, lbmk::launch_batch4(d.storage, d.scheme, d.depth, b->dev_tab(g, lane), tiles,
+                                    j & 1, s));
       else
-        BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, false, b->dev_tab(g, lane),
-                                   b->tiles_of[lane][g], j & 1, s));
+        BHIP(b, lbmk::launch_batch(d.storage, d.scheme, d.block, d.depth, false,
+                                   b->dev_tab(g, lane), tiles, j & 1, s));
     }
   }
   return LBM_OK;
@@ -1137,7 +1202,8 @@ size_t lbm_batch_slot_bytes(const lbm_params* p) {
 size_t lbm_batch_overhead_bytes(size_t arena_bytes, int32_t max_slots) {
   if (max_slots < 1) return 0;
   const size_t stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  return kGroups * kLanes * stride +
+  const size_t stride3 = align_up(lbmk::batch_table3_bytes(max_slots), ALIGN);
+  return (size_t)k3dBase * kLanes * stride + (size_t)(kGroups - k3dBase) * kLanes * stride3 +
          align_up(part_capacity(arena_bytes) * lbmk::NPART * sizeof(double), ALIGN);
 }
 
@@ -1170,12 +1236,18 @@ lbm_status lbm_batch_create(void* arena, size_t bytes, int32_t max_slots, void* 
   b->join = join;
   b->max_slots = max_slots;
   b->tab_stride = align_up(lbmk::batch_table_bytes(max_slots), ALIGN);
-  b->part_off = kGroups * kLanes * b->tab_stride;
+  b->tab3_stride = align_up(lbmk::batch_table3_bytes(max_slots), ALIGN);
+  b->tab3_off = (size_t)k3dBase * kLanes * b->tab_stride;
+  b->part_off = b->tab3_off + (size_t)(kGroups - k3dBase) * kLanes * b->tab3_stride;
   b->part_cap = part_capacity(bytes);
   b->heap_off = over;
   b->slots.resize(max_slots);
   b->free_ranges.push_back(Range{b->heap_off, bytes - b->heap_off});
-  b->host_tab.assign(kGroups * kLanes, std::vector<char>(lbmk::batch_table_bytes(max_slots), 0));
+  b->host_tab.resize(kGroups * kLanes);
+  for (int g = 0; g < kGroups; ++g)
+    for (int lane = 0; lane < kLanes; ++lane)
+      b->host_tab[g * kLanes + lane].assign(
+          g >= k3dBase ? lbmk::batch_table3_bytes(max_slots) : lbmk::batch_table_bytes(max_slots), 0);
   *out = b;
   return LBM_OK;
 }
@@ -1187,7 +1259,6 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   if (!valid_scheme(scheme)) return bfail(b, LBM_EINVAL, "unknown scheme");
   std::string why;
   if (!valid_params(p, &why)) return bfail(b, LBM_EINVAL, why);
-  if (p->nz > 1) return bfail(b, LBM_EINVAL, "batches hold 2-D lattices");
   int idx = -1;
   for (int i = 0; i < b->max_slots; ++i)
     if (b->slots[i].status == LBM_SLOT_FREE) {
@@ -1204,12 +1275,16 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
     free_range(b, r);
     return bfail(b, st, lbm_last_error(nullptr));
   }
-  // default tile of a slot (callers normally set a tuned one): block width
-  // by lattice width, 32-row chunks, two rows in flight; the force-stencil
-  // variant runs 256-wide blocks
-  const int block =
-      p->force_stencil == 1 ? lbmk::kBatch4Block : (p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256));
-  c->tl = make_tiling(c->L.g, block, 32, 2);
+  // default tile of a 2-D slot (callers normally set a tuned one): block
+  // width by lattice width, 32-row chunks, two rows in flight; the
+  // force-stencil variant runs 256-wide blocks.  A 3-D slot keeps the
+  // single lattice's default tiling (32 x 8 tiles, one or two planes in
+  // flight), which batches run.
+  if (!c->d3()) {
+    const int block =
+        p->force_stencil == 1 ? lbmk::kBatch4Block : (p->nx <= 64 ? 64 : (p->nx <= 128 ? 128 : 256));
+    c->tl = make_tiling(c->L.g, block, 32, 2);
+  }
   st = lbm_init(c, rho, nullptr, nullptr, scheme);
   if (st != LBM_OK) {
     std::string m = c->err;
@@ -1237,6 +1312,8 @@ lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t
   if (block != 0 && block_index(block) < 0) return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
   if (block != 0 && s->ctx->prm.force_stencil == 1 && block != lbmk::kBatch4Block)
     return bfail(b, LBM_EINVAL, "force-stencil slots run 256-wide blocks");
+  if (s->ctx->d3() && ((block != 0 && block != lbmk::M3X * lbmk::kBatch3Ty) || depth > 2))
+    return bfail(b, LBM_EINVAL, "3-D slots run 256-thread tiles (32 x 8) with depth 1 or 2");
   if (depth < 0 || depth > 3) return bfail(b, LBM_EINVAL, "batch depth must be 1, 2 or 3");
   lbm_status st = lbm_set_tile(s->ctx, block, rows, depth);
   if (st != LBM_OK) return bfail(b, st, s->ctx->err);
@@ -1300,32 +1377,34 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
     lbm_status st = upload_tables(b);
     if (st != LBM_OK) return st;
   }
+  // partial records of the slots observed by batched launches
   size_t total = 0;
   for (const auto& s : b->slots)
-    if (s.status == LBM_SLOT_ACTIVE) total = std::max(total, s.part_index + s.tiles);
-  if (total == 0) return LBM_OK;
-  for (int lane = 0; lane < kLanes; ++lane)
-    for (int g = 0; g < kPlainGroups; ++g) {
-      if (!b->active_mask[lane].test(g)) continue;
-      int storage, scheme, block, depth;
-      bool stencil4;
-      group_decode(g, &storage, &scheme, &block, &depth, &stencil4);
-      BHIP(b, lbmk::launch_batch(storage, scheme, block, depth, true, b->dev_tab(g, lane),
-                                 b->tiles_of[lane][g], 0, b->stream));
-    }
+    if (s.status == LBM_SLOT_ACTIVE && !polled_alone(s.ctx))
+      total = std::max(total, s.part_index + s.tiles);
   std::vector<double> part(total * lbmk::NPART);
-  BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),
-                         hipMemcpyDeviceToHost, b->stream));
-  BHIP(b, hipStreamSynchronize(b->stream));
+  if (total > 0) {
+    for (int lane = 0; lane < kLanes; ++lane)
+      for (int g = 0; g < kPlainGroups; ++g) {
+        if (!b->active_mask[lane].test(g)) continue;
+        const Group d = group_decode(g);
+        BHIP(b, lbmk::launch_batch(d.storage, d.scheme, d.block, d.depth, true,
+                                   b->dev_tab(g, lane), b->tiles_of[lane][g], 0, b->stream));
+      }
+    BHIP(b, hipMemcpyAsync(part.data(), b->partials(), part.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+  }
   int n = 0;
   bool changed = false;
   for (size_t i = 0; i < b->slots.size(); ++i) {
     lbm_batch::Slot& s = b->slots[i];
     if (s.status != LBM_SLOT_ACTIVE) continue;
     bool bad;
-    if (s.ctx->prm.force_stencil == 1) {
-      // the variant's observe pass (three launches into the slot's own
-      // staging and partials), as lbm_observe on the slot alone
+    if (polled_alone(s.ctx)) {
+      // the observe pass of a 3-D lattice or of the force-stencil variant
+      // (three launches into the slot's own staging and partials), as
+      // lbm_observe on the slot alone
       const lbm_status os = observe_impl(s.ctx, nullptr, nullptr, nullptr, nullptr, nullptr, &s.last);
       if (os != LBM_OK && os != LBM_ENONFINITE) return bfail(b, os, s.ctx->err);
       bad = os == LBM_ENONFINITE;

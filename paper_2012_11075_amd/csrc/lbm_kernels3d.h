@@ -73,4 +73,29 @@ hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Ph
                            hipStream_t s);
 int blocks3(const Geometry3& g);
 
+// One 3-D lattice of a batched launch (device memory), and the table of one
+// launch group: slots in order of tile0, total_tiles = sum of their tiles.
+struct BatchSlot3 {
+  Geometry3 g;
+  Physics3 ph;
+  Tiling3 tl;
+  void* buf[2];  // the two population copies
+  int cur;       // buffer holding the state at parity 0
+  int tile0;     // first work item of this slot in the concatenated list
+};
+struct BatchTable3 {
+  int nslots;
+  int total_tiles;
+  int pad[2];
+  BatchSlot3 slot[1];  // nslots entries (allocated with room for the maximum)
+};
+inline size_t batch_table3_bytes(int max_slots) {
+  return sizeof(BatchTable3) + (size_t)(max_slots > 1 ? max_slots - 1 : 0) * sizeof(BatchSlot3);
+}
+// Batched 3-D step of one launch group: tiles of 32 x kBatch3Ty nodes,
+// depth 1 or 2, D3Q19 or D3Q27 (q), one block per tile.
+constexpr int kBatch3Ty = 8;
+hipError_t launch_batch3(int storage, int scheme, int q, int depth, const BatchTable3* tab,
+                         int tiles, int parity, hipStream_t s);
+
 }  // namespace lbmk

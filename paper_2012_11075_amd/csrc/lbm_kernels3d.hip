@@ -359,8 +359,9 @@ __device__ __forceinline__ void loadq(const __amdgpu_buffer_rsrc_t (&b)[3], unsi
 // planes of populations loaded ahead of the plane being summed (0 = none).
 constexpr int CG = 1;  // velocity pairs per scheduling region of the collision
 template <typename T, int SCHEME, int TY, int D, int Q>
-__global__ void __launch_bounds__(M3X * TY)
-    march3(Geometry3 g, Physics3 p, Tiling3 tl, const T* __restrict__ fin, T* __restrict__ fout) {
+__device__ __forceinline__ void march3_tile(const Geometry3& g, const Physics3& p,
+                                            const Tiling3& tl, int item,
+                                            const T* __restrict__ fin, T* __restrict__ fout) {
   using R = T;
   constexpr int NT = M3X * TY;
   constexpr int RX = M3X + 4, RY = TY + 4;  // rho region: tile and a 2-node halo
@@ -377,7 +378,6 @@ __global__ void __launch_bounds__(M3X * TY)
   __shared__ R ms[3][MY][MX];  // region (i, j) is lattice (x0 - 1 + i, y0 - 1 + j)
   const int t = threadIdx.x;
   const int per_plane = tl.tiles_x * tl.tiles_y;
-  const int item = xcd_item(blockIdx.x, per_plane * tl.chunks);
   const int chunk = item / per_plane;
   const int rem = item - chunk * per_plane;
   const int by = rem / tl.tiles_x, bx = rem - by * tl.tiles_x;
@@ -502,6 +502,39 @@ __global__ void __launch_bounds__(M3X * TY)
       if (k0 + u < K)
         stage(k0 + u, P[u % RP], H[u % RH], P[(u + D) % RP], P[(u + RP - 1) % RP]);
   }
+}
+
+template <typename T, int SCHEME, int TY, int D, int Q>
+__global__ void __launch_bounds__(M3X * TY)
+    march3(Geometry3 g, Physics3 p, Tiling3 tl, const T* __restrict__ fin, T* __restrict__ fout) {
+  march3_tile<T, SCHEME, TY, D, Q>(
+      g, p, tl, xcd_item(blockIdx.x, tl.tiles_x * tl.tiles_y * tl.chunks), fin, fout);
+}
+
+// Many 3-D lattices in one launch: one block per work item of the table's
+// concatenated tile list (as the 2-D batched step), the slot found by a
+// search uniform over the block.
+template <typename T, int SCHEME, int D, int Q>
+__global__ void __launch_bounds__(M3X * kBatch3Ty)
+    march3_batch(const BatchTable3* __restrict__ tab, int parity) {
+  const int total = tab->total_tiles;
+  const int item = xcd_item(blockIdx.x, total);
+  if (item >= total) return;
+  int lo = 0, hi = tab->nslots - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab->slot[mid].tile0 <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const BatchSlot3* sp = &tab->slot[lo];
+  const Geometry3 g = sp->g;
+  const Physics3 ph = sp->ph;
+  const Tiling3 tl = sp->tl;
+  const int which = sp->cur ^ parity;
+  march3_tile<T, SCHEME, kBatch3Ty, D, Q>(g, ph, tl, item - sp->tile0, (const T*)sp->buf[which],
+                                          (T*)sp->buf[which ^ 1]);
 }
 
 // Observe pass, in the storage type's arithmetic as the step (FP32 storage:
@@ -831,6 +864,38 @@ hipError_t launch_step3(int storage, int scheme, const Geometry3& g, const Physi
     return storage == FP64 ? launch_step3_t<double, Q27>(scheme, g, ph, t, fin, fout, s)
                            : launch_step3_t<float, Q27>(scheme, g, ph, t, fin, fout, s);
   return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <typename T, int Q>
+const void* batch3_fn(int scheme, int depth) {
+  if (depth == 1) {
+    if (scheme == STANDARD) return (const void*)march3_batch<T, STANDARD, 0, Q>;
+    if (scheme == STANDARD_EQF) return (const void*)march3_batch<T, STANDARD_EQF, 0, Q>;
+    return (const void*)march3_batch<T, WELL_BALANCED, 0, Q>;
+  }
+  if (depth == 2) {
+    if (scheme == STANDARD) return (const void*)march3_batch<T, STANDARD, 1, Q>;
+    if (scheme == STANDARD_EQF) return (const void*)march3_batch<T, STANDARD_EQF, 1, Q>;
+    return (const void*)march3_batch<T, WELL_BALANCED, 1, Q>;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+hipError_t launch_batch3(int storage, int scheme, int q, int depth, const BatchTable3* tab,
+                         int tiles, int parity, hipStream_t s) {
+  if (scheme != STANDARD && scheme != WELL_BALANCED && scheme != STANDARD_EQF) return hipErrorInvalidValue;
+  const void* fn = nullptr;
+  if (q == Q3)
+    fn = storage == FP64 ? batch3_fn<double, Q3>(scheme, depth) : batch3_fn<float, Q3>(scheme, depth);
+  else if (q == Q27)
+    fn = storage == FP64 ? batch3_fn<double, Q27>(scheme, depth) : batch3_fn<float, Q27>(scheme, depth);
+  if (!fn || tiles <= 0) return hipErrorInvalidValue;
+  void* args[] = {(void*)&tab, (void*)&parity};
+  return hipLaunchKernel(fn, dim3(tiles), dim3(M3X * kBatch3Ty), args, 0, s);
 }
 
 hipError_t launch_observe3(int storage, int scheme, const Geometry3& g, const Physics3& ph,

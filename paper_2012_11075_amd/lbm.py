@@ -306,7 +306,8 @@ class Batch:
         if st != 0:
             raise LbmError(st, self.lib.lbm_batch_last_error(None).decode())
         self.b = h
-        self.shapes = {}
+        self.shapes = {}   # slot -> field shape
+        self.qs = {}       # slot -> populations per node
 
     def _check(self, st):
         if st != 0:
@@ -324,12 +325,16 @@ class Batch:
         return int(load().lbm_batch_overhead_bytes(int(arena_bytes), int(max_slots)))
 
     def admit(self, params: Params, rho, scheme="well_balanced", tol=0.0, step_cap=0) -> int:
+        """rho: (ny, nx), or (nz, ny, nx) for a 3-D lattice (params.nz > 1)."""
         rho = np.ascontiguousarray(rho, dtype=np.float64)
-        assert rho.shape == (params.ny, params.nx)
+        d3 = params.nz > 1
+        shape = (params.nz, params.ny, params.nx) if d3 else (params.ny, params.nx)
+        assert rho.shape == shape
         slot = ctypes.c_int32()
         self._check(self.lib.lbm_batch_admit(self.b, ctypes.byref(params), _dptr(rho), _scheme(scheme),
                                              float(tol), int(step_cap), ctypes.byref(slot)))
-        self.shapes[slot.value] = (params.ny, params.nx)
+        self.shapes[slot.value] = shape
+        self.qs[slot.value] = (params.lattice3 or 19) if d3 else 9
         return slot.value
 
     def try_admit(self, *a, **kw):
@@ -356,8 +361,7 @@ class Batch:
         return SLOT_STATUS[st.value], _obs_dict(ob, 0)
 
     def fetch(self, slot: int, fields=("rho", "ux", "uy", "mu")) -> dict:
-        ny, nx = self.shapes[slot]
-        out = {k: np.empty((ny, nx)) for k in fields}
+        out = {k: np.empty(self.shapes[slot]) for k in fields}
         ob = Observation()
         st = self.lib.lbm_batch_fetch(self.b, int(slot), _dptr(out.get("rho")), _dptr(out.get("ux")),
                                       _dptr(out.get("uy")), _dptr(out.get("mu")), ctypes.byref(ob))
@@ -367,8 +371,7 @@ class Batch:
         return out
 
     def get_populations(self, slot: int) -> np.ndarray:
-        ny, nx = self.shapes[slot]
-        f = np.empty((9, ny, nx))
+        f = np.empty((self.qs[slot],) + self.shapes[slot])
         self._check(self.lib.lbm_batch_get_populations(self.b, int(slot), _dptr(f)))
         return f
 
@@ -381,6 +384,7 @@ class Batch:
     def release(self, slot: int):
         self._check(self.lib.lbm_batch_release(self.b, int(slot)))
         self.shapes.pop(slot, None)
+        self.qs.pop(slot, None)
 
     def close(self):
         if getattr(self, "b", None):
