@@ -33,7 +33,9 @@ def main():
     ap.add_argument("--force-stencil", type=int, default=0,
                     help="1: the fourth-order force-stencil variant (one fused kernel per step)")
     ap.add_argument("--d3", type=int, default=0,
-                    help="profile the 3-D (D3Q19) step on an N^3 droplet instead")
+                    help="profile the 3-D step on an N^3 droplet instead")
+    ap.add_argument("--q3", type=int, default=19, choices=[19, 27],
+                    help="velocity set of the 3-D step: 19 (D3Q19) or 27 (D3Q27)")
     ap.add_argument("--batch", type=int, default=0,
                     help="profile the batched launch over this many uneven instances instead")
     ap.add_argument("--side", type=int, default=0,
@@ -52,9 +54,9 @@ def main():
         rho = I.droplet3_density(n, n, n, ph, I.DROPLET3_RADIUS * n / I.DROPLET3_SIDE,
                                  I.equilibrium_width(ph), 1e-3, seed=13)
         s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=n,
-                       precision=args.precision)
+                       precision=args.precision, q3=args.q3)
         s.init(rho, scheme=args.scheme)
-        print("profile_step: D3Q19 %d^3 %s %s tile=%s" % (n, args.precision, args.scheme,
+        print("profile_step: D3Q%d %d^3 %s %s tile=%s" % (args.q3, n, args.precision, args.scheme,
                                                           s.get_tile()), flush=True)
         s.step(args.steps, args.scheme)
         torch.cuda.synchronize()
