@@ -261,6 +261,55 @@ def droplet3_density(nx: int, ny: int, nz: int, ph: Physics, radius: float, widt
     return np.ascontiguousarray(rho)
 
 
+@dataclass(frozen=True)
+class Problem3:
+    """One 3-D initial-value problem: a droplet of the given radius about the
+    node (nx//2, ny//2, nz//2) of an nx x ny x nz periodic lattice, on the
+    D3Q19 (q3 = 19) or D3Q27 (q3 = 27) lattice."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    physics: Physics
+    radius: float
+    width: float
+    noise: float = 0.0
+    seed: int = 0
+    q3: int = 19
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def rho(self) -> np.ndarray:
+        return droplet3_density(self.nx, self.ny, self.nz, self.physics, self.radius, self.width,
+                                self.noise, self.seed)
+
+
+def request_stream3(n: int, rate_hz: float, seed: int = 7, side_lo: int = 16, side_hi: int = 96,
+                    step_cap: int = 2_000) -> list:
+    """3-D requests: Poisson arrivals at rate_hz; cubic side log-uniform on
+    [side_lo, side_hi]; a droplet (radius 0.2-0.3 of the side) on D3Q19 or
+    D3Q27 with equal probability; density ratio 10, tau 1 and the
+    free-energy constants of Sec. IV; FP32-shifted (tolerance 1e-6) or FP64
+    (1e-10) with equal probability; multiplicative noise 1e-3."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += float(rng.exponential(1.0 / rate_hz))
+        side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
+        ph = Physics(tau=1.0, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=0.1)
+        q3 = 27 if rng.uniform() < 0.5 else 19
+        prob = Problem3("req3d%05d" % k, side, side, side, ph,
+                        float(rng.uniform(0.2, 0.3)) * side, equilibrium_width(ph), 1e-3,
+                        seed * 1_000_000 + k, q3)
+        fp64 = rng.uniform() < 0.5
+        out.append(Request(k, t, prob, "fp64" if fp64 else "fp32s", 1e-10 if fp64 else 1e-6,
+                           step_cap))
+    return out
+
+
 # 3-D throughput lattice: 256^3 D3Q19 droplet of radius 64, the free-energy
 # constants of Sec. IV at density ratio 10, tau 1 (a finite, relaxing state).
 PHYS3 = Physics(tau=1.0, beta=PAPER_BETA, kappa=PAPER_KAPPA, rho_l=1.0, rho_v=0.1)

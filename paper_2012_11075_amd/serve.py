@@ -56,9 +56,11 @@ class BatchExecutor:
 
     def params(self, req):
         ph = req.problem.physics
+        nz = getattr(req.problem, "nz", 0)
         return self.lbm.make_params(req.problem.nx, req.problem.ny, ph.tau, ph.beta, ph.kappa,
                                     ph.rho_l, ph.rho_v, ph.rho0, precision=req.precision,
-                                    force_stencil=getattr(req, "force_stencil", 0))
+                                    force_stencil=getattr(req, "force_stencil", 0), nz=nz,
+                                    q3=getattr(req.problem, "q3", 19))
 
     def footprint(self, req) -> int:
         return self.lbm.Batch.slot_bytes(self.params(req))
@@ -67,7 +69,7 @@ class BatchExecutor:
         slot = self.batch.try_admit(self.params(req), req.problem.rho(),
                                     getattr(req, "scheme", "well_balanced"),
                                     tol=req.tol, step_cap=req.step_cap)
-        if slot is not None and self.tiles is not None:
+        if slot is not None and self.tiles is not None and not getattr(req.problem, "nz", 0):
             tile = self.tiles(req.problem.nx, req.problem.ny, req.precision)
             if tile and getattr(req, "force_stencil", 0):
                 tile = (0,) + tuple(tile[1:])   # the variant keeps its 256-wide blocks
@@ -103,6 +105,11 @@ class BatchExecutor:
 
     def close(self):
         self.batch.close()
+
+
+def nodes_of(problem) -> int:
+    """Lattice nodes of a 2-D or 3-D problem."""
+    return problem.nx * problem.ny * max(1, getattr(problem, "nz", 0))
 
 
 @dataclass
@@ -154,7 +161,7 @@ class Server:
                 t = self.clock() - t0
                 done.append(Outcome(req.rid, req.arrival, adm, t, int(ob["step"]), status,
                                     float(ob["max_u"]), float(ob["mass"]),
-                                    req.problem.nx * req.problem.ny, req.precision, res))
+                                    nodes_of(req.problem), req.precision, res))
                 ex.release(slot)
                 self.log.append(("retire", req.rid, slot, t, status))
         return done

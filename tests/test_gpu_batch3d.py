@@ -3,7 +3,8 @@ runs the fused 3-D step over the batch's table, so it gives the populations
 of the same lattice run alone, bit for bit (FP64 and FP32-shifted, the three
 schemes, depths 1 and 2, mixed with 2-D slots, with and without graphs);
 FP64 slots match the oracle to 1e-11; the poll observes a 3-D slot as
-lbm_observe does and retires it by its criterion."""
+lbm_observe does and retires it by its criterion; a served stream of 3-D and
+2-D requests gives each request the result of running it alone."""
 import numpy as np
 import pytest
 
@@ -118,3 +119,36 @@ def test_3d_slot_tiles_and_retirement(lbm):
     b.run(10)
     assert b.poll() == [] and b.info(d)[1]["step"] == 30
     b.close()
+
+
+def test_served_3d_requests_equal_alone(lbm):
+    """A served stream of 3-D requests (D3Q19 and D3Q27, FP64 and
+    FP32-shifted) mixed with 2-D ones: every result equals the same request
+    run alone for the same number of steps, bit for bit."""
+    from dataclasses import replace
+    from paper_2012_11075_amd.serve import BatchExecutor, Server
+    reqs = I.request_stream3(6, rate_hz=400.0, seed=9, side_lo=12, side_hi=48, step_cap=300)
+    reqs += [replace(r, rid=r.rid + 6) for r in
+             I.request_stream(3, rate_hz=400.0, seed=10, side_lo=32, side_hi=96, step_cap=300)]
+    assert {r.problem.q3 for r in reqs[:6]} == {19, 27}
+    ex = BatchExecutor(int(2e9), max_slots=16, graph_steps=10, capture=True)
+    srv = Server(ex, k=100)
+    out = srv.serve(reqs)
+    ex.close()
+    assert sorted(o.rid for o in out) == list(range(len(reqs)))
+    for o in out:
+        req = reqs[o.rid]
+        ph, pr = req.problem.physics, req.problem
+        print("served", o.rid, type(pr).__name__, pr.nx, getattr(pr, "q3", 9), req.precision,
+              o.status, o.steps, flush=True)
+        if hasattr(pr, "nz"):
+            s = lbm.Solver(pr.nx, pr.ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                           precision=req.precision, nz=pr.nz, q3=pr.q3)
+            assert o.nodes == pr.nx * pr.ny * pr.nz
+        else:
+            s = lbm.Solver.for_problem(pr, precision=req.precision)
+        s.init(pr.rho(), scheme=req.scheme)
+        s.step(o.steps, req.scheme)
+        f = s.get_populations()
+        s.close()
+        assert np.array_equal(f, o.result["populations"], equal_nan=True), (o.rid, o.status)
