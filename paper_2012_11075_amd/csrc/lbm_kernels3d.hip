@@ -30,6 +30,11 @@
 
 #include "lbm_kernels3d.h"
 
+// Multiply-adds are fused only within one source expression (as in the 2-D
+// kernels): the single-lattice and batched steps, every tiling and the
+// observe pass then round a node the same way by construction.
+#pragma clang fp contract(on)
+
 namespace lbmk {
 namespace {
 
