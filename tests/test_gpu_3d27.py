@@ -281,3 +281,24 @@ def test_full_grid_sampled_d3q27(orc, lbm):
         want = orc.step3("well_balanced", p, crop, 1)[M:-M, M:-M, M:-M]
         got = to_oracle(g[:, zs[M:-M]][:, :, ys[M:-M]][:, :, :, xs[M:-M]])
         assert np.abs(got - want).max() <= 1e-12, (z0, y0, x0)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_parity_wb_rho0_3d(orc, lbm, q):
+    """Eq. (24) with rho0 != 0 in 3-D (reading 21): the WB step against the
+    oracle to 1e-11 on both velocity sets, FP64, and the FP32-shifted form
+    within its bound."""
+    from dataclasses import replace
+    ph = replace(I.PAPER_PHYS, rho0=0.5)
+    nx, ny, nz, steps = 17, 11, 9, 150
+    rho0 = I.droplet3_density(nx, ny, nz, ph, 4.0, 4.0, 1e-2, seed=19)
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    fo = orc.step3("well_balanced", p, orc.init3("well_balanced", p, rho0, q=q), steps)
+    for prec, tol in (("fp64", TOL), ("fp32s", 5e-5)):
+        s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0, nz=nz,
+                       q3=q, precision=prec)
+        s.init(rho0, scheme="well_balanced")
+        s.step(steps, "well_balanced")
+        f = np.moveaxis(s.get_populations(), 0, -1)
+        s.close()
+        assert np.abs(f - fo).max() <= tol, (q, prec)
