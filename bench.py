@@ -588,9 +588,11 @@ def main():
     if not args.no_finite:
         out["finite_state"] = finite_state(args.steps, args.warmup)
         progress("finite-state companion done")
-    # The first ~100 steps on a freshly initialised 4096^2 lattice run about 5%
-    # slower than the steady rate, for every scheme; each entry below warms
-    # up past them (the headline takes --warmup steps and times 2,000).
+    # A freshly started process runs its first launches into a dip of the core
+    # clock (power management after an idle device: 2.27 -> 1.8 GHz over
+    # launches 4-25 at 4096^2), 10-25% slower than the steady rate; each
+    # entry below warms up 150 steps past it (the headline takes --warmup
+    # steps and times --steps).
     if not args.no_stencil4:
         # on the finite-state droplet: at density ratio 100 the standard
         # scheme diverges within a few steps, so the WB step is timed
