@@ -302,3 +302,24 @@ def test_parity_wb_rho0_3d(orc, lbm, q):
         f = np.moveaxis(s.get_populations(), 0, -1)
         s.close()
         assert np.abs(f - fo).max() <= tol, (q, prec)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("nx,ny,nz", [(6, 1, 2), (1, 1, 3), (2, 3, 2), (1, 5, 2)])
+def test_degenerate_shapes_3d(orc, lbm, q, nx, ny, nz):
+    """The thinnest 3-D lattices the library accepts (nz = 2, a single row or
+    column; every stencil and pull wraps onto the same few nodes) against the
+    oracle, WB and standard, to 1e-11."""
+    ph = I.PAPER_PHYS
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    rho0 = 0.5 + 0.3 * rng.uniform(-1, 1, (nz, ny, nx))
+    p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
+    for scheme in ("well_balanced", "standard"):
+        fo = orc.step3(scheme, p, orc.init3(scheme, p, rho0, q=q), 40)
+        s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, nz=nz, q3=q)
+        s.init(rho0, scheme=scheme)
+        s.step(40, scheme)
+        f = np.moveaxis(s.get_populations(), 0, -1)
+        s.close()
+        assert np.isfinite(fo).all()
+        assert np.abs(f - fo).max() <= TOL, (scheme, q, nx, ny, nz)
