@@ -1,5 +1,6 @@
 /*
- * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 two-phase lattice Boltzmann step.
+ * lbm.h -- C ABI of the MI355X (gfx950) two-phase lattice Boltzmann step
+ * (D2Q9; D3Q19 and D3Q27 for 3-D lattices, see lbm_params.nz and lattice3).
  *
  * The operation is one time step of the lattice Boltzmann equation for a
  * liquid-vapour fluid driven by a chemical potential, in the two forms of
@@ -29,7 +30,8 @@
  *     and HIP graph objects (a batch also a second stream and two events),
  *     which the destroy calls free.
  *   - Host field arrays are dense, row-major double[ny][nx] (element (x, y)
- *     at index y*nx + x).  Population arrays are double[9][ny][nx].
+ *     at index y*nx + x); 3-D: double[nz][ny][nx].  Population arrays are
+ *     double[9][ny][nx]; 3-D: double[q][nz][ny][nx], q = 19 or 27.
  *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
  *     void*; NULL is the default stream).  lbm_step and lbm_batch_run are
  *     asynchronous; calls that return host data synchronise that stream.
