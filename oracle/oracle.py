@@ -1,8 +1,10 @@
-"""FP64 CPU oracle of the D2Q9 two-phase LBE step -- TEST INFRASTRUCTURE.
+"""FP64 CPU oracle of the two-phase LBE step -- TEST INFRASTRUCTURE.
 
-This module wraps ``lbm_oracle.c`` (plain C, double precision, scalar loops,
-array-of-structures populations) through ctypes and adds the diagnostics the
-paper reads off a steady state (bulk densities, Laplace pressure jump).
+This module wraps ``lbm_oracle.c`` (D2Q9) and ``lbm_oracle3d.c`` (the same
+equations in 3-D, compiled for D3Q19 and, through ``lbm_oracle3d27.c``, for
+D3Q27) -- plain C, double precision, scalar loops, array-of-structures
+populations -- through ctypes, and adds the diagnostics the paper reads off a
+steady state (bulk densities, Laplace pressure jump).
 Only the test-suite, the smoke entry point and the CPU-baseline leg of the
 benchmark use it; the product path never imports it.
 
@@ -13,6 +15,7 @@ LBE, Eqs. 24-26), Sec. IV (double-well free energy, Eqs. 35-37).
 Array conventions (numpy, float64, C-contiguous):
   f    : shape (ny, nx, 9), population i of node (x, y) at f[y, x, i]
   field: shape (ny, nx)
+  3-D  : f (nz, ny, nx, q), fields (nz, ny, nx)
 """
 from __future__ import annotations
 
