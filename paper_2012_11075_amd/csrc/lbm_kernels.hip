@@ -189,11 +189,20 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
                                            Global<T>* __restrict__ fout,
                                            const ObserveOut& obs) {
   using R = T;
-  // LDS column j of the rho ring holds lattice column x0 - 2 + j, column m of
-  // the mu ring lattice column x0 - 1 + m (periodic).
+  // LDS column j of the rho ring holds lattice column x0 - 2 + j (periodic).
   __shared__ R rs[5][BW + 4];  // rho: rows y-2 .. y+2 of the output row y
-  __shared__ R ms[3][BW + 2];  // mu: rows y-1 .. y+1
   __shared__ R fl[2][Q][BW];   // populations of rows y and y+1, each thread its own column
+  // mu stays in registers: each thread evaluates it at its own column and at
+  // both neighbours, for the three rows that its node's gradient needs
+  // (mu3[0..2] = row index k-3 .. k-1 at stage k; [.][0..2] = x-1, x, x+1).
+  // Every value is computed by the same expression from the same rho, so it
+  // is bit-identical to the value of the column's own thread; the price is
+  // two extra evaluations per node, the gain one block-wide barrier per row.
+  R mu3[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) mu3[a][b] = (R)0;
   const PhysR<R> p = to_r<R>(phys);
   const int t = threadIdx.x;
   const int chunk = tile / tl.strips;
@@ -294,7 +303,9 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
 
   // One row step: prefetch row k+D into `nxt`; publish rho of row k (`cur`,
   // which then parks in LDS for two rows); mu of row k-1; update the node of
-  // row k-2.
+  // row k-2.  One barrier per row: the rho ring slot written at stage k + 1
+  // holds row index k - 4, which no thread reads at stage k, and a thread
+  // cannot reach stage k + 2 before every thread has left stage k.
   auto stage = [&](int k, R(&nxt)[Q], R(&cur)[Q], R& hnxt, R& hcur) {
     load_row(yload, nxt);  // rows past the chunk are valid (periodic) and unused
     load_halo(yload, hnxt);
@@ -317,33 +328,37 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
     __syncthreads();
     if (k >= 2) {
       // mu at row index k-1: mu0(rho) - kappa lap(rho), 9-point Laplacian, at
-      // ring column m (rho-ring columns m .. m+2)
-      const int a = (k - 2) % 5, c0 = (k - 1) % 5, d = sk, mk = (k - 1) % 3;
+      // ring column m (rho-ring columns m .. m+2), for this column and its
+      // two neighbours (no exchange through LDS)
+      const int a = (k - 2) % 5, c0 = (k - 1) % 5, d = sk;
       auto mu_at = [&](int m) {
         const R r0 = rs[c0][m + 1];
         const R ax = (rs[c0][m + 2] + rs[c0][m]) + (rs[a][m + 1] + rs[d][m + 1]);
         const R dg = (rs[a][m + 2] + rs[a][m]) + (rs[d][m + 2] + rs[d][m]);
         const R lap = ((R)4 * ax + dg - (R)20 * r0) * ((R)1 / (R)6);
-        ms[mk][m] = mu0(r0, p) - p.kappa * lap;
+        return mu0(r0, p) - p.kappa * lap;
       };
-      mu_at(t + 1);
-      if (t == 0) mu_at(0);
-      if (t == 1) mu_at(BW + 1);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        mu3[0][b] = mu3[1][b];
+        mu3[1][b] = mu3[2][b];
+      }
+      mu3[2][0] = mu_at(t);
+      mu3[2][1] = mu_at(t + 1);
+      mu3[2][2] = mu_at(t + 2);
     }
-    __syncthreads();
     if (k >= 4 && k < K && outc) {
       const int sM = (k - 3) % 5, s0 = (k - 2) % 5, sP = (k - 1) % 5;
-      const int mM = (k - 3) % 3, m0 = (k - 2) % 3, mP = (k - 1) % 3;
       const R third = (R)1 / (R)3, twelfth = (R)1 / (R)12;
       const R rho = rs[s0][t + 2];
       const R grx = (rs[s0][t + 3] - rs[s0][t + 1]) * third +
                     ((rs[sP][t + 3] - rs[sP][t + 1]) + (rs[sM][t + 3] - rs[sM][t + 1])) * twelfth;
       R gry = (rs[sP][t + 2] - rs[sM][t + 2]) * third +
               ((rs[sP][t + 3] + rs[sP][t + 1]) - (rs[sM][t + 3] + rs[sM][t + 1])) * twelfth;
-      const R gmx = (ms[m0][t + 2] - ms[m0][t]) * third +
-                    ((ms[mP][t + 2] - ms[mP][t]) + (ms[mM][t + 2] - ms[mM][t])) * twelfth;
-      R gmy = (ms[mP][t + 1] - ms[mM][t + 1]) * third +
-              ((ms[mP][t + 2] + ms[mP][t]) - (ms[mM][t + 2] + ms[mM][t])) * twelfth;
+      const R gmx = (mu3[1][2] - mu3[1][0]) * third +
+                    ((mu3[2][2] - mu3[2][0]) + (mu3[0][2] - mu3[0][0])) * twelfth;
+      R gmy = (mu3[2][1] - mu3[0][1]) * third +
+              ((mu3[2][2] + mu3[2][0]) - (mu3[0][2] + mu3[0][0])) * twelfth;
       if (up) {
         gry = -gry;
         gmy = -gmy;
@@ -373,7 +388,7 @@ __device__ __forceinline__ void march_tile(const Geometry& g, const Physics& phy
         if (obs.rho) obs.rho[o] = drho;
         if (obs.ux) obs.ux[o] = dux;
         if (obs.uy) obs.uy[o] = duy;
-        if (obs.mu) obs.mu[o] = (double)ms[m0][t + 1];
+        if (obs.mu) obs.mu[o] = (double)mu3[1][1];
         const double u2 = dux * dux + duy * duy;
         const double um = sqrt(u2);
         if (!(isfinite(drho) && drho > 0.0 && isfinite(um))) acc.bad = 1.0;
