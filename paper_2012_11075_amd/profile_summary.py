@@ -117,6 +117,42 @@ def dispatch_table(kt_root, pmc_root, kernel, xcds=8):
     return rows
 
 
+SQ_MIX = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+          "SQ_INSTS_BRANCH"]
+SQ_CYC = ["SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_ANY"]
+
+
+def sq_counters(root, kernel):
+    """Mean per dispatch of every counter of `kernel` in a --pmc run, the
+    first dispatch (cold caches) left out."""
+    by = {}
+    for r in _csv(root, "counter_collection.csv"):
+        if "::" + kernel in r["Kernel_Name"]:
+            d = by.setdefault(int(r["Dispatch_Id"]), {})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    ids = sorted(by)[1:] or sorted(by)
+    return {k: sum(by[i].get(k, 0.0) for i in ids) / len(ids) for k in by[ids[0]]}, len(ids)
+
+
+def sq_table(specs):
+    """Rows of instruction counts per 64 node updates (one wave instruction
+    covers 64 lanes) and per-wave cycle fractions, one per spec
+    'label|mix_dir|cycles_dir|kernel prefix|nodes per launch'."""
+    rows = []
+    for spec in specs:
+        label, mix, cyc, kernel, nodes = spec.split("|")
+        m, n1 = sq_counters(mix, kernel)
+        c, n2 = sq_counters(cyc, kernel)
+        waves64 = int(nodes) / 64.0
+        row = {"label": label, "kernel": kernel, "nodes": int(nodes), "dispatches": [n1, n2]}
+        for k in SQ_MIX:
+            row[k + "_per_64_nodes"] = m.get(k, float("nan")) / waves64
+        for k in SQ_CYC:
+            row[k + "_fraction_of_wave_cycles"] = c.get(k, float("nan")) / c["SQ_WAVE_CYCLES"]
+        rows.append(row)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--root", default="")
@@ -138,9 +174,35 @@ def main():
                          "fp64=304,fp32s=152 (default 144 and 72)")
     ap.add_argument("--kt-only", action="store_true",
                     help="kernel trace only (no counter runs): durations, no traffic")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="'label|mix_dir|cycles_dir|kernel prefix|nodes per launch': instruction "
+                         "mix and cycle fractions from two SQ counter runs (repeatable)")
     args = ap.parse_args()
     global KERNEL
     KERNEL = args.kernel
+    if args.sq:
+        rows = sq_table(args.sq)
+        with open(args.out + ".json", "w") as fh:
+            json.dump({"commands": {"mix": args.command_kt, "cycles": args.command_pmc},
+                       "rows": rows}, fh, indent=1)
+        lines = ["# %s (rocprofv3)" % args.title, "",
+                 "Commands (run from `/tmp`, `TMPDIR=/tmp`, repository at `$R`):", "",
+                 "```", args.command_kt, args.command_pmc, "```", "",
+                 "Instructions are wave instructions per 64 node updates (one per lane and node); "
+                 "cycle columns are the counter over SQ_WAVE_CYCLES, the fraction of a resident "
+                 "wave's time spent issuing that kind of instruction or waiting on one.", "",
+                 "| workload | VALU | SALU | LDS | VMEM rd | VMEM wr | branch | VALU active | "
+                 "scalar active | LDS active | waiting |",
+                 "|---|---|---|---|---|---|---|---|---|---|---|"]
+        for r in rows:
+            lines.append("| %s | %s | %.3f | %.3f | %.3f | %.3f |" % (
+                r["label"] + " (`%s`)" % r["kernel"],
+                " | ".join("%.1f" % r[k + "_per_64_nodes"] for k in SQ_MIX),
+                *[r[k + "_fraction_of_wave_cycles"] for k in SQ_CYC]))
+        with open(args.out + ".md", "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
     if args.dispatch_table:
         kt_dir, pmc_dir = args.dispatch_table.split(",")
         rows = dispatch_table(kt_dir, pmc_dir, args.kernel)
