@@ -85,15 +85,20 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
     t_obs = time.perf_counter() - t_obs
     tile = s.get_tile()
     kps = s.lib.lbm_kernels_per_step(s.ctx)
+    spl = s.lib.lbm_steps_per_launch(s.ctx)
     s.close()
     del s
     torch.cuda.empty_cache()
     nodes = prob.nx * prob.ny
     ms_step = ms / steps
     mlups = nodes * steps / (ms / 1e3) / 1e6
+    # a launch reads and writes every population once and advances the state
+    # `spl` steps (2 with two steps per launch): its algorithmic bytes are
+    # BYTES_PER_UPDATE x nodes over spl steps' time
     bpu = BYTES_PER_UPDATE[precision]
     per_launch = bpu * nodes
-    achieved = per_launch / (ms_step / kps / 1e3) / 1e9
+    launch_ms = ms_step * spl / kps
+    achieved = per_launch / (launch_ms / 1e3) / 1e9
     traffic = measured_traffic(precision)
     return {
         "mlups": mlups,
@@ -102,7 +107,7 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
         "tile": list(tile),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_update": bpu},
+                     "traffic": traffic, "bytes_per_update": bpu / spl, "steps_per_launch": spl},
         "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
         "observation": ob if fields else None,
         # the whole job through the host boundary: density in over PCIe, the
@@ -292,17 +297,20 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     kps = s.lib.lbm_kernels_per_step(s.ctx)
+    spl = s.lib.lbm_steps_per_launch(s.ctx)
     used = s.get_tile()
     ob = s.observe(fields=(), raise_nonfinite=False)
     s.close()
     del s
     torch.cuda.empty_cache()
     nodes = prob.nx * prob.ny
-    bpu = STENCIL4_BYTES // 2 if precision == "fp32s" else STENCIL4_BYTES
+    # HBM bytes per node update: one read and one write of every population
+    # per launch, a launch advancing spl steps
+    bpu = (STENCIL4_BYTES // 2 if precision == "fp32s" else STENCIL4_BYTES) // spl
     gbs = bpu * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
             "scheme": scheme, "precision": precision, "kernels_per_step": kps, "tile": list(used),
-            "bytes_per_update": bpu,
+            "bytes_per_update": bpu, "steps_per_launch": spl,
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "workload": "%s, %s scheme, %s force stencil, %s, %d steps"

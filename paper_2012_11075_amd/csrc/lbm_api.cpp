@@ -309,9 +309,30 @@ void drop_graphs(lbm_ctx* c) {
 }
 
 // Enqueue n plain step launches.
+// Tile depth 4 selects the two-step kernel (FP32-shifted 2-D lattices with
+// the central stencil, 512-thread blocks; lbm_set_tile checks).
+bool fused_pairs(const lbm_ctx* c) { return !c->d3() && c->tl.depth == 4; }
+
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   const lbmk::Physics ph = make_physics(c->prm, scheme);
   const lbmk::Physics3 ph3 = make_physics3(c->prm, scheme);
+  if (fused_pairs(c)) {
+    // two steps per launch; an odd count ends with one step of the same tile
+    int64_t k = 0;
+    for (; k + 2 <= n; k += 2) {
+      HIPCHK(c, lbmk::launch_step2(c->storage(), scheme, c->L.g, ph, c->tl.rows, c->buf(c->cur),
+                                   c->buf(1 - c->cur), s));
+      c->cur = 1 - c->cur;
+    }
+    if (k < n) {
+      lbmk::Tiling t1 = c->tl;
+      t1.depth = 3;
+      HIPCHK(c, lbmk::launch_step(c->storage(), scheme, c->L.g, ph, t1, c->buf(c->cur),
+                                  c->buf(1 - c->cur), s));
+      c->cur = 1 - c->cur;
+    }
+    return LBM_OK;
+  }
   for (int64_t k = 0; k < n; ++k) {
     if (c->d3()) {
       HIPCHK(c, lbmk::launch_step3(c->storage(), scheme, c->L.g3, ph3, c->tl3, c->buf(c->cur),
@@ -328,8 +349,10 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
   return LBM_OK;
 }
 
-// Graph of graph_steps launches starting from the current buffer (even count:
-// the buffer parity is the same after a replay).
+// Graph of graph_steps steps starting from the current buffer, kept per
+// starting buffer (even count: one-step launches leave the buffer parity as
+// it was; two-step launches flip it when graph_steps / 2 is odd, and
+// lbm_step follows that flip).
 lbm_status get_graph(lbm_ctx* c, int scheme, hipGraphExec_t* out) {
   hipGraphExec_t& slot = c->graph[scheme][c->cur];
   if (!slot) {
@@ -526,6 +549,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, lbm_scheme scheme) {
       st = get_graph(c, scheme, &ge);
       if (st != LBM_OK) return st;
       HIPCHK(c, hipGraphLaunch(ge, c->stream));
+      // a replay of two-step launches swaps the buffers once per two steps
+      if (fused_pairs(c) && ((c->graph_steps / 2) & 1)) c->cur = 1 - c->cur;
       left -= c->graph_steps;
     }
   }
@@ -794,7 +819,14 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
   if (block == 0) block = c->tl.block;
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
-  if (depth < 1 || depth > 3) return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3");
+  if (depth == 4) {
+    if (c->prm.precision != LBM_FP32_SHIFTED || c->prm.force_stencil != 0 || block != 512)
+      return fail(c, LBM_EINVAL,
+                  "depth 4 (two steps per launch) needs FP32-shifted storage, the central "
+                  "stencil and block 512");
+  } else if (depth < 1 || depth > 3) {
+    return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3 (4: two steps per launch)");
+  }
   if (!lbmk::block_width_supported(block))
     return fail(c, LBM_EINVAL, "unsupported block width " + std::to_string(block));
   if (c->prm.force_stencil == 1 && !lbmk::stencil4_block_supported(block))
@@ -852,6 +884,10 @@ const char* lbm_last_error(const lbm_ctx* c) {
 
 int32_t lbm_kernels_per_step(const lbm_ctx* c) {
   return 1;
+}
+
+int32_t lbm_steps_per_launch(const lbm_ctx* c) {
+  return c && fused_pairs(c) ? 2 : 1;
 }
 
 }  // extern "C"

@@ -483,6 +483,261 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return xcd * q8 + min(xcd, r8) + l;
 }
 
+// Two steps in one pass (temporal blocking): the step reads and writes each
+// population once per two steps instead of once per step.  A block of 512
+// threads runs the first step on 512 consecutive columns (xa0 .. xa0 + 511,
+// xa0 = x0 - 3) and keeps its output rows in LDS; the second step reads them
+// there and writes columns x0 .. x0 + 505 of the state two steps on.  LDS:
+// four first-step output rows of 9 x 512 values, both steps' rho rings and
+// the first step's parked rows, 131 KB in FP32 (one block per CU); FP64
+// would need twice that and does not fit.  The second step's node needs
+// first-step populations at x +- 3 (its pull, then rho at x +- 2 for mu and
+// the gradients), hence the 6 columns the first step computes in addition.
+// Along y the first step runs 3 rows ahead of the second step's chunk on each
+// side.  One barrier per row: every LDS value a thread reads after the
+// barrier of row k was written before it, or, for the rings written after
+// the barrier, in a slot no thread reads during row k.  Each node is
+// evaluated by the same expressions as in the one-step kernel, so the result
+// is bit-identical to two launches of it.
+constexpr int M2W = 512, M2S = M2W - 6;
+template <typename T, int SCHEME, int D>
+__global__ void __launch_bounds__(M2W)
+    march2(Geometry g, Physics phys, int rows, int strips, int chunks, const T* __restrict__ fin_,
+           T* __restrict__ fout_) {
+  constexpr int BW = M2W;
+  using R = T;
+  const Global<T>* fin = (const Global<T>*)fin_;
+  Global<T>* fout = (Global<T>*)fout_;
+  __shared__ R rs[5][BW + 4];  // first step's rho, column j = lattice xa0 - 2 + j
+  __shared__ R fl[2][Q][BW];   // first step's populations of rows y, y+1 (own column)
+  __shared__ R f1[4][Q][BW];   // first step's post-collision rows, column t = xa0 + t
+  __shared__ R r2[5][BW + 4];  // second step's rho, column j = xa0 - 2 + j
+  R mu3[3][3], mb[3][3];       // mu of the two steps, rows r-1 .. r+1 at columns x-1 .. x+1
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) mu3[a][b] = mb[a][b] = (R)0;
+  const PhysR<R> p = to_r<R>(phys);
+  const int t = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, strips * chunks);
+  const int chunk = tile / strips;
+  const int strip = tile - chunk * strips;
+  const int x0 = strip * M2S, xa0 = x0 - 3;
+  auto wrapx = [&](int x) {
+    x %= g.nx;
+    return x < 0 ? x + g.nx : x;
+  };
+  const int xc = wrapx(xa0 + t);
+  const int y0 = chunk * rows;
+  const int H = min(rows, g.ny - y0);
+  const int K = H + 12;
+  const int xb = xa0 + t;  // the second step's output column of this thread
+  const bool outc = t >= 3 && t < BW - 3 && xb < g.nx;
+  auto wrapy = [&](int y) {
+    y %= g.ny;
+    return y < 0 ? y + g.ny : y;
+  };
+  auto next_row = [&](int y) { return y + 1 == g.ny ? 0 : y + 1; };
+  auto row_above = [&](int y) { return (y == 0) ? g.ny - 1 : y - 1; };
+  auto row_below = [&](int y) { return (y + 1 == g.ny) ? 0 : y + 1; };
+
+  const int xw = (xc == 0) ? g.nx - 1 : xc - 1;
+  const int xe = (xc + 1 == g.nx) ? 0 : xc + 1;
+  const unsigned bc = (unsigned)xc * (unsigned)sizeof(T), bw = (unsigned)xw * (unsigned)sizeof(T),
+                 be = (unsigned)xe * (unsigned)sizeof(T);
+  auto at = [](const Global<T>* row, unsigned b) -> T {
+    return *(const Global<T>*)((const Global<char>*)row + b);
+  };
+  auto load_row = [&](int y, R(&dst)[Q]) {
+    const long long P = g.plane;
+    const Global<T>* r0 = fin + (long long)y * g.pitch;
+    const Global<T>* ru = fin + (long long)row_above(y) * g.pitch;
+    const Global<T>* rd = fin + (long long)row_below(y) * g.pitch;
+    dst[0] = at(r0, bc);
+    dst[1] = at(r0 + P, bw);
+    dst[2] = at(ru + 2 * P, bc);
+    dst[3] = at(r0 + 3 * P, be);
+    dst[4] = at(rd + 4 * P, bc);
+    dst[5] = at(ru + 5 * P, bw);
+    dst[6] = at(ru + 6 * P, be);
+    dst[7] = at(rd + 7 * P, be);
+    dst[8] = at(rd + 8 * P, bw);
+  };
+  const bool hl = t < 4 * Q;
+  const int hcol = t / Q, hq = t - Q * (t / Q);
+  const int hslot = hcol < 2 ? hcol : BW + hcol;
+  int hsx = 0, hcy = 0;
+  long long hplane = 0;
+  if (hl) {
+    const int cxq = (hq == 1 || hq == 5 || hq == 8) ? 1 : ((hq == 3 || hq == 6 || hq == 7) ? -1 : 0);
+    const int cyq = (hq == 2 || hq == 5 || hq == 6) ? 1 : ((hq == 4 || hq == 7 || hq == 8) ? -1 : 0);
+    int hc = hcol < 2 ? xa0 - 2 + hcol : xa0 + BW + hcol - 2;
+    hc = ((hc % g.nx) + g.nx) % g.nx;
+    hsx = hc - cxq;
+    hsx = hsx < 0 ? hsx + g.nx : (hsx >= g.nx ? hsx - g.nx : hsx);
+    hcy = cyq;
+    hplane = (long long)hq * g.plane;
+  }
+  auto load_halo = [&](int y, R& dst) {
+    if (hl) {
+      const int hy = hcy > 0 ? row_above(y) : (hcy < 0 ? row_below(y) : y);
+      dst = fin[hplane + (long long)hy * g.pitch + hsx];
+    }
+  };
+  // first step's row index i <-> lattice row y0 - 5 + i
+  int yload = wrapy(y0 - 5);
+  const int tw = t > 0 ? t - 1 : 0, te = t + 1 < BW ? t + 1 : BW - 1;
+  const R third = (R)1 / (R)3, twelfth = (R)1 / (R)12;
+
+  // Row step k: first step as in the one-step kernel (rho of row k, mu of row
+  // k-1, node of row k-2 into f1); second step: rho of row k-4 from f1 (rows
+  // k-5 .. k-3, written in earlier steps), its pulled populations into Bn;
+  // mu of row k-6; node of row k-7 (populations in Bu, pulled at row k-3)
+  // into fout.
+  auto stage = [&](int k, R(&nxt)[Q], R(&cur)[Q], R& hnxt, R& hcur, R(&Bn)[Q], R(&Bu)[Q]) {
+    load_row(yload, nxt);
+    load_halo(yload, hnxt);
+    yload = next_row(yload);
+    const int sk = k % 5;
+    rs[sk][t + 2] = p.rho_ref + sum9(cur);
+    if (t < 64) {
+      const int base = (hl ? hcol : 0) * Q;
+      R v[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = __shfl(hcur, base + i);
+      if (hl && hq == 0) rs[sk][hslot] = p.rho_ref + sum9(v);
+    }
+    R out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      out[i] = fl[k & 1][i][t];
+      fl[k & 1][i][t] = cur[i];
+    }
+    __syncthreads();
+    auto lap_mu = [&](R(&ring)[5][BW + 4], int a, int c0, int d, int m) {
+      const R r0 = ring[c0][m + 1];
+      const R ax = (ring[c0][m + 2] + ring[c0][m]) + (ring[a][m + 1] + ring[d][m + 1]);
+      const R dg = (ring[a][m + 2] + ring[a][m]) + (ring[d][m + 2] + ring[d][m]);
+      const R lap = ((R)4 * ax + dg - (R)20 * r0) * ((R)1 / (R)6);
+      return mu0(r0, p) - p.kappa * lap;
+    };
+    // first step
+    if (k >= 2) {
+      const int a = (k - 2) % 5, c0 = (k - 1) % 5, d = sk;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        mu3[0][b] = mu3[1][b];
+        mu3[1][b] = mu3[2][b];
+      }
+      mu3[2][0] = lap_mu(rs, a, c0, d, t);
+      mu3[2][1] = lap_mu(rs, a, c0, d, t + 1);
+      mu3[2][2] = lap_mu(rs, a, c0, d, t + 2);
+    }
+    if (k >= 4) {
+      const int sM = (k - 3) % 5, s0 = (k - 2) % 5, sP = (k - 1) % 5;
+      const R rho = rs[s0][t + 2];
+      const R grx = (rs[s0][t + 3] - rs[s0][t + 1]) * third +
+                    ((rs[sP][t + 3] - rs[sP][t + 1]) + (rs[sM][t + 3] - rs[sM][t + 1])) * twelfth;
+      const R gry = (rs[sP][t + 2] - rs[sM][t + 2]) * third +
+                    ((rs[sP][t + 3] + rs[sP][t + 1]) - (rs[sM][t + 3] + rs[sM][t + 1])) * twelfth;
+      const R gmx = (mu3[1][2] - mu3[1][0]) * third +
+                    ((mu3[2][2] - mu3[2][0]) + (mu3[0][2] - mu3[0][0])) * twelfth;
+      const R gmy = (mu3[2][1] - mu3[0][1]) * third +
+                    ((mu3[2][2] + mu3[2][0]) - (mu3[0][2] + mu3[0][0])) * twelfth;
+      R Fx = -rho * gmx, Fy = -rho * gmy;
+      if (SCHEME != WELL_BALANCED) {
+        Fx += grx * third;
+        Fy += gry * third;
+      }
+      R ux, uy;
+      velocity(out, rho, Fx, Fy, ux, uy);
+      const R drho = sizeof(T) == 8 ? rho : sum9(out);
+      collide<R, SCHEME>(out, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
+      const int so = (k - 2) & 3;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f1[so][i][t] = out[i];
+    }
+    // second step: rho of row k-4 (k >= 4)
+    {
+      const int sm = (k + 3) & 3, s0 = k & 3, sp = (k + 1) & 3;  // rows k-5, k-4, k-3
+      Bn[0] = f1[s0][0][t];
+      Bn[1] = f1[s0][1][tw];
+      Bn[2] = f1[sm][2][t];
+      Bn[3] = f1[s0][3][te];
+      Bn[4] = f1[sp][4][t];
+      Bn[5] = f1[sm][5][tw];
+      Bn[6] = f1[sm][6][te];
+      Bn[7] = f1[sp][7][te];
+      Bn[8] = f1[sp][8][tw];
+    }
+    // mu of row k-6 from r2 rows k-7 .. k-5 (written at rows k-3 .. k-1)
+    {
+      const int a = (k + 3) % 5, c0 = (k + 4) % 5, d = k % 5;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        mb[0][b] = mb[1][b];
+        mb[1][b] = mb[2][b];
+      }
+      mb[2][0] = lap_mu(r2, a, c0, d, t);
+      mb[2][1] = lap_mu(r2, a, c0, d, t + 1);
+      mb[2][2] = lap_mu(r2, a, c0, d, t + 2);
+    }
+    if (k >= 12 && k < K && outc) {
+      const int sM = (k + 2) % 5, s0 = (k + 3) % 5, sP = (k + 4) % 5;  // rows k-8 .. k-6
+      const R rho = r2[s0][t + 2];
+      const R grx = (r2[s0][t + 3] - r2[s0][t + 1]) * third +
+                    ((r2[sP][t + 3] - r2[sP][t + 1]) + (r2[sM][t + 3] - r2[sM][t + 1])) * twelfth;
+      const R gry = (r2[sP][t + 2] - r2[sM][t + 2]) * third +
+                    ((r2[sP][t + 3] + r2[sP][t + 1]) - (r2[sM][t + 3] + r2[sM][t + 1])) * twelfth;
+      const R gmx = (mb[1][2] - mb[1][0]) * third +
+                    ((mb[2][2] - mb[2][0]) + (mb[0][2] - mb[0][0])) * twelfth;
+      const R gmy = (mb[2][1] - mb[0][1]) * third +
+                    ((mb[2][2] + mb[2][0]) - (mb[0][2] + mb[0][0])) * twelfth;
+      R Fx = -rho * gmx, Fy = -rho * gmy;
+      if (SCHEME != WELL_BALANCED) {
+        Fx += grx * third;
+        Fy += gry * third;
+      }
+      R o2[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) o2[i] = Bu[i];
+      R ux, uy;
+      velocity(o2, rho, Fx, Fy, ux, uy);
+      const R drho = sizeof(T) == 8 ? rho : sum9(o2);
+      collide<R, SCHEME>(o2, drho, rho, ux, uy, Fx, Fy, grx, gry, p);
+      Global<T>* dst = fout + (long long)(y0 + k - 12) * g.pitch;
+      const unsigned bx = (unsigned)xb * (unsigned)sizeof(T);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        __builtin_nontemporal_store(
+            o2[i], (Global<T>*)((Global<char>*)(dst + (long long)i * g.plane) + bx));
+    }
+    // second step's rho of row k-4 (read from row k+1 on)
+    r2[(k + 1) % 5][t + 2] = p.rho_ref + sum9(Bn);
+  };
+
+  R s0[Q], s1[Q], s2[Q], s3[Q], B0[Q], B1[Q], B2[Q], B3[Q];
+  R h0 = (R)0, h1 = (R)0, h2 = (R)0, h3 = (R)0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) s0[i] = s1[i] = s2[i] = s3[i] = B0[i] = B1[i] = B2[i] = B3[i] = (R)0;
+  static_assert(D == 3, "the two-step kernel prefetches three rows");
+  load_row(yload, s0);
+  load_halo(yload, h0);
+  yload = next_row(yload);
+  load_row(yload, s1);
+  load_halo(yload, h1);
+  yload = next_row(yload);
+  load_row(yload, s2);
+  load_halo(yload, h2);
+  yload = next_row(yload);
+  for (int k = 0; k < K; k += 4) {
+    stage(k, s3, s0, h3, h0, B0, B1);
+    stage(k + 1, s0, s1, h0, h1, B1, B2);
+    stage(k + 2, s1, s2, h1, h2, B2, B3);
+    stage(k + 3, s2, s3, h2, h3, B3, B0);
+  }
+}
+
 // One lattice: one block per tile.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
 __global__ void __launch_bounds__(BW)
@@ -1128,6 +1383,25 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
                        const Tiling& t, const void* fin, void* fout, hipStream_t s) {
   ObserveOut none{nullptr, nullptr, nullptr, nullptr, nullptr};
   return launch_march<false>(storage, scheme, g, ph, t, fin, fout, none, s);
+}
+
+hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
+                        const void* fin, void* fout, hipStream_t s) {
+  if (storage != FP32 || rows < 1) return hipErrorInvalidValue;
+  const int strips = (g.nx + M2S - 1) / M2S, chunks = (g.ny + rows - 1) / rows;
+  const dim3 grid(strips * chunks), block(M2W);
+  const float* in = (const float*)fin;
+  float* out = (float*)fout;
+  if (scheme == STANDARD)
+    hipLaunchKernelGGL((march2<float, STANDARD, 3>), grid, block, 0, s, g, ph, rows, strips,
+                       chunks, in, out);
+  else if (scheme == STANDARD_EQF)
+    hipLaunchKernelGGL((march2<float, STANDARD_EQF, 3>), grid, block, 0, s, g, ph, rows, strips,
+                       chunks, in, out);
+  else
+    hipLaunchKernelGGL((march2<float, WELL_BALANCED, 3>), grid, block, 0, s, g, ph, rows, strips,
+                       chunks, in, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,

@@ -94,6 +94,7 @@ def load():
         "lbm_status_string": (ctypes.c_char_p, [st]),
         "lbm_last_error": (ctypes.c_char_p, [_VP]),
         "lbm_kernels_per_step": (i32, [_VP]),
+        "lbm_steps_per_launch": (i32, [_VP]),
         "lbm_batch_slot_bytes": (ctypes.c_size_t, [P]),
         "lbm_batch_overhead_bytes": (ctypes.c_size_t, [ctypes.c_size_t, i32]),
         "lbm_batch_create": (st, [_VP, ctypes.c_size_t, i32, _VP, ctypes.POINTER(_VP)]),
