@@ -167,7 +167,8 @@ def main():
     ap.add_argument("--command-pmc", default="")
     ap.add_argument("--tile", default="")
     ap.add_argument("--kernel", default="march<",
-                    help="name prefix of the kernel to summarise (march< or march_batch<)")
+                    help="name prefix of the kernel to summarise (march< or march_batch<), or one "
+                         "per precision: fp64=march<,fp32s=march2<")
     ap.add_argument("--title", default="Step kernel on the 4096 x 4096 droplet lattice")
     ap.add_argument("--bytes", default="",
                     help="algorithmic bytes per node and launch per precision, e.g. "
@@ -180,6 +181,7 @@ def main():
     args = ap.parse_args()
     global KERNEL
     KERNEL = args.kernel
+    per_prec = dict(kv.split("=", 1) for kv in args.kernel.split(",")) if "=" in args.kernel else {}
     if args.sq:
         rows = sq_table(args.sq)
         with open(args.out + ".json", "w") as fh:
@@ -232,6 +234,8 @@ def main():
     bpu = dict(kv.split("=") for kv in args.bytes.split(",")) if args.bytes else {}
     for prec in args.precisions.split(","):
         b = int(bpu[prec]) if prec in bpu else None
+        if per_prec:
+            KERNEL = per_prec[prec]
         res[prec] = (durations(args.root, prec, args.nodes, b) if args.kt_only
                      else summarise(args.root, prec, args.copy_mib, args.nodes, b))
     with open(args.out + ".json", "w") as fh:
