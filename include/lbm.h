@@ -223,12 +223,13 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme,
  * 256 threads, 1..2 with 512; D3Q27: 256 threads, depth 1..2; 1 is the
  * fastest measured).  Any valid shape gives
  * bit-identical populations.
- * Depth 4 (2-D, FP32-shifted, central force stencil, block width 512 only,
- * else LBM_EINVAL) selects two steps per launch: each launch reads and
- * writes the populations once and advances the state two steps
- * (bit-identical to two one-step launches); blocks write strips of 506
- * columns by `rows` rows, and an odd step count ends with one step of
- * depth 3.  Graph replays (lbm_set_graph_steps) follow the buffer swaps.
+ * Depth 4 (2-D, central force stencil; block width 512 for FP32-shifted
+ * storage, 256 for FP64, else LBM_EINVAL) selects two steps per launch:
+ * each launch reads and writes the populations once and advances the state
+ * two steps (bit-identical to two one-step launches); blocks write strips
+ * of block width - 6 columns by `rows` rows, and an odd step count ends
+ * with one step of depth 3.  Graph replays (lbm_set_graph_steps) follow the
+ * buffer swaps.
  * 0 keeps the current value.  A new 2-D context starts from a default
  * chosen from the lattice size (64-wide strips with short chunks up to
  * 512 columns, 256-wide strips above).  lbm_get_tile reports the shape in

@@ -309,8 +309,9 @@ void drop_graphs(lbm_ctx* c) {
 }
 
 // Enqueue n plain step launches.
-// Tile depth 4 selects the two-step kernel (FP32-shifted 2-D lattices with
-// the central stencil, 512-thread blocks; lbm_set_tile checks).
+// Tile depth 4 selects the two-step kernel (2-D lattices with the central
+// stencil, 512-thread blocks in FP32-shifted storage and 256 in FP64;
+// lbm_set_tile checks).
 bool fused_pairs(const lbm_ctx* c) { return !c->d3() && c->tl.depth == 4; }
 
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
@@ -820,10 +821,10 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
   if (depth == 4) {
-    if (c->prm.precision != LBM_FP32_SHIFTED || c->prm.force_stencil != 0 || block != 512)
+    if (c->prm.force_stencil != 0 || block != (c->prm.precision == LBM_FP32_SHIFTED ? 512 : 256))
       return fail(c, LBM_EINVAL,
-                  "depth 4 (two steps per launch) needs FP32-shifted storage, the central "
-                  "stencil and block 512");
+                  "depth 4 (two steps per launch) needs the central stencil and block 512 "
+                  "(FP32-shifted) or 256 (FP64)");
   } else if (depth < 1 || depth > 3) {
     return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3 (4: two steps per launch)");
   }

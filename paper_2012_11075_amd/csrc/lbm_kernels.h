@@ -133,9 +133,9 @@ enum Storage { FP64 = 0, FP32 = 1 };
 hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics& ph,
                        const Tiling& t, const void* fin, void* fout, hipStream_t s);
 
-// Two steps in one launch (FP32-shifted storage, central stencil): fin ->
-// fout is the state two steps on, bit-identical to two launch_step calls.
-// Blocks of 512 threads write strips of 506 columns by `rows` rows.
+// Two steps in one launch (central stencil): fin -> fout is the state two
+// steps on, bit-identical to two launch_step calls.  Blocks of 512 threads
+// (FP32) or 256 (FP64) write strips of 506 or 250 columns by `rows` rows.
 hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
                         const void* fin, void* fout, hipStream_t s);
 

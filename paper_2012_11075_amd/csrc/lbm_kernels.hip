@@ -484,13 +484,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Two steps in one pass (temporal blocking): the step reads and writes each
-// population once per two steps instead of once per step.  A block of 512
-// threads runs the first step on 512 consecutive columns (xa0 .. xa0 + 511,
-// xa0 = x0 - 3) and keeps its output rows in LDS; the second step reads them
-// there and writes columns x0 .. x0 + 505 of the state two steps on.  LDS:
-// four first-step output rows of 9 x 512 values, both steps' rho rings and
-// the first step's parked rows, 131 KB in FP32 (one block per CU); FP64
-// would need twice that and does not fit.  The second step's node needs
+// population once per two steps instead of once per step.  A block of BW
+// threads (512 in FP32, 256 in FP64) runs the first step on BW consecutive
+// columns (xa0 .. xa0 + BW - 1, xa0 = x0 - 3) and keeps its output rows in
+// LDS; the second step reads them there and writes columns x0 .. x0 + BW - 7
+// of the state two steps on.  LDS: four first-step output rows of 9 x BW
+// values, both steps' rho rings and the first step's parked rows, 131 KB
+// either way (one block per CU).  The second step's node needs
 // first-step populations at x +- 3 (its pull, then rho at x +- 2 for mu and
 // the gradients), hence the 6 columns the first step computes in addition.
 // Along y the first step runs 3 rows ahead of the second step's chunk on each
@@ -499,12 +499,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // the barrier, in a slot no thread reads during row k.  Each node is
 // evaluated by the same expressions as in the one-step kernel, so the result
 // is bit-identical to two launches of it.
-constexpr int M2W = 512, M2S = M2W - 6;
-template <typename T, int SCHEME, int D>
-__global__ void __launch_bounds__(M2W)
+template <typename T, int SCHEME, int D, int BW>
+__global__ void __launch_bounds__(BW)
     march2(Geometry g, Physics phys, int rows, int strips, int chunks, const T* __restrict__ fin_,
            T* __restrict__ fout_) {
-  constexpr int BW = M2W;
+  constexpr int M2S = BW - 6;
   using R = T;
   const Global<T>* fin = (const Global<T>*)fin_;
   Global<T>* fout = (Global<T>*)fout_;
@@ -1385,23 +1384,33 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
   return launch_march<false>(storage, scheme, g, ph, t, fin, fout, none, s);
 }
 
-hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
-                        const void* fin, void* fout, hipStream_t s) {
-  if (storage != FP32 || rows < 1) return hipErrorInvalidValue;
-  const int strips = (g.nx + M2S - 1) / M2S, chunks = (g.ny + rows - 1) / rows;
-  const dim3 grid(strips * chunks), block(M2W);
-  const float* in = (const float*)fin;
-  float* out = (float*)fout;
+namespace {
+template <typename T, int BW>
+hipError_t launch_step2_t(int scheme, const Geometry& g, const Physics& ph, int rows,
+                          const void* fin, void* fout, hipStream_t s) {
+  const int sw = BW - 6;
+  const int strips = (g.nx + sw - 1) / sw, chunks = (g.ny + rows - 1) / rows;
+  const dim3 grid(strips * chunks), block(BW);
+  const T* in = (const T*)fin;
+  T* out = (T*)fout;
   if (scheme == STANDARD)
-    hipLaunchKernelGGL((march2<float, STANDARD, 3>), grid, block, 0, s, g, ph, rows, strips,
+    hipLaunchKernelGGL((march2<T, STANDARD, 3, BW>), grid, block, 0, s, g, ph, rows, strips,
                        chunks, in, out);
   else if (scheme == STANDARD_EQF)
-    hipLaunchKernelGGL((march2<float, STANDARD_EQF, 3>), grid, block, 0, s, g, ph, rows, strips,
+    hipLaunchKernelGGL((march2<T, STANDARD_EQF, 3, BW>), grid, block, 0, s, g, ph, rows, strips,
                        chunks, in, out);
   else
-    hipLaunchKernelGGL((march2<float, WELL_BALANCED, 3>), grid, block, 0, s, g, ph, rows, strips,
+    hipLaunchKernelGGL((march2<T, WELL_BALANCED, 3, BW>), grid, block, 0, s, g, ph, rows, strips,
                        chunks, in, out);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
+                        const void* fin, void* fout, hipStream_t s) {
+  if (rows < 1) return hipErrorInvalidValue;
+  return storage == FP32 ? launch_step2_t<float, 512>(scheme, g, ph, rows, fin, fout, s)
+                         : launch_step2_t<double, 256>(scheme, g, ph, rows, fin, fout, s);
 }
 
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,

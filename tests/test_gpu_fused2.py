@@ -1,11 +1,12 @@
-"""Two steps per launch (tile depth 4: FP32-shifted 2-D lattices, central
-force stencil, 512-thread blocks) through the C ABI.  Each launch runs the
-first step into LDS and the second step from there (temporal blocking), so
-the populations must equal those of one-step launches bit for bit: for
-every scheme, ragged and tiny lattices, odd step counts (which end with one
-one-step launch), graph replays whose launch count flips the buffers, and
-the benchmark's 4096^2 launch configuration, where one launch is also held
-against two steps of the FP64 oracle on sampled crops."""
+"""Two steps per launch (tile depth 4: 2-D lattices, central force stencil,
+512-thread blocks in FP32-shifted storage and 256 in FP64) through the C
+ABI.  Each launch runs the first step into LDS and the second step from
+there (temporal blocking), so the populations must equal those of one-step
+launches bit for bit: for every scheme, ragged and tiny lattices, odd step
+counts (which end with one one-step launch), graph replays whose launch
+count flips the buffers, and the benchmark's 4096^2 launch configurations,
+where one launch is also held against two steps of the FP64 oracle on
+sampled crops."""
 import numpy as np
 import pytest
 
@@ -24,8 +25,11 @@ def lbm():
     return L
 
 
-def run(L, prob, scheme, tile, steps, graph_steps=0, split=3):
-    s = L.Solver.for_problem(prob, precision="fp32s")
+BLOCK = {"fp32s": 512, "fp64": 256}
+
+
+def run(L, prob, scheme, tile, steps, graph_steps=0, split=3, precision="fp32s"):
+    s = L.Solver.for_problem(prob, precision=precision)
     s.set_tile(*tile)
     if graph_steps:
         s.set_graph_steps(graph_steps)
@@ -39,23 +43,29 @@ def run(L, prob, scheme, tile, steps, graph_steps=0, split=3):
     return f, ob, spl
 
 
-# (nx, ny, rows, steps, graph steps): one strip and several, strips that end
-# ragged or exactly at 506 columns, lattices narrower than the first step's
-# 512 columns and shorter than a chunk, graphs of 4 (even launch count) and
-# of 6 and 10 steps (odd launch count)
-CASES = [(700, 300, 128, 40, 0), (1100, 90, 32, 23, 0), (505, 37, 16, 31, 0), (506, 50, 8, 20, 0),
-         (507, 12, 4, 9, 0), (5, 3, 4, 14, 0), (33, 130, 64, 40, 10), (600, 200, 96, 44, 4),
-         (250, 61, 20, 30, 6)]
+# (precision, nx, ny, rows, steps, graph steps): one strip and several,
+# strips that end ragged or exactly at the strip width (506 columns in FP32,
+# 250 in FP64), lattices narrower than the first step's columns and shorter
+# than a chunk, graphs of 4 (even launch count) and of 6 and 10 steps (odd
+# launch count)
+CASES = [("fp32s", 700, 300, 128, 40, 0), ("fp32s", 1100, 90, 32, 23, 0),
+         ("fp32s", 505, 37, 16, 31, 0), ("fp32s", 506, 50, 8, 20, 0), ("fp32s", 507, 12, 4, 9, 0),
+         ("fp32s", 5, 3, 4, 14, 0), ("fp32s", 33, 130, 64, 40, 10), ("fp32s", 600, 200, 96, 44, 4),
+         ("fp32s", 250, 61, 20, 30, 6),
+         ("fp64", 700, 300, 128, 40, 0), ("fp64", 1100, 90, 32, 23, 0), ("fp64", 249, 37, 16, 31, 0),
+         ("fp64", 250, 50, 8, 20, 0), ("fp64", 251, 12, 4, 9, 0), ("fp64", 5, 3, 4, 14, 0),
+         ("fp64", 33, 130, 64, 40, 10), ("fp64", 600, 200, 96, 44, 6)]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "%dx%d_r%d_n%d_g%d" % c)
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%s_%dx%d_r%d_n%d_g%d" % c)
 def test_two_step_launch_bit_identical(lbm, case):
-    nx, ny, rows, steps, gsteps = case
+    prec, nx, ny, rows, steps, gsteps = case
     prob = I.with_size(I.PAPER_DROPLET, nx, ny)
+    bw = BLOCK[prec]
     for scheme in SCHEMES:
         print("two-step", case, scheme, flush=True)
-        f1, o1, spl1 = run(lbm, prob, scheme, (512, rows, 3), steps, gsteps)
-        f2, o2, spl2 = run(lbm, prob, scheme, (512, rows, 4), steps, gsteps)
+        f1, o1, spl1 = run(lbm, prob, scheme, (bw, rows, 3), steps, gsteps, precision=prec)
+        f2, o2, spl2 = run(lbm, prob, scheme, (bw, rows, 4), steps, gsteps, precision=prec)
         assert (spl1, spl2) == (1, 2)
         assert np.array_equal(f1, f2, equal_nan=True), (case, scheme)
         for k in ("rho", "ux", "uy", "mu"):
@@ -63,70 +73,74 @@ def test_two_step_launch_bit_identical(lbm, case):
         assert o1["step"] == o2["step"] == steps
 
 
-def test_two_step_tile_rules(lbm):
-    """Depth 4 is accepted only for FP32-shifted 2-D lattices with the
-    central stencil and 512-thread blocks; the refused calls leave the tile
-    as it was."""
+@pytest.mark.parametrize("prec", ["fp32s", "fp64"])
+def test_two_step_tile_rules(lbm, prec):
+    """Depth 4 is accepted only for 2-D lattices with the central stencil
+    and 512-thread blocks (FP32-shifted) or 256 (FP64); the refused calls
+    leave the tile as it was."""
     L = lbm
     prob = I.with_size(I.PAPER_DROPLET, 96, 64)
     ph = prob.physics
-    s = L.Solver.for_problem(prob, precision="fp32s")
-    s.set_tile(512, 32, 4)
-    assert s.get_tile() == (512, 32, 4) and s.lib.lbm_steps_per_launch(s.ctx) == 2
-    for bad in [(256, 32, 4), (128, 32, 4), (512, 32, 5)]:
+    bw = BLOCK[prec]
+    s = L.Solver.for_problem(prob, precision=prec)
+    s.set_tile(bw, 32, 4)
+    assert s.get_tile() == (bw, 32, 4) and s.lib.lbm_steps_per_launch(s.ctx) == 2
+    for bad in [(768 - bw, 32, 4), (128, 32, 4), (bw, 32, 5)]:
         with pytest.raises(L.LbmError):
             s.set_tile(*bad)
-    assert s.get_tile() == (512, 32, 4)
-    s.set_tile(512, 32, 3)
+    assert s.get_tile() == (bw, 32, 4)
+    s.set_tile(bw, 32, 3)
     assert s.lib.lbm_steps_per_launch(s.ctx) == 1
     s.close()
-    others = [L.Solver.for_problem(prob, precision="fp64"),
-              L.Solver.for_problem(prob, precision="fp32s", force_stencil=1),
+    others = [L.Solver.for_problem(prob, precision=prec, force_stencil=1),
               L.Solver(24, 20, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
-                       precision="fp32s", nz=12)]
+                       precision=prec, nz=12)]
     for o in others:
         with pytest.raises(L.LbmError):
-            o.set_tile(512, 32, 4)
+            o.set_tile(bw, 32, 4)
         assert o.lib.lbm_steps_per_launch(o.ctx) == 1
         o.close()
 
 
-def test_two_step_checkpoint_resume(lbm):
+@pytest.mark.parametrize("prec", ["fp32s", "fp64"])
+def test_two_step_checkpoint_resume(lbm, prec):
     """Populations saved after an odd number of steps and restored into a
     fresh context continue under two-step launches exactly as an
     uninterrupted run of one-step launches."""
     prob = I.with_size(I.PAPER_DROPLET, 640, 96)
     sch = "well_balanced"
-    a = lbm.Solver.for_problem(prob, precision="fp32s")
-    a.set_tile(512, 24, 4)
+    bw = BLOCK[prec]
+    a = lbm.Solver.for_problem(prob, precision=prec)
+    a.set_tile(bw, 24, 4)
     a.init(prob.rho(), scheme=sch)
     a.step(13, sch)
     f = a.get_populations()
     a.close()
-    b = lbm.Solver.for_problem(prob, precision="fp32s")
-    b.set_tile(512, 24, 4)
+    b = lbm.Solver.for_problem(prob, precision=prec)
+    b.set_tile(bw, 24, 4)
     b.set_populations(f, scheme=sch, step=13)
     b.step(20, sch)
     got = b.get_populations()
     b.close()
-    want, _, _ = run(lbm, prob, sch, (512, 24, 3), 33)
+    want, _, _ = run(lbm, prob, sch, (bw, 24, 3), 33, precision=prec)
     assert np.array_equal(got, want)
 
 
-def test_two_step_full_grid_sampled(orc, lbm):
-    """The benchmark's 4096^2 FP32 launch configuration (two steps per
-    launch): after 20 steps, one more launch against two steps of the FP64
-    oracle from the same (FP32-rounded) populations on periodic crops around
-    sampled windows, including the seams of the 506-column strips.  Two
-    steps add single-precision rounding of O(1) populations twice; the bound
-    is 4e-6."""
+@pytest.mark.parametrize("prec", ["fp32s", "fp64"])
+def test_two_step_full_grid_sampled(orc, lbm, prec):
+    """The benchmark's 4096^2 launch configurations (two steps per launch):
+    after 20 steps, one more launch against two steps of the FP64 oracle
+    from the same populations on periodic crops around sampled windows,
+    including the seams of the strips (506 columns in FP32, 250 in FP64).
+    FP64: 1e-11.  FP32: two steps add single-precision rounding of O(1)
+    populations twice; the bound is 4e-6."""
     from paper_2012_11075_amd import tune
     prob = I.DROPLET_4096_FINITE
     ph = prob.physics
     p = orc.Params(ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
-    tile = tune.bench_tile(prob.nx, prob.ny, "fp32s")
+    tile = tune.bench_tile(prob.nx, prob.ny, prec)
     assert tile[2] == 4, "the benchmark tile runs two steps per launch"
-    s = lbm.Solver.for_problem(prob, precision="fp32s")
+    s = lbm.Solver.for_problem(prob, precision=prec)
     s.set_tile(*tile)
     s.init(prob.rho(), scheme="well_balanced")
     s.step(20, "well_balanced")
@@ -135,7 +149,8 @@ def test_two_step_full_grid_sampled(orc, lbm):
     g = s.get_populations()
     s.close()
     rng = np.random.default_rng(5)
-    corners = [(0, 0), (4090, 4090), (146, 503), (2050, 1009), (1000, 4045)]
+    corners = [(0, 0), (4090, 4090), (146, 503), (2050, 1009), (1000, 4045), (273, 248),
+               (3836, 3998)]
     corners += [tuple(int(v) for v in rng.integers(0, 4096, 2)) for _ in range(5)]
     W, M = 28, 6
     worst = 0.0
@@ -146,5 +161,5 @@ def test_two_step_full_grid_sampled(orc, lbm):
         want = orc.step("well_balanced", p, crop, 2)[M:-M, M:-M]
         got = np.transpose(g[:, ys[M:-M]][:, :, xs[M:-M]], (1, 2, 0))
         worst = max(worst, np.abs(got - want).max())
-    print("fp32 two-step error on 4096^2 crops: %.3e" % worst)
-    assert worst < 4e-6
+    print("%s two-step error on 4096^2 crops: %.3e" % (prec, worst))
+    assert worst < (4e-6 if prec == "fp32s" else 1e-11)
