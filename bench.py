@@ -354,15 +354,18 @@ def time_largest(steps, warmup, n=32768):
     ms = e0.elapsed_time(e1) / steps
     ob = s.observe(fields=(), raise_nonfinite=False)
     used = s.get_tile()
+    spl = s.lib.lbm_steps_per_launch(s.ctx)
     s.close()
     del s
     gc.collect()
     torch.cuda.empty_cache()
     nodes = n * n
-    gbs = 144 * nodes / (ms / 1e3) / 1e9
+    # one read and one write of every population per launch of spl steps
+    bpu = 144 // spl
+    gbs = bpu * nodes / (ms / 1e3) / 1e9
     return {"value": round(nodes / (ms / 1e3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 4),
             "nx": n, "ny": n, "workspace_gb": round(need / 1e9, 1), "tile": list(used),
-            "bytes_per_update": 144, "hbm_gbs_algorithmic": round(gbs, 1),
+            "bytes_per_update": bpu, "steps_per_launch": spl, "hbm_gbs_algorithmic": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
             "workload": "%d^2 separable density, Sec. IV constants (ratio 5), WB, FP64, %d steps "
