@@ -56,6 +56,32 @@ def sweep(solver, scheme="well_balanced", blocks=(128, 192, 256, 320, 512),
     return out
 
 
+def two_step_tile(nx: int, ny: int, precision: str = "fp64", cus: int = 256, min_rows: int = 16,
+                  max_rows: int = 512):
+    """(block, rows, 4) for two steps per launch on an nx x ny lattice, or
+    None where one step per launch is the better choice.  The two-step
+    kernel runs one block per compute unit, so the tile count should fill
+    whole rounds of `cus` blocks: strips of block - 6 columns across x, and
+    chunks along y in a multiple of the blocks one round leaves per strip,
+    the fewest rounds that keep chunks at most `max_rows` tall.  Chunks
+    under `min_rows` rows (a lattice too small to fill the device) would
+    spend most of each block in the 12 lead-in rows: None.  For 4096^2 this
+    gives the measured best tiles, (256, 274, 4) in FP64 and (512, 147, 4)
+    in FP32-shifted storage."""
+    block = 512 if precision == "fp32s" else 256
+    strips = -(-nx // (block - 6))
+    per_round = max(1, cus // strips)
+    rounds = 1
+    while True:
+        rows = -(-ny // (per_round * rounds))
+        if rows <= max_rows:
+            break
+        rounds += 1
+    if rows < min_rows:
+        return None
+    return (block, rows, 4)
+
+
 def batch_bucket(nx: int, ny: int) -> str:
     return _bucket(nx, ny)
 
