@@ -107,7 +107,10 @@ def time_gpu(prob, precision, steps, warmup, scheme="well_balanced", fields=Fals
         "tile": list(tile),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_update": bpu / spl, "steps_per_launch": spl},
+                     "traffic": traffic, "bytes_per_update": bpu / spl, "steps_per_launch": spl,
+                     # the HBM rate a kernel moving every population once per step
+                     # would need for the same step rate (above `peak` when spl = 2)
+                     "one_step_traffic_gbs": round(bpu * nodes / (ms_step / 1e3) / 1e9, 1)},
         "state_after": {"step": ob["step"], "max_u": ob["max_u"], "nonfinite": ob["nonfinite"]},
         "observation": ob if fields else None,
         # the whole job through the host boundary: density in over PCIe, the
