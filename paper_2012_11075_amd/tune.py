@@ -226,6 +226,8 @@ def main():
     ap = argparse.ArgumentParser(description="tile autotuning on the current device")
     ap.add_argument("--batch", action="store_true", help="tune batch tiles per size bucket")
     ap.add_argument("--single", action="store_true", help="tune the 4096^2 lattice tile")
+    ap.add_argument("--two-step", action="store_true",
+                    help="tune the 4096^2 tile of two steps per launch (the benchmark's)")
     ap.add_argument("--write", action="store_true", help="store the result in tuned_tiles.json")
     ap.add_argument("--out", default=None, help="write the table here instead of tuned_tiles.json")
     args = ap.parse_args()
@@ -253,6 +255,36 @@ def main():
             for ms, bw, r, d in res[:5]:
                 print("single 4096", prec, bw, r, d, "%.4f ms/step" % ms, flush=True)
             table["4096/%s" % prec] = list(res[0][1:])
+    if args.two_step:
+        import torch
+        from . import lbm
+        prob = I.DROPLET_4096
+        for prec in ("fp64", "fp32s"):
+            block, base, _ = two_step_tile(prob.nx, prob.ny, prec)
+            strips = -(-prob.nx // (block - 6))
+            per_round = max(1, 256 // strips)
+            # chunk counts filling one round (and one less), two rounds, and
+            # the one-step tile for comparison
+            cands = sorted({-(-prob.ny // c) for c in (per_round, per_round - 1, 2 * per_round)})
+            s = lbm.Solver.for_problem(prob, precision=prec)
+            s.init(prob.rho(), scheme="well_balanced")
+            res = []
+            for tile in [(block, r, 4) for r in cands] + [(512, 128, 3)]:
+                s.set_tile(*tile)
+                s.step(50, "well_balanced")
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                s.step(200, "well_balanced")
+                e1.record()
+                torch.cuda.synchronize()
+                res.append((e0.elapsed_time(e1) / 200, tile))
+            s.close()
+            res.sort()
+            for ms, tile in res:
+                print("two-step 4096", prec, tile, "%.4f ms/step" % ms, flush=True)
+            table["4096/%s" % prec] = list(res[0][1])
     if args.write or args.out:
         with open(args.out or TABLE, "w") as fh:
             json.dump(table, fh, indent=1, sort_keys=True)
