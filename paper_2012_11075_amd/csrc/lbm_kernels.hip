@@ -1390,6 +1390,7 @@ hipError_t launch_step2_t(int scheme, const Geometry& g, const Physics& ph, int 
                           const void* fin, void* fout, hipStream_t s) {
   const int sw = BW - 6;
   const int strips = (g.nx + sw - 1) / sw, chunks = (g.ny + rows - 1) / rows;
+  if ((long long)strips * chunks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid(strips * chunks), block(BW);
   const T* in = (const T*)fin;
   T* out = (T*)fout;
