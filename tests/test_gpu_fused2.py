@@ -163,3 +163,26 @@ def test_two_step_full_grid_sampled(orc, lbm, prec):
         worst = max(worst, np.abs(got - want).max())
     print("%s two-step error on 4096^2 crops: %.3e" % (prec, worst))
     assert worst < (4e-6 if prec == "fp32s" else 1e-11)
+
+
+@pytest.mark.parametrize("prec", ["fp32s", "fp64"])
+def test_two_step_degenerate_shapes(lbm, prec):
+    """Lattices one node wide or tall and 2 x 2, where every pull and
+    stencil wraps onto the node itself or its one neighbour: two-step
+    launches equal one-step launches bit for bit."""
+    ph = I.PAPER_PHYS
+    rng = np.random.default_rng(17)
+    bw = BLOCK[prec]
+    for nx, ny in [(1, 1), (1, 7), (7, 1), (2, 2), (3, 5)]:
+        rho = 0.6 + 0.05 * rng.uniform(-1, 1, (ny, nx))
+        out = []
+        for depth in (3, 4):
+            s = lbm.Solver(nx, ny, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
+                           precision=prec)
+            s.set_tile(bw, 4, depth)
+            s.init(rho, scheme="well_balanced")
+            s.step(9, "well_balanced")
+            out.append(s.get_populations())
+            s.close()
+        print("two-step degenerate", prec, nx, ny, flush=True)
+        assert np.array_equal(out[0], out[1], equal_nan=True), (prec, nx, ny)
