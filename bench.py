@@ -126,7 +126,9 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
     together for `steps` steps of the WB scheme.  Slots retire only at the
     poll after the timed region, so every lattice is advanced every step;
     the poll's count of diverged lattices is split at tau = 0.8, below which
-    the WB step has a growing mode in bulk liquid."""
+    the WB step has a growing mode in bulk liquid.  Slots on two-step tiles
+    (depth 4 in the tuned table) advance two steps per launch; the rate
+    counts the algorithmic bytes of one step per node and step."""
     import torch
     from paper_2012_11075_amd import inputs as I
     from paper_2012_11075_amd import lbm, tune
@@ -138,12 +140,14 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
     b = lbm.Batch(arena, max_slots=count)
     b.set_graph_steps(graph_steps)
     tau_of = {}
+    two_step = 0
     for q, p in zip(prms, probs):
         sl = b.admit(q, p.rho(), "well_balanced")
         tau_of[sl] = p.physics.tau
         t = tune.batch_tile(p.nx, p.ny, precision)
         if t:
             b.set_tile(sl, *t)
+            two_step += t[2] == 4
     b.run(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -171,7 +175,7 @@ def time_batch(precision, steps, warmup, count=512, graph_steps=50):
             "instances": count, "total_nodes": nodes, "steps": steps,
             "ms_per_step": round(ms / steps, 5), "hbm_gbs_algorithmic": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_update": bpu,
-            "graph_steps": graph_steps,
+            "graph_steps": graph_steps, "two_step_slots": two_step,
             "retired_at_end": status,
             "active_at_end": count - len(retired)}
 

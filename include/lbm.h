@@ -326,7 +326,11 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
 /* Tile of a slot's kernels (as lbm_set_tile; block width 64, 128 or 256 and
  * depth 1, 2 or 3 for batches; the fourth-order force stencil's slots run
  * block width 256 only; 3-D slots block 256 (32 x 8 tiles), rows = planes
- * per chunk, depth 1 or 2). */
+ * per chunk, depth 1 or 2).  Depth 4 (2-D slots with the central stencil,
+ * block 512 in FP32-shifted storage or 256 in FP64): two steps per launch,
+ * as for a single lattice; lbm_batch_run(k) then launches such a slot k / 2
+ * times with two steps and, for an odd k, once with one step (depth 3), and
+ * its populations equal those of one-step launches bit for bit. */
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block_width, int32_t rows,
                               int32_t depth);
 

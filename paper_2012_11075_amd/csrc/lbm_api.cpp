@@ -900,14 +900,18 @@ namespace {
 constexpr int kBatchBlocks[3] = {64, 128, 256};
 // Launch groups: storage x scheme x block x depth for the main step, then
 // storage x scheme x depth for the force-stencil variant (block width
-// kBatch4Block), then storage x scheme x lattice (D3Q19, D3Q27) x depth
-// (1, 2) for 3-D lattices (tiles of 32 x kBatch3Ty).
+// kBatch4Block), then storage x scheme x {two steps per launch, one step}
+// for the slots of tile depth 4 (block width step2_block: each such slot is
+// in both tables, the one-step table serving the last step of an odd step
+// count and the observe pass), then storage x scheme x lattice (D3Q19,
+// D3Q27) x depth (1, 2) for 3-D lattices (tiles of 32 x kBatch3Ty).
 constexpr int kPlainGroups = 2 * 3 * 3 * 3;
 constexpr int kStencil4Base = kPlainGroups;
-constexpr int k3dBase = kStencil4Base + 2 * 3 * 3;
+constexpr int kPairBase = kStencil4Base + 2 * 3 * 3;
+constexpr int k3dBase = kPairBase + 2 * 3 * 2;
 constexpr int kGroups = k3dBase + 2 * 3 * 2 * 2;
 using GroupMask = std::bitset<kGroups>;
-enum GroupKind { kMain = 0, kStencil4 = 1, k3d = 2 };
+enum GroupKind { kMain = 0, kStencil4 = 1, k3d = 2, kPair = 3, kPairOne = 4 };
 // Each group's slots are split into two lanes (even and odd slot index), each
 // with its own table, launched on its own stream: the lanes hold disjoint
 // lattices, so one lane's next step fills the compute units that the other
@@ -957,10 +961,13 @@ struct lbm_batch {
   GroupMask active_mask[kLanes];            // per lane: groups with an active slot (launched)
   bool dirty = true;
   int graph_steps = 0;
-  hipGraphExec_t graph[kLanes] = {};
-  GroupMask graph_mask[kLanes];
-  int tiles_of[kLanes][kGroups] = {};     // work items (tiles) of each table, as uploaded
-  int graph_tiles[kLanes][kGroups] = {};  // the same when a lane's graph was captured
+  // per lane and parity of the two-step launches before the replay (a
+  // replay of graph_steps steps makes graph_steps / 2 of them: when that is
+  // odd, consecutive replays alternate between the two graphs)
+  hipGraphExec_t graph[kLanes][2] = {};
+  GroupMask graph_mask[kLanes][2];
+  int tiles_of[kLanes][kGroups] = {};        // work items (tiles) of each table, as uploaded
+  int graph_tiles[kLanes][2][kGroups] = {};  // the same when a graph was captured
   hipStream_t side = nullptr;             // the second lane's stream
   hipEvent_t fork = nullptr, join = nullptr;
   std::string err;
@@ -997,8 +1004,22 @@ int group_of(const lbm_ctx* c, int scheme) {
            (c->tl3.depth - 1);
   if (c->prm.force_stencil == 1)
     return kStencil4Base + (c->storage() * 3 + scheme) * 3 + (c->tl.depth - 1);
+  if (fused_pairs(c)) return kPairBase + (c->storage() * 3 + scheme) * 2;
   const int bi = block_index(c->tl.block);
   return ((c->storage() * 3 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
+}
+
+// Whether a slot's tiles are in the table of group g: its own group, and for
+// a slot of two-step launches also the one-step group after it.
+bool in_group(const lbm_ctx* c, int scheme, int g) {
+  const int own = group_of(c, scheme);
+  return g == own || (fused_pairs(c) && g == own + 1);
+}
+
+void mark_groups(lbm_batch* b, const lbm_ctx* c, int scheme) {
+  const int own = group_of(c, scheme);
+  b->group_mask.set(own);
+  if (fused_pairs(c)) b->group_mask.set(own + 1);
 }
 
 // Launch parameters of group g; q is the 3-D velocity count (0 in 2-D).
@@ -1017,6 +1038,12 @@ Group group_decode(int g) {
     d.q = g % 2 ? lbmk::Q27 : lbmk::Q3;
     g /= 2;
     d.block = lbmk::M3X * lbmk::kBatch3Ty;
+  } else if (g >= kPairBase) {
+    g -= kPairBase;
+    d.kind = g % 2 ? kPairOne : kPair;
+    d.depth = g % 2 ? 3 : 4;
+    g /= 2;
+    d.block = lbmk::step2_block(g / 3);
   } else if (g >= kStencil4Base) {
     g -= kStencil4Base;
     d.kind = kStencil4;
@@ -1111,11 +1138,12 @@ lbm_status upload_tables(lbm_batch* b) {
                                b->stream));
         continue;
       }
+      const GroupKind kind = group_decode(g).kind;
       auto* tab = (lbmk::BatchTable*)h.data();
       int n = 0, tiles = 0;
       for (size_t s = lane; s < b->slots.size(); s += kLanes) {
         lbm_batch::Slot& sl = b->slots[s];
-        if (sl.status != LBM_SLOT_ACTIVE || group_of(sl.ctx, sl.scheme) != g) continue;
+        if (sl.status != LBM_SLOT_ACTIVE || !in_group(sl.ctx, sl.scheme, g)) continue;
         lbm_ctx* c = sl.ctx;
         lbmk::BatchSlot& d = tab->slot[n++];
         d.g = c->L.g;
@@ -1125,6 +1153,14 @@ lbm_status upload_tables(lbm_batch* b) {
         d.buf[1] = c->buf(1);
         d.cur = c->cur;
         d.tile0 = tiles;
+        if (kind == kPair) {
+          // two-step strips of BW - 6 columns; no observe records
+          d.tl.strips = lbmk::step2_strips(c->L.g.nx, c->storage());
+          d.partials = nullptr;
+          tiles += d.tl.blocks();
+          continue;
+        }
+        if (kind == kPairOne) d.tl.depth = 3;
         d.partials = b->partials() + lbmk::NPART * (part + tiles);
         sl.part_index = part + tiles;
         sl.tiles = c->tl.blocks();
@@ -1134,7 +1170,7 @@ lbm_status upload_tables(lbm_batch* b) {
       tab->total_tiles = tiles;
       if (n > 0) active[lane].set(g);
       b->tiles_of[lane][g] = tiles;
-      part += tiles;
+      if (kind != kPair) part += tiles;
       if (part > b->part_cap)
         return bfail(b, LBM_ENOSPACE, "batch holds more tiles than its partials area");
       const size_t used =
@@ -1150,14 +1186,25 @@ lbm_status upload_tables(lbm_batch* b) {
   return LBM_OK;
 }
 
-// `steps` steps of one lane's groups on stream s.
-lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s) {
+// `steps` steps of one lane's groups on stream s.  Slots of two-step launches
+// get one launch at every even step with a step after it and a one-step
+// launch for the last step of an odd count; `pair0` is the parity of the
+// two-step launches made since the tables were uploaded (their buffers swap
+// once per launch).
+lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s, int pair0) {
   for (int j = 0; j < steps; ++j) {
     for (int g = 0; g < kGroups; ++g) {
       if (!b->active_mask[lane].test(g)) continue;
       const Group d = group_decode(g);
       const int tiles = b->tiles_of[lane][g];
-      if (d.kind == k3d)
+      if (d.kind == kPair || d.kind == kPairOne) {
+        const int par = ((j >> 1) + pair0) & 1;
+        if (d.kind == kPair && (j & 1) == 0 && j + 1 < steps)
+          BHIP(b, lbmk::launch_batch2(d.storage, d.scheme, b->dev_tab(g, lane), tiles, par, s));
+        else if (d.kind == kPairOne && (steps & 1) && j == steps - 1)
+          BHIP(b, lbmk::launch_batch(d.storage, d.scheme, d.block, d.depth, false,
+                                     b->dev_tab(g, lane), tiles, par, s));
+      } else if (d.kind == k3d)
         BHIP(b, lbmk::launch_batch3(d.storage, d.scheme, d.q, d.depth, b->dev_tab3(g, lane), tiles,
                                     j & 1, s));
       else if (d.kind == kStencil4)
@@ -1172,20 +1219,28 @@ lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s) {
 }
 
 void drop_batch_graph(lbm_batch* b) {
-  for (auto& g : b->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& lane : b->graph)
+    for (auto& g : lane)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
 }
 
-lbm_status batch_graph(lbm_batch* b, int lane, hipGraphExec_t* out) {
+// Whether a lane launches slots of two-step launches.
+bool lane_pairs(const lbm_batch* b, int lane) {
+  for (int g = kPairBase; g < k3dBase; g += 2)
+    if (b->active_mask[lane].test(g)) return true;
+  return false;
+}
+
+lbm_status batch_graph(lbm_batch* b, int lane, int pair0, hipGraphExec_t* out) {
   // a captured launch holds its group's grid (one block per tile), so a
   // lane's graph is re-captured when its launched groups or their tile
   // counts change
-  hipGraphExec_t& ge = b->graph[lane];
-  if (ge && b->graph_mask[lane] == b->active_mask[lane] &&
-      std::equal(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane])) {
+  hipGraphExec_t& ge = b->graph[lane][pair0];
+  if (ge && b->graph_mask[lane][pair0] == b->active_mask[lane] &&
+      std::equal(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane][pair0])) {
     *out = ge;
     return LBM_OK;
   }
@@ -1200,7 +1255,7 @@ lbm_status batch_graph(lbm_batch* b, int lane, hipGraphExec_t* out) {
     (void)hipStreamDestroy(cs);
     return bfail(b, LBM_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
-  lbm_status st = batch_launches(b, lane, b->graph_steps, cs);
+  lbm_status st = batch_launches(b, lane, b->graph_steps, cs, pair0);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);
@@ -1216,8 +1271,8 @@ lbm_status batch_graph(lbm_batch* b, int lane, hipGraphExec_t* out) {
     ge = nullptr;
     return bfail(b, LBM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
-  b->graph_mask[lane] = b->active_mask[lane];
-  std::copy(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane]);
+  b->graph_mask[lane][pair0] = b->active_mask[lane];
+  std::copy(b->tiles_of[lane], b->tiles_of[lane] + kGroups, b->graph_tiles[lane][pair0]);
   *out = ge;
   return LBM_OK;
 }
@@ -1337,7 +1392,7 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
   s.tol = tol;
   s.cap = cap;
   s.scheme = scheme;
-  b->group_mask.set(group_of(c, scheme));
+  mark_groups(b, c, scheme);
   b->dirty = true;
   *slot = idx;
   return LBM_OK;
@@ -1346,15 +1401,26 @@ lbm_status lbm_batch_admit(lbm_batch* b, const lbm_params* p, const double* rho,
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t rows, int32_t depth) {
   lbm_batch::Slot* s = slot_of(b, slot);
   if (!s) return bfail(b, LBM_EINVAL, "no such slot");
-  if (block != 0 && block_index(block) < 0) return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
-  if (block != 0 && s->ctx->prm.force_stencil == 1 && block != lbmk::kBatch4Block)
-    return bfail(b, LBM_EINVAL, "force-stencil slots run 256-wide blocks");
-  if (s->ctx->d3() && ((block != 0 && block != lbmk::M3X * lbmk::kBatch3Ty) || depth > 2))
-    return bfail(b, LBM_EINVAL, "3-D slots run 256-thread tiles (32 x 8) with depth 1 or 2");
-  if (depth < 0 || depth > 3) return bfail(b, LBM_EINVAL, "batch depth must be 1, 2 or 3");
+  const lbm_ctx* c = s->ctx;
+  if (depth == 4) {
+    // two steps per launch: the single lattice's rule
+    if (c->d3() || c->prm.force_stencil == 1 ||
+        (block ? block : c->tl.block) != lbmk::step2_block(c->storage()))
+      return bfail(b, LBM_EINVAL,
+                   "batch depth 4 (two steps per launch) needs a 2-D slot with the central "
+                   "stencil and block 512 (FP32-shifted) or 256 (FP64)");
+  } else {
+    if (block != 0 && block_index(block) < 0)
+      return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");
+    if (block != 0 && c->prm.force_stencil == 1 && block != lbmk::kBatch4Block)
+      return bfail(b, LBM_EINVAL, "force-stencil slots run 256-wide blocks");
+    if (c->d3() && ((block != 0 && block != lbmk::M3X * lbmk::kBatch3Ty) || depth > 2))
+      return bfail(b, LBM_EINVAL, "3-D slots run 256-thread tiles (32 x 8) with depth 1 or 2");
+    if (depth < 0 || depth > 3) return bfail(b, LBM_EINVAL, "batch depth must be 1, 2, 3 or 4");
+  }
   lbm_status st = lbm_set_tile(s->ctx, block, rows, depth);
   if (st != LBM_OK) return bfail(b, st, s->ctx->err);
-  b->group_mask.set(group_of(s->ctx, s->scheme));
+  mark_groups(b, s->ctx, s->scheme);
   b->dirty = true;
   return LBM_OK;
 }
@@ -1384,26 +1450,34 @@ lbm_status lbm_batch_run(lbm_batch* b, int32_t k) {
     if (b->active_mask[lane].none()) continue;
     hipStream_t ls = lane == 0 ? b->stream : b->side;
     int left = k;
+    int pair0 = 0;
     if (b->graph_steps >= 2) {
+      const int flip = lane_pairs(b, lane) ? (b->graph_steps / 2) & 1 : 0;
       while (left >= b->graph_steps) {
         hipGraphExec_t ge;
-        lbm_status st = batch_graph(b, lane, &ge);
+        lbm_status st = batch_graph(b, lane, pair0, &ge);
         if (st != LBM_OK) return st;
         BHIP(b, hipGraphLaunch(ge, ls));
         left -= b->graph_steps;
+        pair0 ^= flip;
       }
     }
-    lbm_status st = batch_launches(b, lane, left, ls);
+    lbm_status st = batch_launches(b, lane, left, ls, pair0);
     if (st != LBM_OK) return st;
   }
   BHIP(b, hipEventRecord(b->join, b->side));
   BHIP(b, hipStreamWaitEvent(b->stream, b->join, 0));
+  // launches per slot: k, or k / 2 two-step launches and one more for an odd
+  // k; each swaps the slot's buffers
+  const int pair_launches = k / 2 + (k & 1);
   for (auto& s : b->slots) {
     if (s.status != LBM_SLOT_ACTIVE) continue;
     s.ctx->step += k;
-    if (k & 1) s.ctx->cur ^= 1;
+    if ((fused_pairs(s.ctx) ? pair_launches : k) & 1) {
+      s.ctx->cur ^= 1;
+      b->dirty = true;
+    }
   }
-  if (k & 1) b->dirty = true;
   return LBM_OK;
 }
 
@@ -1422,9 +1496,10 @@ lbm_status lbm_batch_poll(lbm_batch* b, int32_t* retired, int32_t cap, int32_t* 
   std::vector<double> part(total * lbmk::NPART);
   if (total > 0) {
     for (int lane = 0; lane < kLanes; ++lane)
-      for (int g = 0; g < kPlainGroups; ++g) {
+      for (int g = 0; g < k3dBase; ++g) {
         if (!b->active_mask[lane].test(g)) continue;
         const Group d = group_decode(g);
+        if (d.kind != kMain && d.kind != kPairOne) continue;
         BHIP(b, lbmk::launch_batch(d.storage, d.scheme, d.block, d.depth, true,
                                    b->dev_tab(g, lane), b->tiles_of[lane][g], 0, b->stream));
       }

@@ -172,9 +172,22 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
                           hipStream_t s);
 
 // Batched step (or observe) of one launch group: one block per tile of the
-// table's `tiles` work items (the group's total_tiles).
+// table's `tiles` work items (the group's total_tiles).  Block widths 64, 128
+// and 256, and 512 in FP32-shifted storage (the one-step launches of slots
+// that otherwise run two steps per launch).
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
                         const BatchTable* tab, int tiles, int parity, hipStream_t s);
+
+// Two steps per launch of a launch group (central stencil, the kernel of
+// launch_step2): block width step2_block(storage), each slot's tiling holding
+// step2_strips / chunks of its rows; one block per tile, as launch_batch.
+constexpr int step2_block(int storage) { return storage == FP32 ? 512 : 256; }
+inline int step2_strips(int nx, int storage) {
+  const int w = step2_block(storage) - 6;
+  return (nx + w - 1) / w;
+}
+hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int tiles, int parity,
+                         hipStream_t s);
 
 // Batched step of a launch group of force-stencil slots (block width
 // kBatch4Block, depth 1..3): one block per tile, as launch_batch.  The

@@ -500,9 +500,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // evaluated by the same expressions as in the one-step kernel, so the result
 // is bit-identical to two launches of it.
 template <typename T, int SCHEME, int D, int BW>
-__global__ void __launch_bounds__(BW)
-    march2(Geometry g, Physics phys, int rows, int strips, int chunks, const T* __restrict__ fin_,
-           T* __restrict__ fout_) {
+__device__ __forceinline__ void march2_tile(Geometry g, Physics phys, int rows,
+                                            int strips, int tile, const T* __restrict__ fin_,
+                                            T* __restrict__ fout_) {
   constexpr int M2S = BW - 6;
   using R = T;
   const Global<T>* fin = (const Global<T>*)fin_;
@@ -518,7 +518,6 @@ __global__ void __launch_bounds__(BW)
     for (int b = 0; b < 3; ++b) mu3[a][b] = mb[a][b] = (R)0;
   const PhysR<R> p = to_r<R>(phys);
   const int t = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, strips * chunks);
   const int chunk = tile / strips;
   const int strip = tile - chunk * strips;
   const int x0 = strip * M2S, xa0 = x0 - 3;
@@ -737,6 +736,15 @@ __global__ void __launch_bounds__(BW)
   }
 }
 
+// One lattice, two steps: one block per tile of `strips` x `chunks`.
+template <typename T, int SCHEME, int D, int BW>
+__global__ void __launch_bounds__(BW)
+    march2(Geometry g, Physics phys, int rows, int strips, int chunks, const T* __restrict__ fin,
+           T* __restrict__ fout) {
+  march2_tile<T, SCHEME, D, BW>(g, phys, rows, strips, xcd_tile(blockIdx.x, strips * chunks), fin,
+                                fout);
+}
+
 // One lattice: one block per tile.
 template <typename T, int SCHEME, int BW, int D, bool OBSERVE>
 __global__ void __launch_bounds__(BW)
@@ -787,6 +795,23 @@ __global__ void __launch_bounds__(BW) march_batch(const BatchTable* __restrict__
   Global<T>* fout = (Global<T>*)(T*)sp->buf[which ^ 1];
   const ObserveOut o{nullptr, nullptr, nullptr, nullptr, sp->partials};
   march_tile<T, SCHEME, BW, D, OBSERVE>(g, ph, tl, item - sp->tile0, fin, fout, o);
+}
+
+// Two steps per launch over a batch: as march_batch, with each slot's tiling
+// holding the two-step strips (BW - 6 columns) and chunks; the state moves
+// from buffer `which` to the other one, two steps on.
+template <typename T, int SCHEME, int BW>
+__global__ void __launch_bounds__(BW) march2_batch(const BatchTable* __restrict__ tab, int parity) {
+  const int total = tab->total_tiles;
+  const int item = xcd_tile(blockIdx.x, total);
+  if (item >= total) return;
+  const BatchSlot* sp = &tab->slot[slot_of_item(tab, item)];
+  const Geometry g = sp->g;
+  const Physics ph = sp->ph;
+  const int rows = sp->tl.rows, strips = sp->tl.strips, tile = item - sp->tile0;
+  const int which = sp->cur ^ parity;
+  march2_tile<T, SCHEME, 3, BW>(g, ph, rows, strips, tile, (const T*)sp->buf[which],
+                                (T*)sp->buf[which ^ 1]);
 }
 
 // Offset, within a plane, of the slot the next pull reads population q of
@@ -1293,7 +1318,9 @@ const void* batch_fn() {
 }
 
 // Kernel of a batched group; null for unsupported combinations.  Batches use
-// block widths 64, 128 and 256 and depth 1, 2 or 3 (observe: depth 1).
+// block widths 64, 128 and 256 and depth 1, 2 or 3 (observe: depth 1), and
+// in FP32 storage block width 512 at depth 3 and for observing (the slots
+// that otherwise run two steps per launch).
 template <typename T, int SCHEME, bool OBS>
 const void* batch_kernel_t(int block, int depth) {
   if (depth == 1) {
@@ -1301,6 +1328,9 @@ const void* batch_kernel_t(int block, int depth) {
       case 64: return batch_fn<T, SCHEME, 64, 1, OBS>();
       case 128: return batch_fn<T, SCHEME, 128, 1, OBS>();
       case 256: return batch_fn<T, SCHEME, 256, 1, OBS>();
+      case 512:
+        if constexpr (sizeof(T) == 4) return batch_fn<T, SCHEME, 512, 1, OBS>();
+        break;
     }
   } else if (depth == 2 && !OBS) {
     switch (block) {
@@ -1313,6 +1343,9 @@ const void* batch_kernel_t(int block, int depth) {
       case 64: return batch_fn<T, SCHEME, 64, 3, OBS>();
       case 128: return batch_fn<T, SCHEME, 128, 3, OBS>();
       case 256: return batch_fn<T, SCHEME, 256, 3, OBS>();
+      case 512:
+        if constexpr (sizeof(T) == 4) return batch_fn<T, SCHEME, 512, 3, OBS>();
+        break;
     }
   }
   return nullptr;
@@ -1367,6 +1400,26 @@ hipError_t launch_batch4(int storage, int scheme, int depth, const BatchTable* t
   if (!fn || tiles <= 0) return hipErrorInvalidValue;
   void* args[] = {(void*)&tab, (void*)&parity};
   return hipLaunchKernel(fn, dim3(tiles), dim3(kBatch4Block), args, 0, s);
+}
+
+hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int tiles, int parity,
+                         hipStream_t s) {
+  if (tiles <= 0) return hipErrorInvalidValue;
+  const void* fn = nullptr;
+  if (storage == FP64) {
+    fn = scheme == STANDARD       ? (const void*)march2_batch<double, STANDARD, 256>
+         : scheme == STANDARD_EQF ? (const void*)march2_batch<double, STANDARD_EQF, 256>
+         : scheme == WELL_BALANCED ? (const void*)march2_batch<double, WELL_BALANCED, 256>
+                                   : nullptr;
+  } else {
+    fn = scheme == STANDARD       ? (const void*)march2_batch<float, STANDARD, 512>
+         : scheme == STANDARD_EQF ? (const void*)march2_batch<float, STANDARD_EQF, 512>
+         : scheme == WELL_BALANCED ? (const void*)march2_batch<float, WELL_BALANCED, 512>
+                                   : nullptr;
+  }
+  if (!fn) return hipErrorInvalidValue;
+  void* args[] = {(void*)&tab, (void*)&parity};
+  return hipLaunchKernel(fn, dim3(tiles), dim3(step2_block(storage)), args, 0, s);
 }
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,

@@ -153,8 +153,10 @@ def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64),
 
 
 def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64, 128),
-                    depths=(1, 2, 3), steps=20, passes=2):
-    """Tile per size bucket on the whole batch.  First every lattice gets the
+                    depths=(1, 2, 3), two_step_rows=(32, 64, 128, 256), steps=20, passes=2):
+    """Tile per size bucket on the whole batch; the candidates are the one-step
+    tiles (blocks x rows x depths) and the two-step tiles (depth 4, block 512
+    in FP32-shifted storage or 256 in FP64, chunks of `two_step_rows`).  First every lattice gets the
     same candidate tile (one launch group) and the fastest is kept; then
     coordinate descent over the buckets: for each bucket in turn, time the
     full batch under every candidate for that bucket's lattices (the others
@@ -190,6 +192,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
         return e0.elapsed_time(e1) / steps
 
     cands = [(bw, r, d) for bw in blocks for r in rows for d in depths]
+    cands += [(512 if precision == "fp32s" else 256, r, 4) for r in two_step_rows]
     uniform = []
     for cand in cands:
         for s in slots:
