@@ -310,8 +310,7 @@ void drop_graphs(lbm_ctx* c) {
 
 // Enqueue n plain step launches.
 // Tile depth 4 selects the two-step kernel (2-D lattices with the central
-// stencil, 512-thread blocks in FP32-shifted storage and 256 in FP64;
-// lbm_set_tile checks).
+// stencil, blocks of lbmk::kStep2Block threads; lbm_set_tile checks).
 bool fused_pairs(const lbm_ctx* c) { return !c->d3() && c->tl.depth == 4; }
 
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
@@ -821,10 +820,9 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
   if (depth == 4) {
-    if (c->prm.force_stencil != 0 || block != (c->prm.precision == LBM_FP32_SHIFTED ? 512 : 256))
+    if (c->prm.force_stencil != 0 || block != lbmk::kStep2Block)
       return fail(c, LBM_EINVAL,
-                  "depth 4 (two steps per launch) needs the central stencil and block 512 "
-                  "(FP32-shifted) or 256 (FP64)");
+                  "depth 4 (two steps per launch) needs the central stencil and block 256");
   } else if (depth < 1 || depth > 3) {
     return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3 (4: two steps per launch)");
   }
@@ -901,7 +899,7 @@ constexpr int kBatchBlocks[3] = {64, 128, 256};
 // Launch groups: storage x scheme x block x depth for the main step, then
 // storage x scheme x depth for the force-stencil variant (block width
 // kBatch4Block), then storage x scheme x {two steps per launch, one step}
-// for the slots of tile depth 4 (block width step2_block: each such slot is
+// for the slots of tile depth 4 (block width kStep2Block: each such slot is
 // in both tables, the one-step table serving the last step of an odd step
 // count and the observe pass), then storage x scheme x lattice (D3Q19,
 // D3Q27) x depth (1, 2) for 3-D lattices (tiles of 32 x kBatch3Ty).
@@ -1043,7 +1041,7 @@ Group group_decode(int g) {
     d.kind = g % 2 ? kPairOne : kPair;
     d.depth = g % 2 ? 3 : 4;
     g /= 2;
-    d.block = lbmk::step2_block(g / 3);
+    d.block = lbmk::kStep2Block;
   } else if (g >= kStencil4Base) {
     g -= kStencil4Base;
     d.kind = kStencil4;
@@ -1155,7 +1153,7 @@ lbm_status upload_tables(lbm_batch* b) {
         d.tile0 = tiles;
         if (kind == kPair) {
           // two-step strips of BW - 6 columns; no observe records
-          d.tl.strips = lbmk::step2_strips(c->L.g.nx, c->storage());
+          d.tl.strips = lbmk::step2_strips(c->L.g.nx);
           d.partials = nullptr;
           tiles += d.tl.blocks();
           continue;
@@ -1405,10 +1403,10 @@ lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t
   if (depth == 4) {
     // two steps per launch: the single lattice's rule
     if (c->d3() || c->prm.force_stencil == 1 ||
-        (block ? block : c->tl.block) != lbmk::step2_block(c->storage()))
+        (block ? block : c->tl.block) != lbmk::kStep2Block)
       return bfail(b, LBM_EINVAL,
                    "batch depth 4 (two steps per launch) needs a 2-D slot with the central "
-                   "stencil and block 512 (FP32-shifted) or 256 (FP64)");
+                   "stencil and block 256");
   } else {
     if (block != 0 && block_index(block) < 0)
       return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");

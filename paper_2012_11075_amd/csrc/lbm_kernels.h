@@ -134,8 +134,8 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
                        const Tiling& t, const void* fin, void* fout, hipStream_t s);
 
 // Two steps in one launch (central stencil): fin -> fout is the state two
-// steps on, bit-identical to two launch_step calls.  Blocks of 512 threads
-// (FP32) or 256 (FP64) write strips of 506 or 250 columns by `rows` rows.
+// steps on, bit-identical to two launch_step calls.  Blocks of kStep2Block
+// threads write strips of kStep2Block - 6 columns by `rows` rows.
 hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
                         const void* fin, void* fout, hipStream_t s);
 
@@ -173,17 +173,16 @@ hipError_t launch_reshift(int storage, const Geometry& g, const double* delta, v
 
 // Batched step (or observe) of one launch group: one block per tile of the
 // table's `tiles` work items (the group's total_tiles).  Block widths 64, 128
-// and 256, and 512 in FP32-shifted storage (the one-step launches of slots
-// that otherwise run two steps per launch).
+// and 256.
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
                         const BatchTable* tab, int tiles, int parity, hipStream_t s);
 
 // Two steps per launch of a launch group (central stencil, the kernel of
-// launch_step2): block width step2_block(storage), each slot's tiling holding
+// launch_step2): block width kStep2Block, each slot's tiling holding
 // step2_strips / chunks of its rows; one block per tile, as launch_batch.
-constexpr int step2_block(int storage) { return storage == FP32 ? 512 : 256; }
-inline int step2_strips(int nx, int storage) {
-  const int w = step2_block(storage) - 6;
+constexpr int kStep2Block = 256;
+inline int step2_strips(int nx) {
+  const int w = kStep2Block - 6;
   return (nx + w - 1) / w;
 }
 hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int tiles, int parity,

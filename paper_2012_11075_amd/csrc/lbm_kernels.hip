@@ -484,13 +484,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Two steps in one pass (temporal blocking): the step reads and writes each
-// population once per two steps instead of once per step.  A block of BW
-// threads (512 in FP32, 256 in FP64) runs the first step on BW consecutive
+// population once per two steps instead of once per step.  A block of BW = 256
+// threads runs the first step on BW consecutive
 // columns (xa0 .. xa0 + BW - 1, xa0 = x0 - 3) and keeps its output rows in
 // LDS; the second step reads them there and writes columns x0 .. x0 + BW - 7
 // of the state two steps on.  LDS: four first-step output rows of 9 x BW
-// values, both steps' rho rings and the first step's parked rows, 131 KB
-// either way (one block per CU).  The second step's node needs
+// values, both steps' rho rings and the first step's parked rows: 131 KB in
+// FP64 (one block per CU), 66 KB in FP32 (two blocks per CU).  The second step's node needs
 // first-step populations at x +- 3 (its pull, then rho at x +- 2 for mu and
 // the gradients), hence the 6 columns the first step computes in addition.
 // Along y the first step runs 3 rows ahead of the second step's chunk on each
@@ -1318,9 +1318,7 @@ const void* batch_fn() {
 }
 
 // Kernel of a batched group; null for unsupported combinations.  Batches use
-// block widths 64, 128 and 256 and depth 1, 2 or 3 (observe: depth 1), and
-// in FP32 storage block width 512 at depth 3 and for observing (the slots
-// that otherwise run two steps per launch).
+// block widths 64, 128 and 256 and depth 1, 2 or 3 (observe: depth 1).
 template <typename T, int SCHEME, bool OBS>
 const void* batch_kernel_t(int block, int depth) {
   if (depth == 1) {
@@ -1328,9 +1326,6 @@ const void* batch_kernel_t(int block, int depth) {
       case 64: return batch_fn<T, SCHEME, 64, 1, OBS>();
       case 128: return batch_fn<T, SCHEME, 128, 1, OBS>();
       case 256: return batch_fn<T, SCHEME, 256, 1, OBS>();
-      case 512:
-        if constexpr (sizeof(T) == 4) return batch_fn<T, SCHEME, 512, 1, OBS>();
-        break;
     }
   } else if (depth == 2 && !OBS) {
     switch (block) {
@@ -1343,9 +1338,6 @@ const void* batch_kernel_t(int block, int depth) {
       case 64: return batch_fn<T, SCHEME, 64, 3, OBS>();
       case 128: return batch_fn<T, SCHEME, 128, 3, OBS>();
       case 256: return batch_fn<T, SCHEME, 256, 3, OBS>();
-      case 512:
-        if constexpr (sizeof(T) == 4) return batch_fn<T, SCHEME, 512, 3, OBS>();
-        break;
     }
   }
   return nullptr;
@@ -1406,20 +1398,21 @@ hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int til
                          hipStream_t s) {
   if (tiles <= 0) return hipErrorInvalidValue;
   const void* fn = nullptr;
+  constexpr int B = kStep2Block;
   if (storage == FP64) {
-    fn = scheme == STANDARD       ? (const void*)march2_batch<double, STANDARD, 256>
-         : scheme == STANDARD_EQF ? (const void*)march2_batch<double, STANDARD_EQF, 256>
-         : scheme == WELL_BALANCED ? (const void*)march2_batch<double, WELL_BALANCED, 256>
+    fn = scheme == STANDARD       ? (const void*)march2_batch<double, STANDARD, B>
+         : scheme == STANDARD_EQF ? (const void*)march2_batch<double, STANDARD_EQF, B>
+         : scheme == WELL_BALANCED ? (const void*)march2_batch<double, WELL_BALANCED, B>
                                    : nullptr;
   } else {
-    fn = scheme == STANDARD       ? (const void*)march2_batch<float, STANDARD, 512>
-         : scheme == STANDARD_EQF ? (const void*)march2_batch<float, STANDARD_EQF, 512>
-         : scheme == WELL_BALANCED ? (const void*)march2_batch<float, WELL_BALANCED, 512>
+    fn = scheme == STANDARD       ? (const void*)march2_batch<float, STANDARD, B>
+         : scheme == STANDARD_EQF ? (const void*)march2_batch<float, STANDARD_EQF, B>
+         : scheme == WELL_BALANCED ? (const void*)march2_batch<float, WELL_BALANCED, B>
                                    : nullptr;
   }
   if (!fn) return hipErrorInvalidValue;
   void* args[] = {(void*)&tab, (void*)&parity};
-  return hipLaunchKernel(fn, dim3(tiles), dim3(step2_block(storage)), args, 0, s);
+  return hipLaunchKernel(fn, dim3(tiles), dim3(B), args, 0, s);
 }
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
@@ -1463,8 +1456,8 @@ hipError_t launch_step2_t(int scheme, const Geometry& g, const Physics& ph, int 
 hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
                         const void* fin, void* fout, hipStream_t s) {
   if (rows < 1) return hipErrorInvalidValue;
-  return storage == FP32 ? launch_step2_t<float, 512>(scheme, g, ph, rows, fin, fout, s)
-                         : launch_step2_t<double, 256>(scheme, g, ph, rows, fin, fout, s);
+  return storage == FP32 ? launch_step2_t<float, kStep2Block>(scheme, g, ph, rows, fin, fout, s)
+                         : launch_step2_t<double, kStep2Block>(scheme, g, ph, rows, fin, fout, s);
 }
 
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,

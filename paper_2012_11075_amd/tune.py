@@ -60,24 +60,30 @@ def two_step_tile(nx: int, ny: int, precision: str = "fp64", cus: int = 256, min
                   max_rows: int = 512):
     """(block, rows, 4) for two steps per launch on an nx x ny lattice, or
     None where one step per launch is the better choice.  The two-step
-    kernel runs one block per compute unit, so the tile count should fill
-    whole rounds of `cus` blocks: strips of block - 6 columns across x, and
-    chunks along y in a multiple of the blocks one round leaves per strip,
-    the fewest rounds that keep chunks at most `max_rows` tall.  Chunks
-    under `min_rows` rows (a lattice too small to fill the device) would
-    spend most of each block in the 12 lead-in rows: None.  For 4096^2 this
-    gives the measured best tiles, (256, 274, 4) in FP64 and (512, 147, 4)
-    in FP32-shifted storage."""
-    block = 512 if precision == "fp32s" else 256
+    kernel (256-thread blocks) runs one block per compute unit in FP64 and
+    two in FP32-shifted storage (its LDS is half as large), so the tile
+    count should fill whole rounds of those blocks: strips of 250 columns
+    across x and, for the fewest rounds that keep chunks at most `max_rows`
+    tall and the rounds at least 90% full, the most chunks whose tiles fit
+    in them.  Chunks under `min_rows` rows (a lattice too small to fill the
+    device) would spend most of each block in the 12 lead-in rows: None.
+    For 4096^2 this gives the measured best tiles, (256, 274, 4) in FP64
+    and (256, 137, 4) in FP32-shifted storage."""
+    block = 256
     strips = -(-nx // (block - 6))
-    per_round = max(1, cus // strips)
-    rounds = 1
-    while True:
-        rows = -(-ny // (per_round * rounds))
-        if rows <= max_rows:
+    resident = cus * (2 if precision == "fp32s" else 1)
+    c_min = -(-ny // max_rows)
+    first = -(-strips * c_min // resident)
+    rows = None
+    for rounds in range(first, first + 64):
+        c = (rounds * resident) // strips
+        if c < c_min:
+            continue
+        rows = -(-ny // c)
+        chunks = -(-ny // rows)
+        if strips * chunks >= 0.9 * rounds * resident:
             break
-        rounds += 1
-    if rows < min_rows:
+    if rows is None or rows < min_rows:
         return None
     return (block, rows, 4)
 
@@ -155,8 +161,8 @@ def tune_batch(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64),
 def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32, 64, 128),
                     depths=(1, 2, 3), two_step_rows=(32, 64, 128, 256), steps=20, passes=2):
     """Tile per size bucket on the whole batch; the candidates are the one-step
-    tiles (blocks x rows x depths) and the two-step tiles (depth 4, block 512
-    in FP32-shifted storage or 256 in FP64, chunks of `two_step_rows`).  First every lattice gets the
+    tiles (blocks x rows x depths) and the two-step tiles (depth 4, block
+    256, chunks of `two_step_rows`).  First every lattice gets the
     same candidate tile (one launch group) and the fastest is kept; then
     coordinate descent over the buckets: for each bucket in turn, time the
     full batch under every candidate for that bucket's lattices (the others
@@ -192,7 +198,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
         return e0.elapsed_time(e1) / steps
 
     cands = [(bw, r, d) for bw in blocks for r in rows for d in depths]
-    cands += [(512 if precision == "fp32s" else 256, r, 4) for r in two_step_rows]
+    cands += [(256, r, 4) for r in two_step_rows]
     uniform = []
     for cand in cands:
         for s in slots:
@@ -265,7 +271,8 @@ def main():
         for prec in ("fp64", "fp32s"):
             block, base, _ = two_step_tile(prob.nx, prob.ny, prec)
             strips = -(-prob.nx // (block - 6))
-            per_round = max(1, 256 // strips)
+            # resident blocks: one per CU in FP64, two in FP32-shifted storage
+            per_round = max(1, (512 if prec == "fp32s" else 256) // strips)
             # chunk counts filling one round (and one less), two rounds, and
             # the one-step tile for comparison
             cands = sorted({-(-prob.ny // c) for c in (per_round, per_round - 1, 2 * per_round)})

@@ -13,7 +13,7 @@ from paper_2012_11075_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 SCHEMES = ["well_balanced", "standard", "standard_eq_forcing"]
-BLOCK = {"fp32s": 512, "fp64": 256}
+BLOCK = {"fp32s": 256, "fp64": 256}
 
 
 @pytest.fixture(scope="module")
@@ -86,8 +86,8 @@ def test_batch_two_step_bit_exact(lbm, graph_steps):
 
 def test_batch_two_step_poll_observations(lbm):
     """The poll observes slots of two-step tiles with the one-step table's
-    batched observe launch (block 512 in FP32-shifted storage): its
-    per-slot scalars agree with the single-lattice observe of fetch."""
+    batched observe launch: its per-slot scalars agree with the
+    single-lattice observe of fetch."""
     cs = cases()
     b, slots = make_batch(lbm, cs, 8)
     b.run(35)
@@ -108,8 +108,8 @@ def test_batch_two_step_poll_observations(lbm):
 
 
 def test_batch_two_step_tile_rules_and_switch(lbm):
-    """Depth 4 needs a 2-D central-stencil slot and block 512 (FP32-shifted)
-    or 256 (FP64); block 512 is refused for one-step tiles.  A slot switched
+    """Depth 4 needs a 2-D central-stencil slot and block 256; block 512 is
+    refused for batched tiles of any depth.  A slot switched
     between two-step and one-step tiles between runs stays bit-identical
     to its run alone."""
     L = lbm
@@ -122,14 +122,14 @@ def test_batch_two_step_tile_rules_and_switch(lbm):
     ph = p.physics
     s4 = b.admit(L.make_params(64, 40, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
                                force_stencil=1), I.with_size(I.PAPER_DROPLET, 64, 40).rho())
-    for sl, bad in [(s64, (512, 16, 4)), (s64, (128, 16, 4)), (s32, (256, 16, 4)),
-                    (s32, (512, 16, 3)), (s4, (256, 16, 4))]:
+    for sl, bad in [(s64, (512, 16, 4)), (s64, (128, 16, 4)), (s32, (512, 16, 4)),
+                    (s32, (512, 16, 3)), (s32, (64, 16, 4)), (s4, (256, 16, 4))]:
         with pytest.raises(L.LbmError):
             b.set_tile(sl, *bad)
     b.release(s4)
     b.set_graph_steps(6)
     b.set_tile(s64, 256, 24, 4)
-    b.set_tile(s32, 512, 8, 4)
+    b.set_tile(s32, 256, 8, 4)
     b.run(17)
     b.set_tile(s64, 256, 16, 3)
     b.run(9)

@@ -1,6 +1,5 @@
 """Two steps per launch (tile depth 4: 2-D lattices, central force stencil,
-512-thread blocks in FP32-shifted storage and 256 in FP64) through the C
-ABI.  Each launch runs the first step into LDS and the second step from
+256-thread blocks, in FP64 and FP32-shifted storage) through the C ABI.  Each launch runs the first step into LDS and the second step from
 there (temporal blocking), so the populations must equal those of one-step
 launches bit for bit: for every scheme, ragged and tiny lattices, odd step
 counts (which end with one one-step launch), graph replays whose launch
@@ -25,7 +24,7 @@ def lbm():
     return L
 
 
-BLOCK = {"fp32s": 512, "fp64": 256}
+BLOCK = {"fp32s": 256, "fp64": 256}
 
 
 def run(L, prob, scheme, tile, steps, graph_steps=0, split=3, precision="fp32s"):
@@ -44,12 +43,13 @@ def run(L, prob, scheme, tile, steps, graph_steps=0, split=3, precision="fp32s")
 
 
 # (precision, nx, ny, rows, steps, graph steps): one strip and several,
-# strips that end ragged or exactly at the strip width (506 columns in FP32,
-# 250 in FP64), lattices narrower than the first step's columns and shorter
+# strips that end ragged or exactly at the strip width (250 columns),
+# lattices narrower than the first step's columns and shorter
 # than a chunk, graphs of 4 (even launch count) and of 6 and 10 steps (odd
 # launch count)
 CASES = [("fp32s", 700, 300, 128, 40, 0), ("fp32s", 1100, 90, 32, 23, 0),
-         ("fp32s", 505, 37, 16, 31, 0), ("fp32s", 506, 50, 8, 20, 0), ("fp32s", 507, 12, 4, 9, 0),
+         ("fp32s", 249, 37, 16, 31, 0), ("fp32s", 250, 50, 8, 20, 0), ("fp32s", 251, 12, 4, 9, 0),
+         ("fp32s", 501, 21, 8, 11, 0),
          ("fp32s", 5, 3, 4, 14, 0), ("fp32s", 33, 130, 64, 40, 10), ("fp32s", 600, 200, 96, 44, 4),
          ("fp32s", 250, 61, 20, 30, 6),
          ("fp64", 700, 300, 128, 40, 0), ("fp64", 1100, 90, 32, 23, 0), ("fp64", 249, 37, 16, 31, 0),
@@ -76,8 +76,7 @@ def test_two_step_launch_bit_identical(lbm, case):
 @pytest.mark.parametrize("prec", ["fp32s", "fp64"])
 def test_two_step_tile_rules(lbm, prec):
     """Depth 4 is accepted only for 2-D lattices with the central stencil
-    and 512-thread blocks (FP32-shifted) or 256 (FP64); the refused calls
-    leave the tile as it was."""
+    and 256-thread blocks; the refused calls leave the tile as it was."""
     L = lbm
     prob = I.with_size(I.PAPER_DROPLET, 96, 64)
     ph = prob.physics
@@ -85,7 +84,7 @@ def test_two_step_tile_rules(lbm, prec):
     s = L.Solver.for_problem(prob, precision=prec)
     s.set_tile(bw, 32, 4)
     assert s.get_tile() == (bw, 32, 4) and s.lib.lbm_steps_per_launch(s.ctx) == 2
-    for bad in [(768 - bw, 32, 4), (128, 32, 4), (bw, 32, 5)]:
+    for bad in [(512, 32, 4), (128, 32, 4), (bw, 32, 5)]:
         with pytest.raises(L.LbmError):
             s.set_tile(*bad)
     assert s.get_tile() == (bw, 32, 4)
@@ -131,7 +130,7 @@ def test_two_step_full_grid_sampled(orc, lbm, prec):
     """The benchmark's 4096^2 launch configurations (two steps per launch):
     after 20 steps, one more launch against two steps of the FP64 oracle
     from the same populations on periodic crops around sampled windows,
-    including the seams of the strips (506 columns in FP32, 250 in FP64).
+    including the seams of the 250-column strips.
     FP64: 1e-11.  FP32: two steps add single-precision rounding of O(1)
     populations twice; the bound is 4e-6."""
     from paper_2012_11075_amd import tune
