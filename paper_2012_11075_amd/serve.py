@@ -72,7 +72,8 @@ class BatchExecutor:
         if slot is not None and self.tiles is not None and not getattr(req.problem, "nz", 0):
             tile = self.tiles(req.problem.nx, req.problem.ny, req.precision)
             if tile and getattr(req, "force_stencil", 0):
-                tile = (0,) + tuple(tile[1:])   # the variant keeps its 256-wide blocks
+                # the variant keeps its 256-wide blocks and one step per launch
+                tile = (0, tile[1], min(tile[2], 3))
             if tile:
                 self.batch.set_tile(slot, *tile)
         return slot

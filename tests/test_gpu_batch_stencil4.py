@@ -100,15 +100,20 @@ def test_stencil4_slot_tile_width(lbm):
     b.close()
 
 
-def test_served_stencil4_requests_equal_alone(lbm):
+@pytest.mark.parametrize("tuned", [False, True])
+def test_served_stencil4_requests_equal_alone(lbm, tuned):
     """A served stream in which every third request uses the fourth-order
-    force stencil: each result equals the same request run alone."""
+    force stencil: each result equals the same request run alone, with the
+    default tiles and with the served stream's table (whose two-step FP32
+    tiles the variant's requests take at one step per launch)."""
     from dataclasses import replace
+    from paper_2012_11075_amd import tune
     from paper_2012_11075_amd.serve import BatchExecutor, Server
     reqs = I.request_stream(9, rate_hz=400.0, seed=41, side_lo=32, side_hi=200, step_cap=400,
                             fp64_fraction=0.5)
     reqs = [replace(r, force_stencil=1) if r.rid % 3 == 1 else r for r in reqs]
-    ex = BatchExecutor(int(2e9), max_slots=16, graph_steps=10, capture=True)
+    ex = BatchExecutor(int(2e9), max_slots=16, graph_steps=10, capture=True,
+                       tiles=(lambda nx, ny, prec: tune.serve_tile(nx, ny, prec)) if tuned else None)
     srv = Server(ex, k=100)
     out = srv.serve(reqs)
     ex.close()

@@ -9,7 +9,17 @@ from paper_2012_11075_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone():
+def served_tiles(kind):
+    """None: the library's default tiles; "tuned": the served stream's table
+    (two steps per launch for FP32-shifted requests)."""
+    if kind is None:
+        return None
+    from paper_2012_11075_amd import tune
+    return lambda nx, ny, prec: tune.serve_tile(nx, ny, prec)
+
+
+@pytest.mark.parametrize("tiles", [None, "tuned"])
+def test_served_results_equal_alone(tiles):
     import torch
     assert torch.cuda.is_available()
     from paper_2012_11075_amd import lbm
@@ -30,7 +40,8 @@ def test_served_results_equal_alone():
         precision=r.precision)) for r in reqs), reverse=True)
     arena = sum(sizes[:3]) + lbm.Batch.overhead_bytes(1 << 26, 16)
     assert sum(sizes) > sum(sizes[:3])
-    ex = BatchExecutor(arena, max_slots=16, graph_steps=20, capture=True)
+    ex = BatchExecutor(arena, max_slots=16, graph_steps=20, capture=True,
+                       tiles=served_tiles(tiles))
     srv = Server(ex, k=100)
     out = srv.serve(reqs)
     ex.close()
@@ -56,11 +67,13 @@ def test_served_results_equal_alone():
             assert o.steps >= req.step_cap
 
 
-def test_served_large_sides_equal_alone():
+@pytest.mark.parametrize("tiles", [None, "tuned"])
+def test_served_large_sides_equal_alone(tiles):
     """The served size range reaches 2048: requests with sides of 1024 and
     more, in FP64 and in FP32-shifted storage, served together for 300 steps
     (tolerance never met, so each retires at its cap), give the populations
-    of the same request run alone, bit for bit."""
+    of the same request run alone, bit for bit, with the default tiles and
+    with the served stream's table."""
     import torch
     assert torch.cuda.is_available()
     from paper_2012_11075_amd import lbm
@@ -70,7 +83,8 @@ def test_served_large_sides_equal_alone():
     big = [r for r in reqs if r.problem.nx >= 1024]
     assert {r.precision for r in big} == {"fp64", "fp32s"}, [(r.problem.nx, r.precision) for r in reqs]
     print("served sides", [(r.problem.nx, r.precision) for r in reqs], flush=True)
-    ex = BatchExecutor(int(12e9), max_slots=16, graph_steps=20, capture=True)
+    ex = BatchExecutor(int(12e9), max_slots=16, graph_steps=20, capture=True,
+                       tiles=served_tiles(tiles))
     srv = Server(ex, k=100)
     out = srv.serve(reqs)
     ex.close()
