@@ -223,8 +223,8 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const double* f, lbm_scheme scheme,
  * 256 threads, 1..2 with 512; D3Q27: 256 threads, depth 1..2; 1 is the
  * fastest measured).  Any valid shape gives
  * bit-identical populations.
- * Depth 4 (2-D, central force stencil; block width 256, else LBM_EINVAL)
- * selects two steps per launch:
+ * Depth 4 (2-D, central force stencil; block width 128 or 256, else
+ * LBM_EINVAL) selects two steps per launch:
  * each launch reads and writes the populations once and advances the state
  * two steps (bit-identical to two one-step launches); blocks write strips
  * of block width - 6 columns by `rows` rows, and an odd step count ends
@@ -327,7 +327,7 @@ lbm_status lbm_batch_get_populations(lbm_batch* b, int32_t slot, double* f);
  * depth 1, 2 or 3 for batches; the fourth-order force stencil's slots run
  * block width 256 only; 3-D slots block 256 (32 x 8 tiles), rows = planes
  * per chunk, depth 1 or 2).  Depth 4 (2-D slots with the central stencil,
- * block 256): two steps per launch,
+ * block 128 or 256): two steps per launch,
  * as for a single lattice; lbm_batch_run(k) then launches such a slot k / 2
  * times with two steps and, for an odd k, once with one step (depth 3), and
  * its populations equal those of one-step launches bit for bit. */

@@ -310,7 +310,7 @@ void drop_graphs(lbm_ctx* c) {
 
 // Enqueue n plain step launches.
 // Tile depth 4 selects the two-step kernel (2-D lattices with the central
-// stencil, blocks of lbmk::kStep2Block threads; lbm_set_tile checks).
+// stencil, blocks of 128 or 256 threads; lbm_set_tile checks).
 bool fused_pairs(const lbm_ctx* c) { return !c->d3() && c->tl.depth == 4; }
 
 lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
@@ -320,8 +320,8 @@ lbm_status launch_steps(lbm_ctx* c, int64_t n, int scheme, hipStream_t s) {
     // two steps per launch; an odd count ends with one step of the same tile
     int64_t k = 0;
     for (; k + 2 <= n; k += 2) {
-      HIPCHK(c, lbmk::launch_step2(c->storage(), scheme, c->L.g, ph, c->tl.rows, c->buf(c->cur),
-                                   c->buf(1 - c->cur), s));
+      HIPCHK(c, lbmk::launch_step2(c->storage(), scheme, c->tl.block, c->L.g, ph, c->tl.rows,
+                                   c->buf(c->cur), c->buf(1 - c->cur), s));
       c->cur = 1 - c->cur;
     }
     if (k < n) {
@@ -820,9 +820,10 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t block, int32_t rows, int32_t depth) 
   if (rows == 0) rows = c->tl.rows;
   if (depth == 0) depth = c->tl.depth;
   if (depth == 4) {
-    if (c->prm.force_stencil != 0 || block != lbmk::kStep2Block)
+    if (c->prm.force_stencil != 0 || !lbmk::step2_block_supported(block))
       return fail(c, LBM_EINVAL,
-                  "depth 4 (two steps per launch) needs the central stencil and block 256");
+                  "depth 4 (two steps per launch) needs the central stencil and block 128 or "
+                  "256");
   } else if (depth < 1 || depth > 3) {
     return fail(c, LBM_EINVAL, "depth must be 1, 2 or 3 (4: two steps per launch)");
   }
@@ -898,15 +899,15 @@ namespace {
 constexpr int kBatchBlocks[3] = {64, 128, 256};
 // Launch groups: storage x scheme x block x depth for the main step, then
 // storage x scheme x depth for the force-stencil variant (block width
-// kBatch4Block), then storage x scheme x {two steps per launch, one step}
-// for the slots of tile depth 4 (block width kStep2Block: each such slot is
-// in both tables, the one-step table serving the last step of an odd step
-// count and the observe pass), then storage x scheme x lattice (D3Q19,
+// kBatch4Block), then storage x scheme x block width (128, 256) x {two steps
+// per launch, one step} for the slots of tile depth 4 (each such slot is in
+// both tables, the one-step table serving the last step of an odd step count
+// and the observe pass), then storage x scheme x lattice (D3Q19,
 // D3Q27) x depth (1, 2) for 3-D lattices (tiles of 32 x kBatch3Ty).
 constexpr int kPlainGroups = 2 * 3 * 3 * 3;
 constexpr int kStencil4Base = kPlainGroups;
 constexpr int kPairBase = kStencil4Base + 2 * 3 * 3;
-constexpr int k3dBase = kPairBase + 2 * 3 * 2;
+constexpr int k3dBase = kPairBase + 2 * 3 * 2 * 2;
 constexpr int kGroups = k3dBase + 2 * 3 * 2 * 2;
 using GroupMask = std::bitset<kGroups>;
 enum GroupKind { kMain = 0, kStencil4 = 1, k3d = 2, kPair = 3, kPairOne = 4 };
@@ -1002,7 +1003,8 @@ int group_of(const lbm_ctx* c, int scheme) {
            (c->tl3.depth - 1);
   if (c->prm.force_stencil == 1)
     return kStencil4Base + (c->storage() * 3 + scheme) * 3 + (c->tl.depth - 1);
-  if (fused_pairs(c)) return kPairBase + (c->storage() * 3 + scheme) * 2;
+  if (fused_pairs(c))
+    return kPairBase + ((c->storage() * 3 + scheme) * 2 + (c->tl.block == 256 ? 1 : 0)) * 2;
   const int bi = block_index(c->tl.block);
   return ((c->storage() * 3 + scheme) * 3 + bi) * 3 + (c->tl.depth - 1);
 }
@@ -1041,7 +1043,8 @@ Group group_decode(int g) {
     d.kind = g % 2 ? kPairOne : kPair;
     d.depth = g % 2 ? 3 : 4;
     g /= 2;
-    d.block = lbmk::kStep2Block;
+    d.block = g % 2 ? 256 : 128;
+    g /= 2;
   } else if (g >= kStencil4Base) {
     g -= kStencil4Base;
     d.kind = kStencil4;
@@ -1153,7 +1156,7 @@ lbm_status upload_tables(lbm_batch* b) {
         d.tile0 = tiles;
         if (kind == kPair) {
           // two-step strips of BW - 6 columns; no observe records
-          d.tl.strips = lbmk::step2_strips(c->L.g.nx);
+          d.tl.strips = lbmk::step2_strips(c->L.g.nx, c->tl.block);
           d.partials = nullptr;
           tiles += d.tl.blocks();
           continue;
@@ -1198,7 +1201,8 @@ lbm_status batch_launches(lbm_batch* b, int lane, int steps, hipStream_t s, int 
       if (d.kind == kPair || d.kind == kPairOne) {
         const int par = ((j >> 1) + pair0) & 1;
         if (d.kind == kPair && (j & 1) == 0 && j + 1 < steps)
-          BHIP(b, lbmk::launch_batch2(d.storage, d.scheme, b->dev_tab(g, lane), tiles, par, s));
+          BHIP(b, lbmk::launch_batch2(d.storage, d.scheme, d.block, b->dev_tab(g, lane), tiles, par,
+                                      s));
         else if (d.kind == kPairOne && (steps & 1) && j == steps - 1)
           BHIP(b, lbmk::launch_batch(d.storage, d.scheme, d.block, d.depth, false,
                                      b->dev_tab(g, lane), tiles, par, s));
@@ -1403,10 +1407,10 @@ lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t slot, int32_t block, int32_t
   if (depth == 4) {
     // two steps per launch: the single lattice's rule
     if (c->d3() || c->prm.force_stencil == 1 ||
-        (block ? block : c->tl.block) != lbmk::kStep2Block)
+        !lbmk::step2_block_supported(block ? block : c->tl.block))
       return bfail(b, LBM_EINVAL,
                    "batch depth 4 (two steps per launch) needs a 2-D slot with the central "
-                   "stencil and block 256");
+                   "stencil and block 128 or 256");
   } else {
     if (block != 0 && block_index(block) < 0)
       return bfail(b, LBM_EINVAL, "batch block width must be 64, 128 or 256");

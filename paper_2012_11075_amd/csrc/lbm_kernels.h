@@ -134,10 +134,12 @@ hipError_t launch_step(int storage, int scheme, const Geometry& g, const Physics
                        const Tiling& t, const void* fin, void* fout, hipStream_t s);
 
 // Two steps in one launch (central stencil): fin -> fout is the state two
-// steps on, bit-identical to two launch_step calls.  Blocks of kStep2Block
-// threads write strips of kStep2Block - 6 columns by `rows` rows.
-hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
-                        const void* fin, void* fout, hipStream_t s);
+// steps on, bit-identical to two launch_step calls.  Blocks of `block`
+// threads (step2_block_supported) write strips of block - 6 columns by `rows`
+// rows.
+constexpr bool step2_block_supported(int block) { return block == 128 || block == 256; }
+hipError_t launch_step2(int storage, int scheme, int block, const Geometry& g, const Physics& ph,
+                        int rows, const void* fin, void* fout, hipStream_t s);
 
 // Fields and per-block reduction partials of the state f.
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,
@@ -178,15 +180,14 @@ hipError_t launch_batch(int storage, int scheme, int block, int depth, bool obse
                         const BatchTable* tab, int tiles, int parity, hipStream_t s);
 
 // Two steps per launch of a launch group (central stencil, the kernel of
-// launch_step2): block width kStep2Block, each slot's tiling holding
+// launch_step2, block width 128 or 256), each slot's tiling holding
 // step2_strips / chunks of its rows; one block per tile, as launch_batch.
-constexpr int kStep2Block = 256;
-inline int step2_strips(int nx) {
-  const int w = kStep2Block - 6;
+inline int step2_strips(int nx, int block) {
+  const int w = block - 6;
   return (nx + w - 1) / w;
 }
-hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int tiles, int parity,
-                         hipStream_t s);
+hipError_t launch_batch2(int storage, int scheme, int block, const BatchTable* tab, int tiles,
+                         int parity, hipStream_t s);
 
 // Batched step of a launch group of force-stencil slots (block width
 // kBatch4Block, depth 1..3): one block per tile, as launch_batch.  The

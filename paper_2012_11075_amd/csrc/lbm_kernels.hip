@@ -484,13 +484,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Two steps in one pass (temporal blocking): the step reads and writes each
-// population once per two steps instead of once per step.  A block of BW = 256
-// threads runs the first step on BW consecutive
+// population once per two steps instead of once per step.  A block of BW
+// threads (128 or 256) runs the first step on BW consecutive
 // columns (xa0 .. xa0 + BW - 1, xa0 = x0 - 3) and keeps its output rows in
 // LDS; the second step reads them there and writes columns x0 .. x0 + BW - 7
 // of the state two steps on.  LDS: four first-step output rows of 9 x BW
-// values, both steps' rho rings and the first step's parked rows: 131 KB in
-// FP64 (one block per CU), 66 KB in FP32 (two blocks per CU).  The second step's node needs
+// values, both steps' rho rings and the first step's parked rows: 513 bytes
+// (FP64) or 257 (FP32) per thread, so 131 KB for a 256-thread FP64 block (one
+// per CU) and 66 KB for a 128-thread FP64 or 256-thread FP32 block (two per
+// CU).  The second step's node needs
 // first-step populations at x +- 3 (its pull, then rho at x +- 2 for mu and
 // the gradients), hence the 6 columns the first step computes in addition.
 // Along y the first step runs 3 rows ahead of the second step's chunk on each
@@ -1394,25 +1396,27 @@ hipError_t launch_batch4(int storage, int scheme, int depth, const BatchTable* t
   return hipLaunchKernel(fn, dim3(tiles), dim3(kBatch4Block), args, 0, s);
 }
 
-hipError_t launch_batch2(int storage, int scheme, const BatchTable* tab, int tiles, int parity,
-                         hipStream_t s) {
-  if (tiles <= 0) return hipErrorInvalidValue;
-  const void* fn = nullptr;
-  constexpr int B = kStep2Block;
-  if (storage == FP64) {
-    fn = scheme == STANDARD       ? (const void*)march2_batch<double, STANDARD, B>
-         : scheme == STANDARD_EQF ? (const void*)march2_batch<double, STANDARD_EQF, B>
-         : scheme == WELL_BALANCED ? (const void*)march2_batch<double, WELL_BALANCED, B>
+namespace {
+template <typename T, int B>
+const void* batch2_kernel_t(int scheme) {
+  return scheme == STANDARD        ? (const void*)march2_batch<T, STANDARD, B>
+         : scheme == STANDARD_EQF  ? (const void*)march2_batch<T, STANDARD_EQF, B>
+         : scheme == WELL_BALANCED ? (const void*)march2_batch<T, WELL_BALANCED, B>
                                    : nullptr;
-  } else {
-    fn = scheme == STANDARD       ? (const void*)march2_batch<float, STANDARD, B>
-         : scheme == STANDARD_EQF ? (const void*)march2_batch<float, STANDARD_EQF, B>
-         : scheme == WELL_BALANCED ? (const void*)march2_batch<float, WELL_BALANCED, B>
-                                   : nullptr;
-  }
+}
+}  // namespace
+
+hipError_t launch_batch2(int storage, int scheme, int block, const BatchTable* tab, int tiles,
+                         int parity, hipStream_t s) {
+  if (tiles <= 0 || !step2_block_supported(block)) return hipErrorInvalidValue;
+  const void* fn = storage == FP64
+                       ? (block == 128 ? batch2_kernel_t<double, 128>(scheme)
+                                       : batch2_kernel_t<double, 256>(scheme))
+                       : (block == 128 ? batch2_kernel_t<float, 128>(scheme)
+                                       : batch2_kernel_t<float, 256>(scheme));
   if (!fn) return hipErrorInvalidValue;
   void* args[] = {(void*)&tab, (void*)&parity};
-  return hipLaunchKernel(fn, dim3(tiles), dim3(B), args, 0, s);
+  return hipLaunchKernel(fn, dim3(tiles), dim3(block), args, 0, s);
 }
 
 hipError_t launch_batch(int storage, int scheme, int block, int depth, bool observe,
@@ -1453,11 +1457,14 @@ hipError_t launch_step2_t(int scheme, const Geometry& g, const Physics& ph, int 
 }
 }  // namespace
 
-hipError_t launch_step2(int storage, int scheme, const Geometry& g, const Physics& ph, int rows,
-                        const void* fin, void* fout, hipStream_t s) {
-  if (rows < 1) return hipErrorInvalidValue;
-  return storage == FP32 ? launch_step2_t<float, kStep2Block>(scheme, g, ph, rows, fin, fout, s)
-                         : launch_step2_t<double, kStep2Block>(scheme, g, ph, rows, fin, fout, s);
+hipError_t launch_step2(int storage, int scheme, int block, const Geometry& g, const Physics& ph,
+                        int rows, const void* fin, void* fout, hipStream_t s) {
+  if (rows < 1 || !step2_block_supported(block)) return hipErrorInvalidValue;
+  if (storage == FP32)
+    return block == 128 ? launch_step2_t<float, 128>(scheme, g, ph, rows, fin, fout, s)
+                        : launch_step2_t<float, 256>(scheme, g, ph, rows, fin, fout, s);
+  return block == 128 ? launch_step2_t<double, 128>(scheme, g, ph, rows, fin, fout, s)
+                      : launch_step2_t<double, 256>(scheme, g, ph, rows, fin, fout, s);
 }
 
 hipError_t launch_observe(int storage, int scheme, const Geometry& g, const Physics& ph,

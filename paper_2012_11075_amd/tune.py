@@ -60,18 +60,20 @@ def two_step_tile(nx: int, ny: int, precision: str = "fp64", cus: int = 256, min
                   max_rows: int = 512):
     """(block, rows, 4) for two steps per launch on an nx x ny lattice, or
     None where one step per launch is the better choice.  The two-step
-    kernel (256-thread blocks) runs one block per compute unit in FP64 and
-    two in FP32-shifted storage (its LDS is half as large), so the tile
-    count should fill whole rounds of those blocks: strips of 250 columns
-    across x and, for the fewest rounds that keep chunks at most `max_rows`
-    tall and the rounds at least 90% full, the most chunks whose tiles fit
-    in them.  Chunks under `min_rows` rows (a lattice too small to fill the
-    device) would spend most of each block in the 12 lead-in rows: None.
-    For 4096^2 this gives the measured best tiles, (256, 274, 4) in FP64
-    and (256, 137, 4) in FP32-shifted storage."""
-    block = 256
+    kernel runs 128-thread blocks in FP64 and 256-thread blocks in
+    FP32-shifted storage (the faster of the two in each, measured at
+    4096^2); either takes 66 KB of LDS, so two blocks are resident per
+    compute unit, and the tile count should fill whole rounds of them:
+    strips of block - 6 columns across x and, for the fewest rounds that
+    keep chunks at most `max_rows` tall and the rounds at least 90% full,
+    the most chunks whose tiles fit in them.  Chunks under `min_rows` rows
+    (a lattice too small to fill the device) would spend most of each
+    block in the 12 lead-in rows: None.  For 4096^2 this gives the
+    measured best tiles, (128, 274, 4) in FP64 and (256, 137, 4) in
+    FP32-shifted storage."""
+    block = 256 if precision == "fp32s" else 128
     strips = -(-nx // (block - 6))
-    resident = cus * (2 if precision == "fp32s" else 1)
+    resident = 2 * cus
     c_min = -(-ny // max_rows)
     first = -(-strips * c_min // resident)
     rows = None
@@ -164,7 +166,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
                     depths=(1, 2, 3), two_step_rows=(32, 64, 128, 256), steps=20, passes=2):
     """Tile per size bucket on the whole batch; the candidates are the one-step
     tiles (blocks x rows x depths) and the two-step tiles (depth 4, block
-    256, chunks of `two_step_rows`).  First every lattice gets the
+    128 or 256, chunks of `two_step_rows`).  First every lattice gets the
     same candidate tile (one launch group) and the fastest is kept; then
     coordinate descent over the buckets: for each bucket in turn, time the
     full batch under every candidate for that bucket's lattices (the others
@@ -200,7 +202,7 @@ def tune_batch_full(problems, precision, blocks=(64, 128, 256), rows=(8, 16, 32,
         return e0.elapsed_time(e1) / steps
 
     cands = [(bw, r, d) for bw in blocks for r in rows for d in depths]
-    cands += [(256, r, 4) for r in two_step_rows]
+    cands += [(bw, r, 4) for bw in (128, 256) for r in two_step_rows]
     uniform = []
     for cand in cands:
         for s in slots:
@@ -273,8 +275,8 @@ def main():
         for prec in ("fp64", "fp32s"):
             block, base, _ = two_step_tile(prob.nx, prob.ny, prec)
             strips = -(-prob.nx // (block - 6))
-            # resident blocks: one per CU in FP64, two in FP32-shifted storage
-            per_round = max(1, (512 if prec == "fp32s" else 256) // strips)
+            # resident blocks: two per CU
+            per_round = max(1, 512 // strips)
             # chunk counts filling one round (and one less), two rounds, and
             # the one-step tile for comparison
             cands = sorted({-(-prob.ny // c) for c in (per_round, per_round - 1, 2 * per_round)})

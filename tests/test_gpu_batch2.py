@@ -13,7 +13,6 @@ from paper_2012_11075_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 SCHEMES = ["well_balanced", "standard", "standard_eq_forcing"]
-BLOCK = {"fp32s": 256, "fp64": 256}
 
 
 @pytest.fixture(scope="module")
@@ -42,8 +41,8 @@ def alone(L, prob, precision, scheme, steps):
 
 def cases():
     """(problem, precision, scheme, tile): uneven lattices from 1 node to
-    several strips wide, most on two-step tiles of several chunk heights,
-    every fourth on a one-step tile."""
+    several strips wide, most on two-step tiles of both block widths and
+    several chunk heights, every fourth on a one-step tile."""
     probs = I.batch_instances(64, seed=9, side_lo=8, side_hi=600)[:12]
     probs += [I.with_size(I.PAPER_DROPLET, nx, ny) for nx, ny in
               [(1, 7), (7, 1), (507, 12), (251, 40), (2, 2), (300, 251)]]
@@ -51,7 +50,8 @@ def cases():
     out = []
     for k, p in enumerate(probs):
         prec = "fp64" if k % 2 == 0 else "fp32s"
-        tile = (BLOCK[prec], rows[k % len(rows)], 4) if k % 4 != 3 else (128, 16, 2)
+        bw = 128 if k % 3 else 256
+        tile = (bw, rows[k % len(rows)], 4) if k % 4 != 3 else (128, 16, 2)
         out.append((p, prec, SCHEMES[k % 3], tile))
     return out
 
@@ -108,8 +108,8 @@ def test_batch_two_step_poll_observations(lbm):
 
 
 def test_batch_two_step_tile_rules_and_switch(lbm):
-    """Depth 4 needs a 2-D central-stencil slot and block 256; block 512 is
-    refused for batched tiles of any depth.  A slot switched
+    """Depth 4 needs a 2-D central-stencil slot and block 128 or 256; block
+    512 is refused for batched tiles of any depth.  A slot switched
     between two-step and one-step tiles between runs stays bit-identical
     to its run alone."""
     L = lbm
@@ -122,20 +122,24 @@ def test_batch_two_step_tile_rules_and_switch(lbm):
     ph = p.physics
     s4 = b.admit(L.make_params(64, 40, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
                                force_stencil=1), I.with_size(I.PAPER_DROPLET, 64, 40).rho())
-    for sl, bad in [(s64, (512, 16, 4)), (s64, (128, 16, 4)), (s32, (512, 16, 4)),
-                    (s32, (512, 16, 3)), (s32, (64, 16, 4)), (s4, (256, 16, 4))]:
+    for sl, bad in [(s64, (512, 16, 4)), (s64, (64, 16, 4)), (s32, (512, 16, 4)),
+                    (s32, (512, 16, 3)), (s32, (192, 16, 4)), (s4, (256, 16, 4)),
+                    (s4, (128, 16, 4))]:
         with pytest.raises(L.LbmError):
             b.set_tile(sl, *bad)
     b.release(s4)
     b.set_graph_steps(6)
-    b.set_tile(s64, 256, 24, 4)
+    b.set_tile(s64, 128, 24, 4)
     b.set_tile(s32, 256, 8, 4)
     b.run(17)
     b.set_tile(s64, 256, 16, 3)
     b.run(9)
     b.set_tile(s64, 256, 40, 4)
+    b.set_tile(s32, 128, 20, 4)
+    b.run(7)
+    b.set_tile(s64, 128, 40, 4)
     b.set_tile(s32, 128, 16, 2)
     b.run(12)
-    assert np.array_equal(b.get_populations(s64), alone(L, p, "fp64", "well_balanced", 38))
-    assert np.array_equal(b.get_populations(s32), alone(L, q, "fp32s", "standard", 38))
+    assert np.array_equal(b.get_populations(s64), alone(L, p, "fp64", "well_balanced", 45))
+    assert np.array_equal(b.get_populations(s32), alone(L, q, "fp32s", "standard", 45))
     b.close()

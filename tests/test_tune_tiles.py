@@ -1,7 +1,8 @@
 """Tile tables and the two-step tile helper (paper_2012_11075_amd/tune.py),
 on the CPU: the benchmark's 4096^2 tiles run two steps per launch and fill
-one round of blocks (one block per compute unit in FP64, two in
-FP32-shifted storage); the helper reproduces them, fills whole rounds of
+one round of blocks (two per compute unit: 128-thread blocks in FP64,
+256-thread blocks in FP32-shifted storage); the helper reproduces them,
+fills whole rounds of
 blocks on other sizes and leaves lattices too small for the device to one
 step per launch."""
 import math
@@ -15,11 +16,12 @@ def tiles_of(nx, ny, tile):
     return math.ceil(nx / (block - 6)) * math.ceil(ny / rows)
 
 
-RESIDENT = {"fp64": 256, "fp32s": 512}
+RESIDENT = {"fp64": 512, "fp32s": 512}
+BLOCK = {"fp64": 128, "fp32s": 256}
 
 
 def test_bench_tiles_two_steps_per_launch():
-    assert tune.bench_tile(4096, 4096, "fp64") == (256, 274, 4)
+    assert tune.bench_tile(4096, 4096, "fp64") == (128, 274, 4)
     assert tune.bench_tile(4096, 4096, "fp32s") == (256, 137, 4)
     for prec in ("fp64", "fp32s"):
         r = RESIDENT[prec]
@@ -35,7 +37,7 @@ def test_two_step_helper_rounds_and_limits():
     for n in (2048, 8192, 32768):
         for prec in ("fp64", "fp32s"):
             t = tune.two_step_tile(n, n, prec)
-            assert t is not None and t[0] == 256
+            assert t is not None and t[0] == BLOCK[prec]
             assert 16 <= t[1] <= 512
             k = tiles_of(n, n, t)
             r = RESIDENT[prec]
@@ -44,4 +46,4 @@ def test_two_step_helper_rounds_and_limits():
             assert k > (rounds - 1) * r + r // 2 or rounds == 1, (n, prec, t, k)
     assert tune.two_step_tile(512, 512, "fp64") is None
     assert tune.two_step_tile(1024, 1024, "fp32s") is None
-    assert tune.two_step_tile(1024, 1024, "fp64") == (256, 21, 4)
+    assert tune.two_step_tile(1024, 1024, "fp64") == (128, 19, 4)
