@@ -110,11 +110,10 @@ def stencil4_tile(nx: int, ny: int, precision: str = "fp64"):
 def serve_tile(nx: int, ny: int, precision: str = "fp64"):
     """(block, rows, depth) for a lattice of the served stream, or None.  A
     served batch holds a few tens of lattices at a time, not hundreds, so
-    short chunks (more tiles per step) keep the device full: FP64 runs
-    one-step tiles of 16 rows (with the batch's 32-row chunks the served
-    stream measured 6% less aggregate throughput and a 20% higher p50
-    latency), FP32 two-step tiles of 32 rows (two blocks per CU; 27% lower
-    p50 latency than its one-step tiles of 16 rows).  The table covers
+    short chunks (more tiles per step) keep the device full: two-step
+    tiles of 32 rows, 256-thread blocks in FP32 and 128-thread blocks in
+    FP64 (two blocks per CU; p50 latency 3.98 s against 6.49 s for one-step
+    tiles of 16 rows, at the same aggregate throughput).  The table covers
     every request size, so all requests of one precision share one launch
     group."""
     t = _table().get("serve/%s/%s" % (_bucket(nx, ny), precision))
