@@ -327,9 +327,10 @@ def time_stencil4(prob, steps, warmup, scheme="standard", tile=None, precision="
 
 def time_largest(steps, warmup, n=32768):
     """The FP64 WB step on the largest square lattice HBM holds in FP64
-    (32768^2, a 189 GB workspace), with the headline's tile, on a separable
-    density (Sec. IV constants, density ratio 5): the rate at 64x the
-    headline's node count."""
+    (32768^2, a 189 GB workspace), with the two-step tile that
+    tune.two_step_tile picks for its size, on a separable density (Sec. IV
+    constants, density ratio 5): the rate at 64x the headline's node
+    count."""
     import ctypes
     import gc
     import torch
@@ -346,7 +347,7 @@ def time_largest(steps, warmup, n=32768):
                            % (need / 1e9, free / 1e9)}
     rho = I.separable_density(n, n, 17)
     s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0)
-    s.set_tile(*tune.bench_tile(4096, 4096, "fp64"))
+    s.set_tile(*(tune.two_step_tile(n, n, "fp64") or tune.bench_tile(4096, 4096, "fp64")))
     s.init(rho, scheme="well_balanced")
     del rho
     s.step(warmup, "well_balanced")
