@@ -68,7 +68,9 @@ def main():
         n, ph = args.side, I.PAPER_PHYS
         s = lbm.Solver(n, n, ph.tau, ph.beta, ph.kappa, ph.rho_l, ph.rho_v, ph.rho0,
                        precision=args.precision)
-        s.set_tile(*tune.bench_tile(4096, 4096, args.precision))
+        # the benchmark's tile for this size (bench.py, largest lattice)
+        s.set_tile(*(tune.two_step_tile(n, n, args.precision)
+                     or tune.bench_tile(4096, 4096, args.precision)))
         s.init(I.separable_density(n, n, 17), scheme=args.scheme)
         print("profile_step: %d^2 separable density %s %s tile=%s" % (n, args.precision, args.scheme,
                                                                       s.get_tile()), flush=True)
